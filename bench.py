@@ -1,0 +1,163 @@
+"""Benchmark of the column merge on one MI355X.
+
+Default workload: the 100M-row u64 column whose dictionary grows from
+1,048,000 to 1,948,000 entries (code width 20 -> 21 bits), with a 1M-row
+delta (90% new values).  One step = one whole merge of that column: delta
+sort and dictionary (Step 1(a)), dictionary merge (Step 1(b)), width
+(Step 2(a)) and re-encode + delta append (Step 2(b)), inputs resident in
+HBM.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(col, n_new, w_new, n_ud):
+    """Compulsory bytes of one merge: inputs read once, outputs written once
+    (main codes, U_M, delta values in; U' and the new codes out)."""
+    E = col.value_len
+    n_out = col.n_main + col.n_delta
+    b_in = col.n_main * col.w / 8 + col.u_m.shape[0] * E + col.n_delta * E
+    b_out = n_new * E + n_out * w_new / 8
+    return b_in + b_out
+
+
+def reencode_bytes(col, n_new, w_new, n_ud):
+    """Algorithmic bytes of the re-encode kernel (Step 2(b)): the packed main
+    codes in, the packed result out, the delta rows' dictionary indices in,
+    and each translation-table entry read once."""
+    n_out = col.n_main + col.n_delta
+    return (col.n_main * col.w / 8 + n_out * w_new / 8 + 4 * col.n_delta
+            + 4 * col.u_m.shape[0] + 4 * n_ud)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(columns are independent: a multi-GPU run would shard columns or row ranges, "
+              "which is not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1109_6885_amd as cm
+    from workloads import gen
+
+    if not os.path.exists(cm._lib.LIB_PATH):
+        from paper_1109_6885_amd import build as hipbuild
+        hipbuild.build()
+
+    torch.cuda.set_device(0)
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
+
+    t = time.time()
+    col = gen.config_column(2)
+    log(f"generated c2 in {time.time() - t:.1f}s")
+    dcol = cm.ColumnInput.from_numpy(col)
+    out = cm.alloc_output(dcol, tables=False)
+    _, _, sbytes = cm.merge_bounds(dcol)
+    scratch = cm.alloc_scratch(sbytes)
+    ctx = cm.context()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+    torch.cuda.synchronize()
+    sc = out.scalars()
+    assert sc["error"] == 0, sc
+    log(f"|U'|={sc['n_new']} w'={sc['w_new']} words={sc['words']}")
+
+    # timed region: K whole merges, wall clock around them
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+
+    # the same K merges again with HIP events around every step on the
+    # launch stream: per-step averages
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+    steps_ms = ctx.step_times()
+    ctx.set_timing(False)
+    torch.cuda.synchronize()
+
+    n_out = col.n_main + col.n_delta
+    value = n_out / (ms_per_step / 1000.0)
+    b_alg = algorithmic_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
+    b_re = reencode_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
+    re_ms = steps_ms[3]
+    achieved = b_re / (re_ms / 1000.0) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        t = time.perf_counter()
+        ref = oracle.merge_column("u64", col.u_m, col.main_packed, col.n_main, col.w, col.delta)
+        dt = time.perf_counter() - t
+        assert ref["n_new"] == sc["n_new"]
+        cpu = {"value": n_out / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole 101M-tuple column, one serial run of the C oracle "
+                         f"({dt:.1f} s)"}
+
+    line = {
+        "metric": "merged tuples/s and achieved HBM GB/s (% of peak); batched vs per-column plain",
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded numpy PCG64)",
+        "config": {"workload": "single u64 column: 100M main rows at 20 bits, 1,048,000-entry "
+                               "dictionary, 1M delta rows (90% new) -> 1,948,000 entries at 21 bits",
+                   "main_rows": col.n_main, "delta_rows": col.n_delta,
+                   "dict": int(col.u_m.shape[0]), "w": col.w, "w_new": sc["w_new"],
+                   "new_dict": sc["n_new"]},
+        "hbm_gbs_alg": b_alg / (ms_per_step / 1000.0) / 1e9,
+        "hbm_frac_alg": b_alg / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS,
+        "bytes_alg": b_alg,
+        "step_ms": {"clear+sort": steps_ms[0], "emit": steps_ms[1], "merge_dict": steps_ms[2],
+                    "reencode": steps_ms[3], "whole": steps_ms[4]},
+        "roofline": {"kernel": "k_repack (Step 2(b))", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": b_re},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * colmerge.h -- C ABI of the MI355X (gfx950) column-merge library.
+ *
+ * The operation is the online merge of one dictionary-encoded column of a
+ * read-optimized column store (Krueger et al., "Fast Updates on
+ * Read-Optimized Databases Using Multi-Core CPUs", arXiv 1109.6885):
+ *
+ *   inputs   U_M  sorted unique main dictionary            (Section 3)
+ *            M    main codes, bit-packed at width E_C = w  (Section 4.1)
+ *            D    delta values in append order             (Section 3)
+ *   outputs  U'   sorted unique merged dictionary          (Eq. 3)
+ *            M'   N_M + N_D codes at width E_C' = w'       (Eqs. 2, 4)
+ *            X_M, X_D translation tables (old -> new code) (Section 5.3)
+ *
+ * Step 1(a) builds the delta dictionary U_D and the index of every delta
+ * row in it, Step 1(b) merges U_M and U_D into U' while emitting X_M and
+ * X_D, Step 2(a) computes w' (Eq. 4) and Step 2(b) rewrites every main code
+ * through X_M and appends the delta codes through X_D (Eq. 11).
+ *
+ * Conventions (the paper leaves them open):
+ *  - Value types: MC_U32 (4 bytes) and MC_U64 (8 bytes) are unsigned
+ *    little-endian integers in numeric order; MC_STR16 is 16 raw bytes
+ *    ordered as unsigned bytes, first byte most significant (memcmp).
+ *  - Packed codes: code i occupies stream bits [i*w, (i+1)*w), least
+ *    significant bit first; stream bit b is bit (b % 64) of 64-bit word
+ *    b / 64.  Result bits beyond N'*w' in the last word are zero.
+ *  - width(n) = ceil(log2 n) for n >= 2, and 1 for n <= 1.
+ *  - Every U_M entry is kept (Eq. 3 unions with U_M) and every row is kept
+ *    (insert-only updates, Eq. 2).
+ *
+ * Memory: every data pointer in mc_column_in / mc_column_out and every
+ * scratch pointer is a DEVICE pointer owned by the caller.  Value arrays,
+ * code arrays and scratch must be 16-byte aligned.  Main code buffers are
+ * read only up to word ceil(N_M * w / 64); result code buffers are written
+ * up to the capacity returned by mc_merge_bounds (words past W' may be
+ * overwritten with zeros).  The library never allocates or frees caller
+ * memory and never synchronizes the caller's stream: every mc_merge_* call
+ * only enqueues work on `stream` and returns; results are valid once the
+ * stream reaches that point.
+ *
+ * Errors: every call returns MC_OK (0) or a negative mc_status.  A failed
+ * call enqueues nothing and leaves the inputs untouched.  Data errors that
+ * only the device can see (a main code >= |U_M|, a delta index out of range)
+ * are reported in mc_result.error after the stream completes; the outputs
+ * are then unspecified but every access stays inside the buffers.
+ * mc_last_error() returns a message for the calling thread's last failure.
+ *
+ * Threading: an mc_ctx is used from one host thread at a time.  Different
+ * contexts, or one context on different streams with different scratch
+ * buffers, may run concurrently.
+ */
+#ifndef COLMERGE_H
+#define COLMERGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t; /* hipStream_t is `struct ihipStream_t *` */
+
+typedef struct mc_ctx mc_ctx;
+typedef struct mc_graph mc_graph;
+
+typedef enum mc_type { MC_U32 = 0, MC_U64 = 1, MC_STR16 = 2 } mc_type;
+
+typedef enum mc_status {
+    MC_OK = 0,
+    MC_E_ARG = -1,   /* null pointer, size or width out of range, misaligned */
+    MC_E_CAP = -2,   /* an output or scratch capacity is below the bounds    */
+    MC_E_NOMEM = -3, /* host-side allocation failed                           */
+    MC_E_HIP = -4,   /* a HIP runtime call failed (see mc_last_error)         */
+    MC_E_DATA = -5   /* invalid data reported by the device                   */
+} mc_status;
+
+/* Bits of mc_result.error. */
+#define MC_DEVERR_CODE_RANGE 1u  /* a main code >= |U_M| was read            */
+#define MC_DEVERR_DELTA_RANGE 2u /* a delta index >= |U_D| (internal)        */
+#define MC_DEVERR_SPIN 4u        /* a cross-workgroup wait hit its bound     */
+
+/* Result scalars, written by the device (caller-allocated device memory). */
+typedef struct mc_result {
+    uint64_t new_dict_len;    /* |U'|                                        */
+    uint64_t new_codes_words; /* W' = ceil((N_M + N_D) * w' / 64)            */
+    uint64_t delta_dict_len;  /* |U_D|                                       */
+    uint32_t new_bitwidth;    /* w' (Eq. 4)                                  */
+    uint32_t error;           /* MC_DEVERR_* bits, 0 if none                 */
+} mc_result;
+
+/* One column's inputs (device pointers). */
+typedef struct mc_column_in {
+    int32_t type;              /* mc_type                                    */
+    uint32_t bitwidth;         /* w, 1..32, with |U_M| <= 2^w                */
+    const void *main_dict;     /* U_M: main_dict_len values, strictly increasing */
+    uint64_t main_dict_len;    /* |U_M|; 0 only if main_rows == 0            */
+    const uint64_t *main_codes;/* packed main codes, ceil(main_rows*w/64) words */
+    uint64_t main_rows;        /* N_M                                        */
+    const void *delta_values;  /* D: delta_rows values in append order       */
+    uint64_t delta_rows;       /* N_D, < 2^30                                */
+} mc_column_in;
+
+/* One column's outputs (device pointers, caller-allocated). */
+typedef struct mc_column_out {
+    void *new_dict;               /* U': capacity new_dict_cap values        */
+    uint64_t new_dict_cap;        /* >= dict_cap of mc_merge_bounds          */
+    uint64_t *new_codes;          /* M': capacity new_codes_cap_words words  */
+    uint64_t new_codes_cap_words; /* >= codes_words of mc_merge_bounds       */
+    uint32_t *x_main;             /* X_M (|U_M| entries) or NULL             */
+    uint32_t *x_delta;            /* X_D (delta_rows entries) or NULL        */
+    mc_result *result;            /* device scalars, required                */
+} mc_column_out;
+
+/* ---- contexts -------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device`. */
+int mc_ctx_create(int device, mc_ctx **out);
+void mc_ctx_destroy(mc_ctx *ctx);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *mc_last_error(void);
+
+/* ---- sizing (host only, no device access) ---------------------------- */
+
+/* Worst-case sizes for one column, from the input sizes alone:
+ *   dict_cap      = |U_M| + N_D values for U'
+ *   codes_words   = ceil((N_M + N_D) * width(|U_M| + N_D) / 64) rounded up
+ *                   to a multiple of 2 (room for 128-bit stores)
+ *   scratch_bytes = device workspace for mc_merge_column.
+ * These bounds need no device read, so they serve admission control and
+ * graph capture (outputs sized before the real |U'| is known). */
+int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap,
+                    uint64_t *codes_words, uint64_t *scratch_bytes);
+
+/* ---- the merge of one column (Section 5, Steps 1(a) to 2(b)) --------- */
+
+/* Enqueue the whole merge of one column on `stream`.  `scratch` is a
+ * device workspace of at least scratch_bytes (mc_merge_bounds); its
+ * contents need not be initialized.  X_M / X_D are written only if the
+ * out pointers are non-NULL. */
+int mc_merge_column(mc_ctx *ctx, const mc_column_in *in,
+                    const mc_column_out *out, void *scratch,
+                    uint64_t scratch_bytes, struct ihipStream_t *stream);
+
+/* ---- single steps (the same kernels as mc_merge_column) --------------- */
+
+/* Step 1(a), modified form (Sections 5.1 and 5.3): sorted unique delta
+ * dictionary u_d (delta_rows capacity, same value type) and each delta
+ * row's index in it (drank, delta_rows entries).  *d_count (device u64)
+ * receives |U_D|.  Scratch: mc_delta_dictionary_scratch bytes. */
+int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values,
+                        uint64_t delta_rows, void *u_d, uint32_t *drank,
+                        uint64_t *d_count, void *scratch,
+                        uint64_t scratch_bytes, struct ihipStream_t *stream);
+int mc_delta_dictionary_scratch(int32_t type, uint64_t delta_rows,
+                                uint64_t *scratch_bytes);
+
+/* Step 1(b) and Step 2(a) (Sections 5.1, 5.3, 6.2.1; Eq. 4): merge the
+ * sorted unique dictionaries u_m (n_um values) and u_d (*d_n_ud values,
+ * read on the device, at most n_ud_max) into u_new with tables x_m and x_d.
+ * Writes result->new_dict_len, ->new_bitwidth and ->new_codes_words for a
+ * merged column of `rows_total` rows.  Scratch: mc_merge_dictionaries_scratch. */
+int mc_merge_dictionaries(mc_ctx *ctx, int32_t type, const void *u_m,
+                          uint64_t n_um, const void *u_d,
+                          const uint64_t *d_n_ud, uint64_t n_ud_max,
+                          void *u_new, uint32_t *x_m, uint32_t *x_d,
+                          uint64_t rows_total, mc_result *result,
+                          void *scratch, uint64_t scratch_bytes,
+                          struct ihipStream_t *stream);
+int mc_merge_dictionaries_scratch(uint64_t n_um, uint64_t n_ud_max,
+                                  uint64_t *scratch_bytes);
+
+/* Step 2(b), modified form (Eq. 11; Section 6.2.2): out[i] = x_m[main[i]]
+ * for i < n_main, out[n_main + j] = x_d[drank[j]] for j < n_delta, packed
+ * at width result->new_bitwidth (read on the device).  x_m has n_um
+ * entries, x_d has result->delta_dict_len entries.  Writes
+ * ceil((n_main + n_delta) * w' / 64) words (rounded up to even, zero
+ * padded) into out (capacity out_cap_words). */
+int mc_reencode(mc_ctx *ctx, const uint64_t *main_codes, uint64_t n_main,
+                uint32_t w, const uint32_t *x_m, uint64_t n_um,
+                const uint32_t *drank, uint64_t n_delta, const uint32_t *x_d,
+                mc_result *result, uint64_t *out, uint64_t out_cap_words,
+                struct ihipStream_t *stream);
+
+/* ---- many columns at once (Section 6.2.1, scheme (i)) ----------------- */
+
+/* Worst-case scratch for merging ncols columns in one batched call. */
+int mc_merge_batched_bounds(const mc_column_in *ins, uint32_t ncols,
+                            uint64_t *scratch_bytes);
+
+/* Enqueue the merge of ncols independent columns (uneven sizes and value
+ * types) as one batched launch sequence: every kernel covers the tiles of
+ * all columns, so the launch count does not grow with ncols.  If `graph`
+ * is non-NULL the sequence is captured once into a HIP graph (returned in
+ * *graph, reusable with mc_graph_launch for the same buffers) and launched;
+ * otherwise it is enqueued directly.  ins/outs are host arrays of ncols
+ * descriptors whose pointers are device pointers. */
+int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins,
+                             const mc_column_out *outs, uint32_t ncols,
+                             void *scratch, uint64_t scratch_bytes,
+                             struct ihipStream_t *stream, mc_graph **graph);
+int mc_graph_launch(mc_graph *graph, struct ihipStream_t *stream);
+void mc_graph_destroy(mc_graph *graph);
+
+/* ---- step timing (for measurement) ------------------------------------ */
+
+/* Enabling (or re-enabling) timing starts a new measurement: from then on
+ * every mc_merge_column call records HIP events around each step on its
+ * own stream.  mc_ctx_step_times waits for the last recorded merge and
+ * returns the AVERAGE milliseconds over the recorded merges for:
+ * [0] workspace clear + delta sort, [1] delta dictionary emit,
+ * [2] dictionary merge and width, [3] re-encode, [4] whole call. */
+int mc_ctx_set_timing(mc_ctx *ctx, int enable);
+int mc_ctx_step_times(mc_ctx *ctx, float *ms5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLMERGE_H */

@@ -1,0 +1,207 @@
+// common.hpp -- value traits, wave/block scans and the cross-workgroup
+// prefix protocol shared by the column-merge kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "colmerge.h"
+
+namespace mc {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 waves of 64)
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------------------
+// Value traits.  Stored values are always the caller's raw bytes.  For
+// ordering, a value is mapped to a "normalized" key whose unsigned
+// comparison is the column order: identity for integers, the two 8-byte
+// halves byte-swapped (big-endian) for 16-byte strings.
+// ---------------------------------------------------------------------------
+
+struct alignas(16) Raw16 {
+    uint64_t a, b;  // bytes 0..7 and 8..15, little-endian loads
+};
+struct Norm16 {
+    uint64_t hi, lo;  // most / least significant 8 bytes in byte order
+};
+
+struct TU32 {
+    typedef uint32_t K;
+    typedef uint32_t N;
+    static constexpr int kBytes = 4;
+    __device__ static K load(const void *p, uint64_t i) { return static_cast<const K *>(p)[i]; }
+    __device__ static void store(void *p, uint64_t i, K k) { static_cast<K *>(p)[i] = k; }
+    // radix digit `d` (0 = least significant byte of the order)
+    __device__ static uint32_t digit(K k, int d) { return (k >> (8 * d)) & 0xffu; }
+    __device__ static N norm(K k) { return k; }
+    __device__ static K denorm(N n) { return n; }
+    __device__ static bool lt(N a, N b) { return a < b; }
+    __device__ static bool le(N a, N b) { return a <= b; }
+    __device__ static bool eq(N a, N b) { return a == b; }
+    __device__ static bool keq(K a, K b) { return a == b; }
+};
+
+struct TU64 {
+    typedef uint64_t K;
+    typedef uint64_t N;
+    static constexpr int kBytes = 8;
+    __device__ static K load(const void *p, uint64_t i) { return static_cast<const K *>(p)[i]; }
+    __device__ static void store(void *p, uint64_t i, K k) { static_cast<K *>(p)[i] = k; }
+    __device__ static uint32_t digit(K k, int d) { return (uint32_t)(k >> (8 * d)) & 0xffu; }
+    __device__ static N norm(K k) { return k; }
+    __device__ static K denorm(N n) { return n; }
+    __device__ static bool lt(N a, N b) { return a < b; }
+    __device__ static bool le(N a, N b) { return a <= b; }
+    __device__ static bool eq(N a, N b) { return a == b; }
+    __device__ static bool keq(K a, K b) { return a == b; }
+};
+
+struct TS16 {
+    typedef Raw16 K;
+    typedef Norm16 N;
+    static constexpr int kBytes = 16;
+    __device__ static K load(const void *p, uint64_t i) { return static_cast<const K *>(p)[i]; }
+    __device__ static void store(void *p, uint64_t i, K k) { static_cast<K *>(p)[i] = k; }
+    // digit d is byte 15 - d of the string (byte 15 is least significant)
+    __device__ static uint32_t digit(K k, int d) {
+        int byte = 15 - d;
+        uint64_t w = byte >= 8 ? k.b : k.a;
+        return (uint32_t)(w >> (8 * (byte & 7))) & 0xffu;
+    }
+    __device__ static N norm(K k) {
+        N n;
+        n.hi = __builtin_bswap64(k.a);
+        n.lo = __builtin_bswap64(k.b);
+        return n;
+    }
+    __device__ static K denorm(N n) {
+        K k;
+        k.a = __builtin_bswap64(n.hi);
+        k.b = __builtin_bswap64(n.lo);
+        return k;
+    }
+    __device__ static bool lt(N x, N y) { return x.hi < y.hi || (x.hi == y.hi && x.lo < y.lo); }
+    __device__ static bool le(N x, N y) { return x.hi < y.hi || (x.hi == y.hi && x.lo <= y.lo); }
+    __device__ static bool eq(N x, N y) { return x.hi == y.hi && x.lo == y.lo; }
+    __device__ static bool keq(K x, K y) { return x.a == y.a && x.b == y.b; }
+};
+
+// ---------------------------------------------------------------------------
+// Wave and block scans (wave64, 256-thread blocks).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive scan over the block; s_tmp must hold kWaves values.  Returns the
+// exclusive prefix of v and stores the block total in *total.  Contains two
+// barriers; every thread of the block must call it.
+template <class T>
+__device__ __forceinline__ T block_excl_scan(T v, T *s_tmp, T *total) {
+    T inc = wave_incl_scan(v);
+    if (lane_id() == 63) s_tmp[wave_id()] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) {
+        T x = s_tmp[i];
+        if (i < wave_id()) off += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup prefix ("decoupled look-back").  Tiles take their index
+// from an atomic counter in launch order, publish their own aggregate, then
+// add the aggregates of earlier tiles until one of them has published an
+// inclusive prefix.  A tile only ever waits for tiles that took their index
+// earlier, which are resident and never wait for later tiles, so the wait
+// ends; it is additionally bounded, and on overrun the error word is set
+// and the wave moves on, so every wave exits.
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPre = 2ull << 62;
+constexpr uint64_t kValMask = kFlagAgg - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t ld_acq(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void flag_error(uint32_t *err, uint32_t bit) {
+    if (err) atomicOr(err, bit);
+}
+
+// Called by wave 0 of the block only.  Returns the exclusive prefix of tile
+// `tile` (sum of the aggregates of tiles 0 .. tile-1).
+__device__ inline uint64_t lookback_wave(uint64_t *status, uint32_t tile, uint64_t agg,
+                                         uint32_t *err) {
+    const int lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0) st_rel(&status[0], kFlagPre | agg);
+        return 0;
+    }
+    if (lane == 0) st_rel(&status[tile], kFlagAgg | agg);
+    uint64_t prefix = 0;
+    int64_t base = (int64_t)tile - 1;
+    while (true) {
+        int64_t t = base - lane;  // lane 0 looks at the nearest predecessor
+        uint64_t s = kFlagPre;    // lanes before tile 0 act as a zero prefix
+        if (t >= 0) {
+            uint32_t spins = 0;
+            s = ld_acq(&status[t]);
+            while ((s >> 62) == 0) {
+                if (++spins > kSpinLimit) {
+                    flag_error(err, MC_DEVERR_SPIN);
+                    s = kFlagPre;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                s = ld_acq(&status[t]);
+            }
+        }
+        uint64_t pre = __ballot((s & kFlagPre) != 0);
+        int stop = pre ? (__ffsll((long long)pre) - 1) : 64;
+        uint64_t v = lane <= stop ? (s & kValMask) : 0;
+        prefix += wave_sum(v);
+        if (pre) break;
+        base -= 64;
+    }
+    if (lane == 0) st_rel(&status[tile], kFlagPre | (prefix + agg));
+    return prefix;
+}
+
+// Code width for a dictionary of n entries: ceil(log2 n), at least 1.
+__device__ __host__ inline uint32_t code_width(uint64_t n) {
+    uint32_t w = 1;
+    while (w < 64 && (1ull << w) < n) w++;
+    return w;
+}
+
+}  // namespace mc

@@ -1,0 +1,129 @@
+// repack.hpp -- Step 2(b) on the GPU (modified Step 2(b) of Section 5.3,
+// Eq. 11, parallelized by row ranges as in Section 6.2.2): every main code
+// is unpacked at the old width w, translated through X_M and repacked at
+// the new width w'; the delta rows follow, translated through X_D.
+//
+// A workgroup owns 4096 consecutive output rows.  Because 64 codes of width
+// w fill exactly w 64-bit words, a tile of 4096 rows starts on a word
+// boundary both in the input (64*w words) and in the output (64*w' words),
+// so tiles never share a word and need no atomics.  The tile's input words
+// are staged in LDS with 128-bit loads, each thread decodes 16 codes and
+// gathers their new codes from X_M (X_D for delta rows) into an LDS code
+// array, and then each thread assembles whole output words from the codes
+// that overlap them and writes them with coalesced 128-bit stores.
+#pragma once
+
+#include "common.hpp"
+
+namespace mc {
+
+struct RepackJob {
+    const uint64_t *main_codes;
+    uint64_t n_main;
+    uint32_t w;
+    const uint32_t *x_m;
+    uint64_t n_um;
+    const uint32_t *drank;
+    uint64_t n_delta;
+    const uint32_t *x_d;
+    const mc_result *result;  // w' and |U_D| (device scalars)
+    uint64_t *out;
+    uint64_t out_cap_words;
+    uint32_t *err;
+};
+
+constexpr int kRepackCodes = 4096;               // rows per tile (64 groups of 64)
+constexpr int kRepackPer = kRepackCodes / kBlock;  // codes per thread
+
+__global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
+    __shared__ __attribute__((aligned(16))) uint64_t s_in[64 * 32 + 2];
+    __shared__ uint32_t s_code[kRepackCodes];
+
+    const uint32_t w = J.w;
+    const uint32_t wn = J.result->new_bitwidth;
+    const uint64_t n_ud = J.result->delta_dict_len;
+    const uint64_t n_out = J.n_main + J.n_delta;
+    const uint64_t t = blockIdx.x;
+    const uint64_t c0 = t * kRepackCodes;
+    if (c0 >= n_out) return;
+    const uint32_t tn = (uint32_t)min<uint64_t>(kRepackCodes, n_out - c0);
+
+    // stage the main words of this tile
+    if (c0 < J.n_main) {
+        const uint64_t win = (J.n_main * w + 63) / 64;  // readable input words
+        const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 64
+        const uint32_t nw = (uint32_t)min<uint64_t>(64ull * w, win - wbase);
+        const uint32_t npair = nw / 2;
+        const ulonglong2 *src2 = reinterpret_cast<const ulonglong2 *>(J.main_codes + wbase);
+        ulonglong2 *dst2 = reinterpret_cast<ulonglong2 *>(s_in);
+        for (uint32_t x = threadIdx.x; x < npair; x += kBlock) dst2[x] = src2[x];
+        if ((nw & 1u) && threadIdx.x == 0) s_in[nw - 1] = J.main_codes[wbase + nw - 1];
+    }
+    __syncthreads();
+
+    // decode + translate
+    const uint64_t mask = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
+    uint32_t bad = 0;
+#pragma unroll 4
+    for (int j = 0; j < kRepackPer; j++) {
+        const uint32_t i = j * kBlock + threadIdx.x;
+        const uint64_t g = c0 + i;
+        uint32_t nc = 0;
+        if (i < tn) {
+            if (g < J.n_main) {
+                const uint32_t bit = i * w;
+                const uint32_t wi = bit >> 6, sh = bit & 63u;
+                uint64_t v = s_in[wi] >> sh;
+                if (sh + w > 64) v |= s_in[wi + 1] << (64 - sh);
+                const uint32_t c = (uint32_t)(v & mask);
+                if (c < J.n_um)
+                    nc = J.x_m[c];
+                else
+                    bad |= MC_DEVERR_CODE_RANGE;
+            } else {
+                const uint32_t r = J.drank[g - J.n_main];
+                if (r < n_ud)
+                    nc = J.x_d[r];
+                else
+                    bad |= MC_DEVERR_DELTA_RANGE;
+            }
+        }
+        s_code[i] = nc;
+    }
+    if (bad) flag_error(J.err, bad);
+    __syncthreads();
+
+    // assemble output words: local word k covers tile bits [64k, 64k + 64)
+    const uint64_t obase = t * 64ull * wn;
+    const uint64_t wres = (n_out * wn + 63) / 64;
+    const uint64_t wlim = min<uint64_t>(J.out_cap_words, (wres + 1) & ~1ull);
+    const uint32_t nwo = 64u * wn;  // words of a full tile (even)
+    for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
+        uint64_t word[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint32_t k = 2 * k2 + h;
+            const uint32_t b0 = 64u * k;
+            uint32_t q = b0 / wn;
+            const uint32_t qe = min<uint32_t>((b0 + 63) / wn, kRepackCodes - 1);
+            uint64_t acc = 0;
+            for (; q <= qe; q++) {
+                const uint64_t c = s_code[q];
+                const int sh = (int)(q * wn) - (int)b0;
+                acc |= sh < 0 ? (c >> (-sh)) : (c << sh);
+            }
+            word[h] = acc;
+        }
+        const uint64_t gw = obase + 2ull * k2;
+        if (gw + 1 < wlim) {
+            ulonglong2 v;
+            v.x = word[0];
+            v.y = word[1];
+            *reinterpret_cast<ulonglong2 *>(J.out + gw) = v;
+        } else if (gw < wlim) {
+            J.out[gw] = word[0];
+        }
+    }
+}
+
+}  // namespace mc

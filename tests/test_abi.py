@@ -1,0 +1,101 @@
+"""The C-ABI library loads on a machine without a GPU, exports every symbol
+include/colmerge.h declares, and its host-only sizing call computes the
+documented bounds and rejects invalid arguments (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1109_6885_amd as cm
+from paper_1109_6885_amd import _lib, build as hipbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        hipbuild.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "colmerge.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_exports(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    assert sorted(_lib.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_exports_are_c_symbols(lib):
+    # extern "C": the names are not mangled
+    out = os.popen(f"nm -D --defined-only {_lib.LIB_PATH}").read()
+    for n in declared_functions():
+        assert re.search(rf"\bT {n}$", out, flags=re.M), n
+
+
+def test_struct_sizes_match_header(lib):
+    assert ctypes.sizeof(_lib.McResult) == 32
+    assert ctypes.sizeof(_lib.McColumnIn) == 56
+    assert ctypes.sizeof(_lib.McColumnOut) == 56
+
+
+def _in(type_=1, w=20, n_um=1_048_000, n_main=100_000_000, nd=1_000_000, ptr=256):
+    d = _lib.McColumnIn()
+    d.type, d.bitwidth = type_, w
+    d.main_dict, d.main_dict_len = ptr, n_um
+    d.main_codes, d.main_rows = ptr, n_main
+    d.delta_values, d.delta_rows = ptr, nd
+    return d
+
+
+def _bounds(lib, d):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib.mc_merge_bounds(ctypes.byref(d), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return rc, a.value, b.value, c.value
+
+
+def test_bounds_formula(lib):
+    rc, dc, words, sb = _bounds(lib, _in())
+    assert rc == 0
+    assert dc == 1_048_000 + 1_000_000
+    wmax = (dc - 1).bit_length()                      # 21
+    raw = (101_000_000 * wmax + 63) // 64
+    assert words == raw + (raw & 1)
+    # scratch holds at least the two ping-pong sort buffers and the tables
+    assert sb >= 2 * 1_000_000 * 12 + 4 * 1_048_000
+    rc, dc, words, sb = _bounds(lib, _in(type_=2, w=24, n_um=10_000_000, nd=10_000_000))
+    assert rc == 0 and dc == 20_000_000
+    assert words == (((110_000_000 * 25 + 63) // 64) + 1) // 2 * 2
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(w=0), -1), (dict(w=33), -1), (dict(type_=7), -1),
+    (dict(n_um=2 ** 20 + 1, w=20), -1),          # |U_M| > 2^w
+    (dict(nd=2 ** 30), -1),                       # delta too long
+    (dict(n_um=0), -1),                           # rows without a dictionary
+    (dict(ptr=8), -1),                            # misaligned
+])
+def test_bounds_rejects(lib, kw, code):
+    rc, *_ = _bounds(lib, _in(**kw))
+    assert rc == code
+    assert lib.mc_last_error()
+
+
+def test_bounds_empty_column(lib):
+    rc, dc, words, sb = _bounds(lib, _in(n_um=0, n_main=0, nd=0))
+    assert rc == 0 and dc == 0 and words == 0 and sb > 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.load()

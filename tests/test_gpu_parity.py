@@ -1,0 +1,251 @@
+"""GPU parity: the HIP library against the CPU oracle, byte for byte.
+
+Every case prints its name, seed and shape before it touches the GPU.
+Integer work: the tolerance is zero everywhere (U', w', |U'|, the W'
+result words, X_M, X_D, U_D and the delta indices)."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1109_6885_amd as cm
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_merge(col, tables=True):
+    out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=tables)
+    torch.cuda.synchronize()
+    return out.fetch()
+
+
+def ora_merge(col):
+    return oracle.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w, col.delta)
+
+
+def assert_same(got, ref):
+    assert got["error"] == 0, f"device error word {got['error']}"
+    assert got["n_new"] == ref["n_new"]
+    assert got["w_new"] == ref["w_new"]
+    assert got["words"] == ref["n_words"]
+    assert np.array_equal(got["u_new"], ref["u_new"])
+    assert np.array_equal(got["codes"], ref["codes"])
+    if "x_m" in got:
+        assert np.array_equal(got["x_m"], ref["x_m"])
+        assert np.array_equal(got["x_d"], ref["x_d"])
+    assert got["n_ud"] == ref["u_d"].shape[0]
+
+
+# shapes: (n_um, n_main, n_delta, frac_new) -- several tiles and ragged tails
+SHAPES = [
+    (1, 1, 1, 0.0), (1, 10, 0, 0.0), (2, 64, 64, 0.5), (5, 4095, 17, 1.0),
+    (300, 4096, 4096, 0.5), (1000, 4097, 3071, 0.3), (777, 12_289, 9_001, 0.9),
+    (4096, 20_000, 2_049, 0.5), (50_000, 70_001, 40_000, 0.5), (0, 0, 5_000, 1.0),
+    (3, 100_000, 0, 0.0), (20_000, 9_000, 100_000, 0.1), (100_000, 1, 1, 1.0),
+    (60_000, 250_000, 33_333, 0.95),
+]
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_random_columns(vtype, shape):
+    n_um, n_main, nd, fn = shape
+    seed = zlib.crc32(repr((vtype, shape)).encode())
+    say(f"case {vtype} {shape} seed={seed}")
+    rng = np.random.default_rng(seed)
+    col = gen.random_column(rng, vtype, n_um, n_main, nd, fn,
+                            u64_high=2 ** 64 if vtype == "u64" else 2 ** 63)
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+@pytest.mark.parametrize("w_extra", [0, 1, 5])
+@pytest.mark.parametrize("n_um", [2, 3, 255, 256, 257, 65_537])
+def test_widths(n_um, w_extra):
+    """Input widths from 1 to 22 bits, output widths across word straddles."""
+    rng = np.random.default_rng(n_um * 7 + w_extra)
+    w = gen.code_width(n_um) + w_extra
+    say(f"case widths n_um={n_um} w={w}")
+    col = gen.random_column(rng, "u64", n_um, 30_011, 5_003, 0.5, w=w)
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+def test_wide_codes_32_bits():
+    rng = np.random.default_rng(32)
+    say("case width 32")
+    col = gen.random_column(rng, "u32", 3000, 20_000, 2000, 0.5, w=32)
+    assert_same(gpu_merge(col), ora_merge(col))
+    # an over-provisioned input width (31 bits for 8 entries): w' < w
+    u_m = np.arange(8, dtype=np.uint64)
+    codes = gen.pack_codes(np.arange(8) % 8, 31)
+    col = gen.Column("u64", u_m, codes, 8, 31, np.array([5, 2 ** 40], np.uint64))
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+def test_heavy_duplicates_and_zipf():
+    rng = np.random.default_rng(99)
+    say("case zipf str16")
+    col = gen.random_column(rng, "str16", 20_000, 200_000, 150_000, 0.3, zipf_s=1.1,
+                            new_pool=20_000)
+    assert_same(gpu_merge(col), ora_merge(col))
+    say("case all-equal delta u64")
+    u_m = np.array([10, 20, 30], np.uint64)
+    col = gen.Column("u64", u_m, gen.pack_codes(np.array([0, 1, 2] * 1000), 2), 3000, 2,
+                     np.full(70_000, 25, np.uint64))
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+def test_hand_example():
+    import json, os
+    ex = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_example.json")))
+    pad = lambda s: s.encode() + b"\0" * (16 - len(s))
+    arr = lambda ws: np.frombuffer(b"".join(pad(x) for x in ws), np.uint8).reshape(-1, 16).copy()
+    codes = [ex["u_m"].index(x) for x in ex["main_rows"]]
+    col = gen.Column("str16", arr(ex["u_m"]), gen.pack_codes(np.array(codes), 3), len(codes), 3,
+                     arr(ex["delta"]))
+    say("case hand example")
+    got = gpu_merge(col)
+    e = ex["expected"]
+    assert got["x_m"].tolist() == e["x_m"] and got["x_d"].tolist() == e["x_d"]
+    assert got["codes"].view(np.uint8)[:6].tobytes().hex() == e["new_packed_bytes"]
+    assert got["w_new"] == 4 and got["n_new"] == 9
+
+
+def test_config1_full():
+    say("case config 1 full")
+    col = gen.config_column(1)
+    got, ref = gpu_merge(col), ora_merge(col)
+    assert_same(got, ref)
+    assert got["n_new"] == 15_000 and got["w_new"] == 14
+
+
+def test_deterministic_and_no_tables():
+    rng = np.random.default_rng(3)
+    col = gen.random_column(rng, "u64", 40_000, 300_000, 60_000, 0.5)
+    say("case determinism")
+    a = gpu_merge(col, tables=False)
+    b = gpu_merge(col, tables=False)
+    assert np.array_equal(a["codes"], b["codes"]) and np.array_equal(a["u_new"], b["u_new"])
+    assert_same(a, ora_merge(col))
+
+
+def test_steps_individually():
+    """Each step entry point against the oracle's step (rows a1, a2+a3, a4+a5)."""
+    rng = np.random.default_rng(17)
+    for vtype in ("u32", "u64", "str16"):
+        col = gen.random_column(rng, vtype, 5_000, 40_000, 30_000, 0.6)
+        say(f"case steps {vtype}")
+        d_delta = cm.to_device(col.delta)
+        u_d, drank, cnt = cm.delta_dictionary(vtype, d_delta)
+        torch.cuda.synchronize()
+        ref_ud, ref_drank = oracle.delta_dictionary(vtype, col.delta)
+        n_ud = int(cnt[0].item())
+        assert n_ud == ref_ud.shape[0]
+        got_ud = u_d[:n_ud].cpu().numpy()
+        assert np.array_equal(got_ud.view(ref_ud.dtype) if vtype != "str16" else got_ud, ref_ud)
+        assert np.array_equal(drank.cpu().numpy().view(np.uint32), ref_drank)
+
+        d_um = cm.to_device(col.u_m)
+        u_new, x_m, x_d, res = cm.merge_dictionaries(vtype, d_um, u_d, cnt, col.n_delta,
+                                                     col.n_main + col.n_delta)
+        torch.cuda.synchronize()
+        ref_new, ref_xm, ref_xd = oracle.merge_dictionaries(vtype, col.u_m, ref_ud)
+        nn = ref_new.shape[0]
+        got_new = u_new[:nn].cpu().numpy()
+        assert np.array_equal(got_new.view(ref_new.dtype) if vtype != "str16" else got_new, ref_new)
+        assert np.array_equal(x_m.cpu().numpy().view(np.uint32), ref_xm)
+        assert np.array_equal(x_d[:n_ud].cpu().numpy().view(np.uint32), ref_xd)
+
+        w_new = oracle.width(nn)
+        words = (col.n_main + col.n_delta) * 32 // 64 + 2
+        out = torch.zeros(words, dtype=torch.int64, device="cuda")
+        cm.reencode(cm.to_device(col.main_packed), col.n_main, col.w, x_m, col.u_m.shape[0],
+                    drank, x_d, res, out)
+        torch.cuda.synchronize()
+        ref_codes = oracle.reencode(col.main_packed, col.n_main, col.w, ref_xm, ref_drank,
+                                    ref_xd, w_new)
+        got = out.cpu().numpy().view(np.uint64)[: ref_codes.shape[0]]
+        assert np.array_equal(got, ref_codes)
+
+
+def test_code_out_of_range_is_reported():
+    """A main code >= |U_M| is caught by the kernel's bounds check."""
+    u_m = np.array([1, 2, 3], np.uint64)
+    codes = gen.pack_codes(np.array([0, 1, 3, 2]), 2)     # 3 is outside the dictionary
+    col = gen.Column("u64", u_m, codes, 4, 2, np.array([7], np.uint64))
+    say("case code out of range")
+    got = gpu_merge(col)
+    assert got["error"] & 1
+
+
+def test_invalid_arguments_rejected_on_host():
+    col = gen.Column("u64", np.array([1, 2], np.uint64), gen.pack_codes(np.array([0, 1]), 1), 2, 1,
+                     np.array([3], np.uint64))
+    dcol = cm.ColumnInput.from_numpy(col)
+    out = cm.alloc_output(dcol)
+    out.new_codes = out.new_codes[:0]                        # no capacity
+    with pytest.raises(cm.ColmergeError) as e:
+        cm.merge_column(dcol, out=out)
+    assert e.value.code == -2
+    with pytest.raises(cm.ColmergeError) as e:
+        cm.merge_column(cm.ColumnInput("u64", dcol.u_m, dcol.main_codes, 2, 0, dcol.delta))
+    assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------
+# Full-size configurations: U', w', X tables in full; codes on sampled rows
+# plus properties that hold at any size.
+# ---------------------------------------------------------------------------
+
+def check_large(col, got, n_samples=20_000):
+    ref_ud, ref_drank = oracle.delta_dictionary(col.vtype, col.delta)
+    ref_new, ref_xm, ref_xd = oracle.merge_dictionaries(col.vtype, col.u_m, ref_ud)
+    assert got["error"] == 0
+    assert got["n_new"] == ref_new.shape[0]
+    assert got["w_new"] == oracle.width(ref_new.shape[0])
+    n_out = col.n_main + col.n_delta
+    assert got["words"] == (n_out * got["w_new"] + 63) // 64
+    assert np.array_equal(got["u_new"], ref_new)
+    assert np.array_equal(got["x_m"], ref_xm)
+    assert np.array_equal(got["x_d"], ref_xd)
+    rng = np.random.default_rng(1)
+    rows = np.concatenate([rng.integers(0, n_out, n_samples), [0, col.n_main - 1, col.n_main,
+                                                                n_out - 1]])
+    rows = rows[(rows >= 0) & (rows < n_out)]
+    w, wn = col.w, got["w_new"]
+    for i in rows.tolist():
+        c = oracle.unpack(got["codes"], i, wn)
+        if i < col.n_main:
+            exp = ref_xm[oracle.unpack(col.main_packed, i, w)]
+        else:
+            exp = ref_xd[ref_drank[i - col.n_main]]
+        assert c == exp, i
+    used = n_out * wn
+    if used % 64:
+        assert int(got["codes"][-1]) >> (used % 64) == 0
+
+
+@pytest.mark.slow
+def test_config2_full_size():
+    say("case config 2 (100M rows, 20->21 bits)")
+    col = gen.config_column(2)
+    got = gpu_merge(col)
+    assert got["n_new"] == 1_948_000 and got["w_new"] == 21
+    check_large(col, got)
+
+
+@pytest.mark.slow
+def test_config3_full_size():
+    say("case config 3 (100M rows, 16-byte strings, Zipf)")
+    col = gen.config_column(3)
+    got = gpu_merge(col)
+    assert got["w_new"] == 24
+    check_large(col, got)
