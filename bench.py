@@ -109,6 +109,22 @@ def main():
     ctx.set_timing(False)
     torch.cuda.synchronize()
 
+    # achievable streaming bandwidth: the library's plain 128-bit copy of
+    # 1 GiB (2 GiB moved per copy), timed with events on the same stream
+    copy_bytes = 1 << 30
+    src = torch.empty(copy_bytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        cm.copy_bytes(src, dst, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        cm.copy_bytes(src, dst, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * copy_bytes * 5 / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del src, dst
+
     n_out = col.n_main + col.n_delta
     value = n_out / (ms_per_step / 1000.0)
     b_alg = algorithmic_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
@@ -154,6 +170,8 @@ def main():
         "roofline": {"kernel": "k_repack (Step 2(b))", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": b_re},
+        "copy_kernel_gbs": copy_gbs,
+        "reencode_frac_of_copy": achieved / copy_gbs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -213,6 +213,15 @@ void mc_graph_destroy(mc_graph *graph);
 int mc_ctx_set_timing(mc_ctx *ctx, int enable);
 int mc_ctx_step_times(mc_ctx *ctx, float *ms5);
 
+/* ---- measurement ------------------------------------------------------- */
+
+/* Copy `bytes` (a multiple of 16; 16-byte aligned device buffers) with a
+ * plain 128-bit streaming kernel.  Not part of the merge: it measures the
+ * achievable HBM bandwidth beside the merge kernels and serves as the
+ * known-traffic kernel that calibrates hardware byte counters. */
+int mc_copy_bytes(mc_ctx *ctx, const void *src, void *dst, uint64_t bytes,
+                  struct ihipStream_t *stream);
+
 #ifdef __cplusplus
 }
 #endif

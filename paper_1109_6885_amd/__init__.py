@@ -297,6 +297,15 @@ def reencode(main_codes: torch.Tensor, n_main: int, w: int, x_m: torch.Tensor, n
     return out
 
 
+def copy_bytes(src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None, stream=None,
+               ctx=None):
+    """mc_copy_bytes: plain 128-bit device copy (bandwidth reference)."""
+    ctx = ctx or context()
+    n = src.numel() * src.element_size() if nbytes is None else nbytes
+    check(load().mc_copy_bytes(ctx.handle, _ptr(src), _ptr(dst), n, _stream(stream)),
+          "mc_copy_bytes")
+
+
 # ---------------------------------------------------------------------------
 # Batched
 # ---------------------------------------------------------------------------

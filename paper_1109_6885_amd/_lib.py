@@ -28,7 +28,7 @@ EXPORTS = [
     "mc_delta_dictionary", "mc_delta_dictionary_scratch", "mc_merge_dictionaries",
     "mc_merge_dictionaries_scratch", "mc_reencode", "mc_merge_batched_bounds",
     "mc_merge_columns_batched", "mc_graph_launch", "mc_graph_destroy", "mc_ctx_set_timing",
-    "mc_ctx_step_times",
+    "mc_ctx_step_times", "mc_copy_bytes",
 ]
 
 
@@ -92,6 +92,7 @@ def load():
         "mc_graph_destroy": (None, [p]),
         "mc_ctx_set_timing": (ctypes.c_int, [p, ctypes.c_int]),
         "mc_ctx_step_times": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_float)]),
+        "mc_copy_bytes": (ctypes.c_int, [p, p, p, u64, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

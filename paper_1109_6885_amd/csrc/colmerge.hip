@@ -159,6 +159,15 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, ui
         p1[i] = 0u;
 }
 
+// Plain 128-bit copy: the achievable streaming bandwidth on this GPU, and
+// the kernel of known traffic that calibrates hardware byte counters.
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
+                                                uint4 *__restrict__ dst, uint64_t n16) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
 int launch_fill(void *p0, uint64_t bytes0, void *p1, uint64_t bytes1, hipStream_t s) {
     const uint64_t n = (bytes0 > bytes1 ? bytes0 : bytes1) / 4;
     uint32_t grid = (uint32_t)(n / 256 / 4 + 1);
@@ -552,6 +561,23 @@ int mc_ctx_step_times(mc_ctx *ctx, float *ms5) {
         }
     }
     for (int k = 0; k < 5; k++) ms5[k] = (float)(acc[k] / (double)ctx->used);
+    return MC_OK;
+}
+
+int mc_copy_bytes(mc_ctx *ctx, const void *src, void *dst, uint64_t bytes, hipStream_t s) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    if ((bytes & 15u) || !aligned16(src) || !aligned16(dst))
+        return fail(MC_E_ARG, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+    if (bytes && (!src || !dst)) return fail(MC_E_ARG, "null buffer");
+    if (bytes == 0) return MC_OK;
+    int dev = 0, cus = 256;
+    MC_HIP(hipGetDevice(&dev));
+    MC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    uint64_t grid = ceil_div(bytes / 16, 256);
+    if (grid > (uint64_t)cus * 16) grid = (uint64_t)cus * 16;
+    hipLaunchKernelGGL(k_copy16, dim3((uint32_t)grid), dim3(256), 0, s,
+                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), bytes / 16);
+    MC_LAUNCHED("k_copy16");
     return MC_OK;
 }
 

@@ -35,6 +35,8 @@ struct RepackJob {
 constexpr int kRepackCodes = 4096;               // rows per tile (64 groups of 64)
 constexpr int kRepackPer = kRepackCodes / kBlock;  // codes per thread
 
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
 __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
     __shared__ __attribute__((aligned(16))) uint64_t s_in[64 * 32 + 2];
     __shared__ uint32_t s_code[kRepackCodes];
@@ -48,27 +50,33 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
     if (c0 >= n_out) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(kRepackCodes, n_out - c0);
 
-    // stage the main words of this tile
+    // stage the main words of this tile (streamed once: non-temporal, so the
+    // translation tables keep the cache)
     if (c0 < J.n_main) {
         const uint64_t win = (J.n_main * w + 63) / 64;  // readable input words
         const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 64
         const uint32_t nw = (uint32_t)min<uint64_t>(64ull * w, win - wbase);
         const uint32_t npair = nw / 2;
-        const ulonglong2 *src2 = reinterpret_cast<const ulonglong2 *>(J.main_codes + wbase);
-        ulonglong2 *dst2 = reinterpret_cast<ulonglong2 *>(s_in);
-        for (uint32_t x = threadIdx.x; x < npair; x += kBlock) dst2[x] = src2[x];
-        if ((nw & 1u) && threadIdx.x == 0) s_in[nw - 1] = J.main_codes[wbase + nw - 1];
+        const u64x2 *src2 = reinterpret_cast<const u64x2 *>(J.main_codes + wbase);
+        u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
+        for (uint32_t x = threadIdx.x; x < npair; x += kBlock)
+            dst2[x] = __builtin_nontemporal_load(src2 + x);
+        if ((nw & 1u) && threadIdx.x == 0)
+            s_in[nw - 1] = __builtin_nontemporal_load(J.main_codes + wbase + nw - 1);
     }
     __syncthreads();
 
-    // decode + translate
-    const uint64_t mask = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
+    // decode every code of this thread first, then issue all gathers together
+    const uint64_t mask = (1ull << w) - 1ull;
+    const uint32_t *tab[kRepackPer];
+    uint32_t idx[kRepackPer];
     uint32_t bad = 0;
-#pragma unroll 4
+#pragma unroll
     for (int j = 0; j < kRepackPer; j++) {
         const uint32_t i = j * kBlock + threadIdx.x;
         const uint64_t g = c0 + i;
-        uint32_t nc = 0;
+        tab[j] = nullptr;
+        idx[j] = 0;
         if (i < tn) {
             if (g < J.n_main) {
                 const uint32_t bit = i * w;
@@ -76,20 +84,28 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
                 uint64_t v = s_in[wi] >> sh;
                 if (sh + w > 64) v |= s_in[wi + 1] << (64 - sh);
                 const uint32_t c = (uint32_t)(v & mask);
-                if (c < J.n_um)
-                    nc = J.x_m[c];
-                else
+                if (c < J.n_um) {
+                    tab[j] = J.x_m;
+                    idx[j] = c;
+                } else {
                     bad |= MC_DEVERR_CODE_RANGE;
+                }
             } else {
                 const uint32_t r = J.drank[g - J.n_main];
-                if (r < n_ud)
-                    nc = J.x_d[r];
-                else
+                if (r < n_ud) {
+                    tab[j] = J.x_d;
+                    idx[j] = r;
+                } else {
                     bad |= MC_DEVERR_DELTA_RANGE;
+                }
             }
         }
-        s_code[i] = nc;
     }
+    uint32_t nc[kRepackPer];
+#pragma unroll
+    for (int j = 0; j < kRepackPer; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRepackPer; j++) s_code[j * kBlock + threadIdx.x] = nc[j];
     if (bad) flag_error(J.err, bad);
     __syncthreads();
 
@@ -98,14 +114,17 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
     const uint64_t wres = (n_out * wn + 63) / 64;
     const uint64_t wlim = min<uint64_t>(J.out_cap_words, (wres + 1) & ~1ull);
     const uint32_t nwo = 64u * wn;  // words of a full tile (even)
+    // floor(x / wn) for x < 2^17 as a multiply-high by ceil(2^32 / wn): the
+    // rounding error of the reciprocal times x stays below 2^32, so it is exact
+    const uint32_t rcp = (uint32_t)((0x100000000ull + wn - 1) / wn);
     for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
         uint64_t word[2];
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const uint32_t k = 2 * k2 + h;
             const uint32_t b0 = 64u * k;
-            uint32_t q = b0 / wn;
-            const uint32_t qe = min<uint32_t>((b0 + 63) / wn, kRepackCodes - 1);
+            uint32_t q = __umulhi(b0, rcp);
+            const uint32_t qe = min<uint32_t>(__umulhi(b0 + 63, rcp), kRepackCodes - 1);
             uint64_t acc = 0;
             for (; q <= qe; q++) {
                 const uint64_t c = s_code[q];
@@ -116,10 +135,10 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
         }
         const uint64_t gw = obase + 2ull * k2;
         if (gw + 1 < wlim) {
-            ulonglong2 v;
+            u64x2 v;
             v.x = word[0];
             v.y = word[1];
-            *reinterpret_cast<ulonglong2 *>(J.out + gw) = v;
+            __builtin_nontemporal_store(v, reinterpret_cast<u64x2 *>(J.out + gw));
         } else if (gw < wlim) {
             J.out[gw] = word[0];
         }
