@@ -24,7 +24,10 @@ struct mc_ctx {
     // one set of five events per timed merge since timing was enabled
     std::vector<std::array<hipEvent_t, 5>> ev;
     size_t used = 0;
-    hipEvent_t *cur = nullptr;  // events of the merge being enqueued
+    // pinned staging of batched descriptors, and the event of its last copy
+    void *meta_host = nullptr;
+    uint64_t meta_cap = 0;
+    hipEvent_t meta_event = nullptr;
 };
 
 struct mc_graph {
@@ -82,29 +85,12 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 // ---------------------------------------------------------------------------
-// Workspace layout.  The first region is cleared by one fill kernel at the
+// Workspace layout of one column.  Part Z is cleared by a fill kernel at the
 // start of every call (tile counters, histograms, prefix words, the sort's
-// "same digit" flags); the rest is written before it is read.
+// "same digit" flags, |U_D|, an error word); part B is written before it is
+// read.  A single-column call places Z then B in its scratch; a batched call
+// places every column's Z first (one contiguous clear) and then every B.
 // ---------------------------------------------------------------------------
-
-struct Layout {
-    uint64_t total = 0;
-    uint64_t zero_bytes = 0;  // zeroed region starts at offset 0
-    // zeroed
-    uint64_t counters = 0;    // u32[16]: [0] emit tiles, [1] merge tiles, [2] error word
-    uint64_t n_ud = 0;        // u64
-    uint64_t gh = 0;          // u32[passes*256]
-    uint64_t trivial = 0;     // u32[16]
-    uint64_t emit_status = 0; // u64[emit tiles]
-    uint64_t merge_status = 0;// u64[merge tiles]
-    // written before read
-    uint64_t base = 0;        // u32[passes*256]
-    uint64_t tcount = 0;      // u32[256*sort tiles]
-    uint64_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0;
-    uint64_t u_d = 0, drank = 0, x_d = 0, x_m = 0;
-    uint32_t sort_tiles = 0, emit_tiles = 0;
-    uint64_t merge_tiles = 0;
-};
 
 struct Carver {
     uint64_t off = 0;
@@ -114,41 +100,114 @@ struct Carver {
         off += bytes;
         return at;
     }
+    uint64_t size() const { return align_up(off, 256); }
 };
 
-Layout make_layout(int32_t type, uint64_t n_um, uint64_t nd, bool need_dict_scratch) {
-    Layout L;
+struct ColLayout {
+    // part Z
+    uint64_t counters = 0, n_ud = 0, err = 0, gh = 0, trivial = 0, emit_status = 0,
+             merge_status = 0, z_size = 0;
+    // part B
+    uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
+             drank = 0, x_d = 0, x_m = 0, b_size = 0;
+    uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
+    uint64_t merge_tiles = 0, repack_tiles = 0;
+};
+
+ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) {
+    ColLayout L;
     const uint32_t E = value_len(type);
-    const uint32_t P = E;  // one 8-bit digit per value byte
+    L.passes = E;  // one 8-bit digit per value byte
     L.sort_tiles = (uint32_t)ceil_div(nd, sort_tile_of(type));
     L.emit_tiles = (uint32_t)ceil_div(nd, mc::kEmitTile);
+    L.hist_tiles = (uint32_t)ceil_div(nd, mc::kHistChunk);
     L.merge_tiles = ceil_div(n_um + nd, mc::kMergeTile);
-    Carver c;
-    L.counters = c.take(16 * 4);
-    L.n_ud = c.take(8);
-    L.gh = c.take((uint64_t)P * 256 * 4);
-    L.trivial = c.take(16 * 4);
-    L.emit_status = c.take((uint64_t)L.emit_tiles * 8);
-    L.merge_status = c.take(L.merge_tiles * 8);
-    L.zero_bytes = align_up(c.off, 256);
-    c.off = L.zero_bytes;
-    L.base = c.take((uint64_t)P * 256 * 4);
-    L.tcount = c.take((uint64_t)256 * L.sort_tiles * 4);
-    L.keys0 = c.take(nd * E);
-    L.keys1 = c.take(nd * E);
-    L.vals0 = c.take(nd * 4);
-    L.vals1 = c.take(nd * 4);
-    if (need_dict_scratch) L.u_d = c.take(nd * E);
-    L.drank = c.take(nd * 4);
-    L.x_d = c.take(nd * 4);
-    L.x_m = c.take(n_um * 4);
-    L.total = align_up(c.off, 256);
+    L.repack_tiles = ceil_div(n_main + nd, mc::kRepackCodes);
+    Carver z;
+    L.counters = z.take(16 * 4);
+    L.n_ud = z.take(8);
+    L.err = z.take(8);
+    L.gh = z.take((uint64_t)L.passes * 256 * 4);
+    L.trivial = z.take(16 * 4);
+    L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
+    L.merge_status = z.take(L.merge_tiles * 8);
+    L.z_size = z.size();
+    Carver b;
+    L.base = b.take((uint64_t)L.passes * 256 * 4);
+    L.tcount = b.take((uint64_t)256 * L.sort_tiles * 4);
+    L.keys0 = b.take(nd * E);
+    L.keys1 = b.take(nd * E);
+    L.vals0 = b.take(nd * 4);
+    L.vals1 = b.take(nd * 4);
+    L.u_d = b.take(nd * E);
+    L.drank = b.take(nd * 4);
+    L.x_d = b.take(nd * 4);
+    L.x_m = b.take(n_um * 4);
+    L.b_size = b.size();
     return L;
 }
 
+uint64_t single_scratch(const ColLayout &L) { return L.z_size + L.b_size; }
+
+// Descriptor of one column with its workspace at za (part Z) and zb (part B).
+mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za, char *zb,
+                      const ColLayout &L) {
+    mc::ColDesc C;
+    memset(&C, 0, sizeof(C));
+    C.type = in->type;
+    C.w = in->bitwidth;
+    C.u_m = in->main_dict;
+    C.n_um = in->main_dict_len;
+    C.main_codes = in->main_codes;
+    C.n_main = in->main_rows;
+    C.delta = in->delta_values;
+    C.nd = (uint32_t)in->delta_rows;
+    C.sort_tiles = L.sort_tiles;
+    C.u_new = out->new_dict;
+    C.u_new_cap = out->new_dict_cap;
+    C.out = out->new_codes;
+    C.out_cap = out->new_codes_cap_words;
+    C.x_m = out->x_main ? out->x_main : reinterpret_cast<uint32_t *>(zb + L.x_m);
+    C.x_d = out->x_delta ? out->x_delta : reinterpret_cast<uint32_t *>(zb + L.x_d);
+    C.result = out->result;
+    C.err = &out->result->error;
+    C.rows_total = in->main_rows + in->delta_rows;
+    C.keys0 = zb + L.keys0;
+    C.keys1 = zb + L.keys1;
+    C.vals0 = reinterpret_cast<uint32_t *>(zb + L.vals0);
+    C.vals1 = reinterpret_cast<uint32_t *>(zb + L.vals1);
+    C.gh = reinterpret_cast<uint32_t *>(za + L.gh);
+    C.base = reinterpret_cast<uint32_t *>(zb + L.base);
+    C.trivial = reinterpret_cast<uint32_t *>(za + L.trivial);
+    C.tcount = reinterpret_cast<uint32_t *>(zb + L.tcount);
+    C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
+    C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);
+    C.merge_status = reinterpret_cast<uint64_t *>(za + L.merge_status);
+    C.n_ud = reinterpret_cast<uint64_t *>(za + L.n_ud);
+    C.n_ud_in = C.n_ud;
+    C.nd_max = in->delta_rows;
+    C.u_d = zb + L.u_d;
+    C.drank = reinterpret_cast<uint32_t *>(zb + L.drank);
+    return C;
+}
+
 // ---------------------------------------------------------------------------
-// Kernels that do not depend on the value type.
+// Kernels.  k1_* serve one column (descriptor by value, grid = its tiles);
+// kn_* serve a batch: every workgroup finds its column in a per-phase prefix
+// of tile counts and runs the same tile function, dispatched on the value
+// type, with LDS sized for the largest type.
 // ---------------------------------------------------------------------------
+
+template <class A, class B, class C3>
+constexpr size_t max3(A a, B b, C3 c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+constexpr size_t kSmemHist = sizeof(mc::HistSmem<mc::TS16>);
+constexpr size_t kSmemDown = max3(sizeof(mc::DownSmem<mc::TU32>), sizeof(mc::DownSmem<mc::TU64>),
+                                  sizeof(mc::DownSmem<mc::TS16>));
+constexpr size_t kSmemMerge = max3(sizeof(mc::MergeSmem<mc::TU32>),
+                                   sizeof(mc::MergeSmem<mc::TU64>),
+                                   sizeof(mc::MergeSmem<mc::TS16>));
+constexpr size_t kSmemSmall = 1024;
 
 __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, uint32_t *p1,
                                                    uint64_t n1) {
@@ -168,6 +227,131 @@ __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
         dst[i] = src[i];
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k1_hist(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::HistSmem<T>)];
+    mc::hist_tile<T>(C, blockIdx.x, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_hist_scan(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[64];
+    mc::hist_scan_col<T>(C, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_sort_up(mc::ColDesc C, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
+    mc::sort_up_tile<T>(C, p, blockIdx.x, smem);
+}
+__global__ __launch_bounds__(256) void k1_sort_scan(mc::ColDesc C, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[64];
+    mc::sort_scan_digit(C, p, blockIdx.x, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
+    mc::sort_down_tile<T>(C, p, blockIdx.x, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem)];
+    mc::emit_tile<T>(C, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_merge(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T>)];
+    mc::merge_tile<T>(C, smem);
+}
+__global__ __launch_bounds__(256) void k1_repack(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
+    mc::repack_tile(C, blockIdx.x, smem);
+}
+
+// ---- batched ----
+
+struct Batch {
+    const mc::ColDesc *cols;
+    const uint32_t *map;  // ncols + 1 prefix of tile counts for this phase
+    uint32_t ncols;
+};
+
+// Column of workgroup b: the j with map[j] <= b < map[j + 1].
+__device__ __forceinline__ uint32_t find_col(const Batch &B, uint32_t b) {
+    uint32_t lo = 0, hi = B.ncols;  // map[lo] <= b < map[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (B.map[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+#define MC_DISPATCH(C, FN, ...)                                     \
+    switch ((C).type) {                                             \
+        case MC_U32: FN<mc::TU32>(__VA_ARGS__); break;              \
+        case MC_U64: FN<mc::TU64>(__VA_ARGS__); break;              \
+        default: FN<mc::TS16>(__VA_ARGS__); break;                  \
+    }
+
+__global__ __launch_bounds__(256) void kn_zero_results(Batch B) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < B.ncols;
+         j += gridDim.x * blockDim.x) {
+        mc_result *r = B.cols[j].result;
+        r->new_dict_len = 0;
+        r->new_codes_words = 0;
+        r->delta_dict_len = 0;
+        r->new_bitwidth = 0;
+        r->error = 0;
+    }
+}
+__global__ __launch_bounds__(256) void kn_hist(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemHist];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::hist_tile, C, blockIdx.x - B.map[j], smem);
+}
+__global__ __launch_bounds__(256) void kn_hist_scan(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[64];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::hist_scan_col, C, smem);
+}
+__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::sort_up_tile, C, p, blockIdx.x - B.map[j], smem);
+}
+__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[64];
+    const uint32_t j = find_col(B, blockIdx.x);
+    mc::sort_scan_digit(B.cols[j], p, blockIdx.x - B.map[j], smem);
+}
+__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::sort_down_tile, C, p, blockIdx.x - B.map[j], smem);
+}
+__global__ __launch_bounds__(256) void kn_emit(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem)];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::emit_tile, C, smem);
+}
+__global__ __launch_bounds__(256) void kn_merge(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemMerge];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::merge_tile, C, smem);
+}
+__global__ __launch_bounds__(256) void kn_repack(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
+    const uint32_t j = find_col(B, blockIdx.x);
+    mc::repack_tile(B.cols[j], blockIdx.x - B.map[j], smem);
+}
+
 int launch_fill(void *p0, uint64_t bytes0, void *p1, uint64_t bytes1, hipStream_t s) {
     const uint64_t n = (bytes0 > bytes1 ? bytes0 : bytes1) / 4;
     uint32_t grid = (uint32_t)(n / 256 / 4 + 1);
@@ -179,106 +363,47 @@ int launch_fill(void *p0, uint64_t bytes0, void *p1, uint64_t bytes1, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// Step launchers
+// Single-column step launchers
 // ---------------------------------------------------------------------------
 
-// Step 1(a): sort the delta and emit U_D / drank.  Scratch regions come from
-// the layout; the zeroed region must already be clear.
 template <class T>
-int launch_delta_dictionary(const void *delta, uint64_t nd, void *u_d, uint32_t *drank,
-                            uint64_t *n_ud, char *ws, const Layout &L, uint32_t *err,
-                            hipStream_t s, mc_ctx *ctx) {
-    if (nd == 0) return MC_OK;
-    mc::SortJob J;
-    J.src = delta;
-    J.keys[0] = ws + L.keys0;
-    J.keys[1] = ws + L.keys1;
-    J.vals[0] = reinterpret_cast<uint32_t *>(ws + L.vals0);
-    J.vals[1] = reinterpret_cast<uint32_t *>(ws + L.vals1);
-    J.n = (uint32_t)nd;
-    J.ntiles = L.sort_tiles;
-    J.gh = reinterpret_cast<uint32_t *>(ws + L.gh);
-    J.base = reinterpret_cast<uint32_t *>(ws + L.base);
-    J.trivial = reinterpret_cast<uint32_t *>(ws + L.trivial);
-    J.tcount = reinterpret_cast<uint32_t *>(ws + L.tcount);
-    J.err = err;
-    constexpr int P = T::kBytes;
-    uint32_t hgrid = (uint32_t)ceil_div(nd, 256 * 16);
-    if (hgrid > 1024) hgrid = 1024;
-    hipLaunchKernelGGL(mc::k_hist_all<T>, dim3(hgrid), dim3(mc::kBlock), 0, s, J);
-    MC_LAUNCHED("k_hist_all");
-    hipLaunchKernelGGL(mc::k_hist_scan<T>, dim3(1), dim3(mc::kBlock), 0, s, J);
-    MC_LAUNCHED("k_hist_scan");
-    for (int p = 0; p < P; p++) {
-        hipLaunchKernelGGL(mc::k_sort_up<T>, dim3(J.ntiles), dim3(mc::kBlock), 0, s, J, p);
-        MC_LAUNCHED("k_sort_up");
-        hipLaunchKernelGGL(mc::k_sort_scan<T>, dim3(256), dim3(mc::kBlock), 0, s, J, p);
-        MC_LAUNCHED("k_sort_scan");
-        hipLaunchKernelGGL(mc::k_sort_down<T>, dim3(J.ntiles), dim3(mc::kBlock), 0, s, J, p);
-        MC_LAUNCHED("k_sort_down");
+int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_t s,
+                            hipEvent_t after_sort) {
+    if (C.nd == 0) {
+        if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
+        return MC_OK;
     }
-    if (ctx && ctx->cur) MC_HIP(hipEventRecord(ctx->cur[1], s));
-    mc::EmitJob E;
-    E.keys = J.keys[(P - 1) & 1];
-    E.rows = J.vals[(P - 1) & 1];
-    E.n = (uint32_t)nd;
-    E.u_d = u_d;
-    E.drank = drank;
-    E.n_ud = n_ud;
-    E.status = reinterpret_cast<uint64_t *>(ws + L.emit_status);
-    E.counter = reinterpret_cast<uint32_t *>(ws + L.counters) + 0;
-    E.err = err;
-    hipLaunchKernelGGL(mc::k_emit<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, E);
-    MC_LAUNCHED("k_emit");
+    hipLaunchKernelGGL(k1_hist<T>, dim3(L.hist_tiles), dim3(mc::kBlock), 0, s, C);
+    MC_LAUNCHED("k1_hist");
+    hipLaunchKernelGGL(k1_hist_scan<T>, dim3(1), dim3(mc::kBlock), 0, s, C);
+    MC_LAUNCHED("k1_hist_scan");
+    for (int p = 0; p < T::kBytes; p++) {
+        hipLaunchKernelGGL(k1_sort_up<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, p);
+        MC_LAUNCHED("k1_sort_up");
+        hipLaunchKernelGGL(k1_sort_scan, dim3(256), dim3(mc::kBlock), 0, s, C, p);
+        MC_LAUNCHED("k1_sort_scan");
+        hipLaunchKernelGGL(k1_sort_down<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, p);
+        MC_LAUNCHED("k1_sort_down");
+    }
+    if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
+    hipLaunchKernelGGL(k1_emit<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
+    MC_LAUNCHED("k1_emit");
     return MC_OK;
 }
 
 template <class T>
-int launch_merge(const void *u_m, uint64_t n_um, const void *u_d, const uint64_t *d_n_ud,
-                 uint64_t nd_max, void *u_new, uint32_t *x_m, uint32_t *x_d,
-                 uint64_t rows_total, mc_result *result, char *ws, const Layout &L,
-                 hipStream_t s) {
-    mc::MergeJob M;
-    M.u_m = u_m;
-    M.n_um = n_um;
-    M.u_d = u_d;
-    M.d_n_ud = d_n_ud;
-    M.n_ud_max = nd_max;
-    M.u_new = u_new;
-    M.x_m = x_m;
-    M.x_d = x_d;
-    M.rows_total = rows_total;
-    M.result = result;
-    M.status = reinterpret_cast<uint64_t *>(ws + L.merge_status);
-    M.counter = reinterpret_cast<uint32_t *>(ws + L.counters) + 1;
-    M.err = &result->error;
-    uint64_t grid = ceil_div(n_um + nd_max, mc::kMergeTile);
-    if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(mc::k_merge<T>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, M);
-    MC_LAUNCHED("k_merge");
+int launch_merge(const mc::ColDesc &C, uint64_t merge_tiles, hipStream_t s) {
+    const uint64_t grid = merge_tiles ? merge_tiles : 1;
+    hipLaunchKernelGGL(k1_merge<T>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C);
+    MC_LAUNCHED("k1_merge");
     return MC_OK;
 }
 
-int launch_repack(const uint64_t *main_codes, uint64_t n_main, uint32_t w, const uint32_t *x_m,
-                  uint64_t n_um, const uint32_t *drank, uint64_t nd, const uint32_t *x_d,
-                  mc_result *result, uint64_t *out, uint64_t cap, hipStream_t s) {
-    mc::RepackJob R;
-    R.main_codes = main_codes;
-    R.n_main = n_main;
-    R.w = w;
-    R.x_m = x_m;
-    R.n_um = n_um;
-    R.drank = drank;
-    R.n_delta = nd;
-    R.x_d = x_d;
-    R.result = result;
-    R.out = out;
-    R.out_cap_words = cap;
-    R.err = &result->error;
-    uint64_t grid = ceil_div(n_main + nd, mc::kRepackCodes);
+int launch_repack(const mc::ColDesc &C, hipStream_t s) {
+    const uint64_t grid = ceil_div(C.n_main + C.nd, mc::kRepackCodes);
     if (grid == 0) return MC_OK;
-    hipLaunchKernelGGL(mc::k_repack, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, R);
-    MC_LAUNCHED("k_repack");
+    hipLaunchKernelGGL(k1_repack, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C);
+    MC_LAUNCHED("k1_repack");
     return MC_OK;
 }
 
@@ -302,6 +427,7 @@ int check_in(const mc_column_in *in) {
     if (in->delta_rows >= (1ull << 30)) return fail(MC_E_ARG, "delta_rows must be < 2^30");
     if (in->main_dict_len + in->delta_rows > (1ull << 32))
         return fail(MC_E_ARG, "|U_M| + N_D must be <= 2^32");
+    if (in->main_rows > (1ull << 40)) return fail(MC_E_ARG, "main_rows must be <= 2^40");
     if (in->main_dict_len > 0 && !in->main_dict) return fail(MC_E_ARG, "null main_dict");
     if (in->main_rows > 0 && !in->main_codes) return fail(MC_E_ARG, "null main_codes");
     if (in->delta_rows > 0 && !in->delta_values) return fail(MC_E_ARG, "null delta_values");
@@ -329,43 +455,31 @@ int check_out(const mc_column_in *in, const mc_column_out *out) {
 
 template <class T>
 int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out, char *ws,
-                   const Layout &L, hipStream_t s) {
-    uint32_t *err = &out->result->error;
-    const uint64_t nd = in->delta_rows;
-    uint32_t *x_m = out->x_main ? out->x_main : reinterpret_cast<uint32_t *>(ws + L.x_m);
-    uint32_t *x_d = out->x_delta ? out->x_delta : reinterpret_cast<uint32_t *>(ws + L.x_d);
-    uint32_t *drank = reinterpret_cast<uint32_t *>(ws + L.drank);
-    uint64_t *n_ud = reinterpret_cast<uint64_t *>(ws + L.n_ud);
-    void *u_d = ws + L.u_d;
-    ctx->cur = nullptr;
+                   const ColLayout &L, hipStream_t s) {
+    const mc::ColDesc C = make_desc(in, out, ws, ws + L.z_size, L);
+    hipEvent_t *ev = nullptr;
     if (ctx->timing) {
         if (ctx->used == ctx->ev.size()) {
             std::array<hipEvent_t, 5> set{};
             for (auto &e : set) MC_HIP(hipEventCreate(&e));
             ctx->ev.push_back(set);
         }
-        ctx->cur = ctx->ev[ctx->used].data();
-        MC_HIP(hipEventRecord(ctx->cur[0], s));
+        ev = ctx->ev[ctx->used].data();
+        MC_HIP(hipEventRecord(ev[0], s));
     }
-    int rc = launch_fill(ws, L.zero_bytes, out->result, sizeof(mc_result), s);
+    int rc = launch_fill(ws, L.z_size, out->result, sizeof(mc_result), s);
     if (rc) return rc;
-    rc = launch_delta_dictionary<T>(in->delta_values, nd, u_d, drank, n_ud, ws, L, err, s, ctx);
+    rc = launch_delta_dictionary<T>(C, L, s, ev ? ev[1] : nullptr);
     if (rc) return rc;
-    if (ctx->cur) {
-        if (nd == 0) MC_HIP(hipEventRecord(ctx->cur[1], s));
-        MC_HIP(hipEventRecord(ctx->cur[2], s));
-    }
-    rc = launch_merge<T>(in->main_dict, in->main_dict_len, u_d, n_ud, nd, out->new_dict, x_m, x_d,
-                         in->main_rows + nd, out->result, ws, L, s);
+    if (ev) MC_HIP(hipEventRecord(ev[2], s));
+    rc = launch_merge<T>(C, L.merge_tiles, s);
     if (rc) return rc;
-    if (ctx->cur) MC_HIP(hipEventRecord(ctx->cur[3], s));
-    rc = launch_repack(in->main_codes, in->main_rows, in->bitwidth, x_m, in->main_dict_len, drank,
-                       nd, x_d, out->result, out->new_codes, out->new_codes_cap_words, s);
+    if (ev) MC_HIP(hipEventRecord(ev[3], s));
+    rc = launch_repack(C, s);
     if (rc) return rc;
-    if (ctx->cur) {
-        MC_HIP(hipEventRecord(ctx->cur[4], s));
+    if (ev) {
+        MC_HIP(hipEventRecord(ev[4], s));
         ctx->used++;
-        ctx->cur = nullptr;
     }
     return MC_OK;
 }
@@ -377,8 +491,9 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
     if (rc) return rc;
     rc = check_out(in, out);
     if (rc) return rc;
-    const Layout L = make_layout(in->type, in->main_dict_len, in->delta_rows, true);
-    if (!scratch || scratch_bytes < L.total) return fail(MC_E_CAP, "scratch below mc_merge_bounds");
+    const ColLayout L = col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows);
+    if (!scratch || scratch_bytes < single_scratch(L))
+        return fail(MC_E_CAP, "scratch below mc_merge_bounds");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
     char *ws = static_cast<char *>(scratch);
     switch (in->type) {
@@ -386,6 +501,127 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
         case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, s);
         default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, s);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batched plan: every column's workspace, the device descriptor array and
+// the per-phase tile maps, all inside the caller's scratch.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxPasses = 16;
+// map slots: 0 hist, 1 hist_scan, 2..17 pass up/down, 18..33 pass scan,
+// 34 emit, 35 merge, 36 repack, 37 zero-results (one entry per column)
+constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 2 + kMaxPasses,
+              kMapEmit = 2 + 2 * kMaxPasses, kMapMerge = kMapEmit + 1, kMapRepack = kMapEmit + 2,
+              kNumMaps = kMapEmit + 3;
+
+struct BatchPlan {
+    uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, total = 0;
+    std::vector<uint64_t> z_off, b_off;
+    std::vector<ColLayout> L;
+    std::vector<uint32_t> maps;  // kNumMaps x (ncols + 1)
+    uint32_t max_passes = 0;
+};
+
+int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P) {
+    P.z_off.resize(ncols);
+    P.b_off.resize(ncols);
+    P.L.resize(ncols);
+    P.maps.assign((size_t)kNumMaps * (ncols + 1), 0u);
+    uint64_t z = 0, b = 0;
+    for (uint32_t i = 0; i < ncols; i++) {
+        int rc = check_in(&ins[i]);
+        if (rc) return rc;
+        P.L[i] = col_layout(ins[i].type, ins[i].main_dict_len, ins[i].delta_rows,
+                            ins[i].main_rows);
+        P.z_off[i] = z;
+        z += P.L[i].z_size;
+        P.b_off[i] = b;
+        b += P.L[i].b_size;
+        if (ins[i].delta_rows > 0 && P.L[i].passes > P.max_passes) P.max_passes = P.L[i].passes;
+    }
+    P.z_total = align_up(z, 256);
+    P.b_total = align_up(b, 256);
+    P.desc_off = P.z_total + P.b_total;
+    P.map_off = P.desc_off + align_up((uint64_t)ncols * sizeof(mc::ColDesc), 256);
+    P.total = P.map_off + align_up((uint64_t)P.maps.size() * 4, 256);
+    // tile-count prefixes per phase
+    auto at = [&](int m, uint32_t j) -> uint32_t & { return P.maps[(size_t)m * (ncols + 1) + j]; };
+    for (int m = 0; m < kNumMaps; m++) {
+        uint64_t acc = 0;
+        for (uint32_t j = 0; j < ncols; j++) {
+            const ColLayout &L = P.L[j];
+            const bool has_delta = ins[j].delta_rows > 0;
+            uint64_t n = 0;
+            if (m == kMapHist) n = L.hist_tiles;
+            else if (m == kMapHistScan) n = has_delta ? 1 : 0;
+            else if (m >= kMapPass && m < kMapPass + kMaxPasses)
+                n = (has_delta && (uint32_t)(m - kMapPass) < L.passes) ? L.sort_tiles : 0;
+            else if (m >= kMapScan && m < kMapScan + kMaxPasses)
+                n = (has_delta && (uint32_t)(m - kMapScan) < L.passes) ? 256 : 0;
+            else if (m == kMapEmit) n = L.emit_tiles;
+            else if (m == kMapMerge) n = L.merge_tiles ? L.merge_tiles : 1;
+            else if (m == kMapRepack) n = L.repack_tiles;
+            at(m, j) = (uint32_t)acc;
+            acc += n;
+            if (acc >= (1ull << 31)) return fail(MC_E_ARG, "batch has too many tiles for one launch");
+        }
+        at(m, ncols) = (uint32_t)acc;
+    }
+    return MC_OK;
+}
+
+// Enqueue the batched launch sequence (descriptors and maps already on the device).
+int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
+    const mc::ColDesc *d_cols = reinterpret_cast<const mc::ColDesc *>(ws + P.desc_off);
+    const uint32_t *d_maps = reinterpret_cast<const uint32_t *>(ws + P.map_off);
+    auto batch = [&](int m) {
+        Batch B;
+        B.cols = d_cols;
+        B.map = d_maps + (size_t)m * (ncols + 1);
+        B.ncols = ncols;
+        return B;
+    };
+    auto tiles = [&](int m) { return P.maps[(size_t)m * (ncols + 1) + ncols]; };
+    int rc = launch_fill(ws, P.z_total, nullptr, 0, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(kn_zero_results, dim3((ncols + 255) / 256), dim3(256), 0, s, batch(0));
+    MC_LAUNCHED("kn_zero_results");
+    if (tiles(kMapHist)) {
+        hipLaunchKernelGGL(kn_hist, dim3(tiles(kMapHist)), dim3(mc::kBlock), 0, s, batch(kMapHist));
+        MC_LAUNCHED("kn_hist");
+        hipLaunchKernelGGL(kn_hist_scan, dim3(tiles(kMapHistScan)), dim3(mc::kBlock), 0, s,
+                           batch(kMapHistScan));
+        MC_LAUNCHED("kn_hist_scan");
+    }
+    for (uint32_t p = 0; p < P.max_passes; p++) {
+        const uint32_t tp = tiles(kMapPass + p);
+        if (!tp) continue;
+        hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + p),
+                           (int)p);
+        MC_LAUNCHED("kn_sort_up");
+        hipLaunchKernelGGL(kn_sort_scan, dim3(tiles(kMapScan + p)), dim3(mc::kBlock), 0, s,
+                           batch(kMapScan + p), (int)p);
+        MC_LAUNCHED("kn_sort_scan");
+        hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + p),
+                           (int)p);
+        MC_LAUNCHED("kn_sort_down");
+    }
+    if (tiles(kMapEmit)) {
+        hipLaunchKernelGGL(kn_emit, dim3(tiles(kMapEmit)), dim3(mc::kBlock), 0, s, batch(kMapEmit));
+        MC_LAUNCHED("kn_emit");
+    }
+    if (tiles(kMapMerge)) {
+        hipLaunchKernelGGL(kn_merge, dim3(tiles(kMapMerge)), dim3(mc::kBlock), 0, s,
+                           batch(kMapMerge));
+        MC_LAUNCHED("kn_merge");
+    }
+    if (tiles(kMapRepack)) {
+        hipLaunchKernelGGL(kn_repack, dim3(tiles(kMapRepack)), dim3(mc::kBlock), 0, s,
+                           batch(kMapRepack));
+        MC_LAUNCHED("kn_repack");
+    }
+    return MC_OK;
 }
 
 }  // namespace
@@ -412,6 +648,11 @@ int mc_ctx_create(int device, mc_ctx **out) {
 
 void mc_ctx_destroy(mc_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->meta_event) {
+        (void)hipEventSynchronize(ctx->meta_event);
+        (void)hipEventDestroy(ctx->meta_event);
+    }
+    if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
     for (auto &set : ctx->ev)
         for (auto &e : set)
             if (e) (void)hipEventDestroy(e);
@@ -427,7 +668,8 @@ int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap, uint64_t *codes_
     if (dict_cap) *dict_cap = dc;
     if (codes_words) *codes_words = codes_words_bound(rows, dc);
     if (scratch_bytes)
-        *scratch_bytes = make_layout(in->type, in->main_dict_len, in->delta_rows, true).total;
+        *scratch_bytes = single_scratch(
+            col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows));
     return MC_OK;
 }
 
@@ -439,7 +681,7 @@ int mc_merge_column(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *ou
 int mc_delta_dictionary_scratch(int32_t type, uint64_t delta_rows, uint64_t *scratch_bytes) {
     if (value_len(type) == 0) return fail(MC_E_ARG, "unknown value type");
     if (delta_rows >= (1ull << 30)) return fail(MC_E_ARG, "delta_rows must be < 2^30");
-    if (scratch_bytes) *scratch_bytes = make_layout(type, 0, delta_rows, false).total;
+    if (scratch_bytes) *scratch_bytes = single_scratch(col_layout(type, 0, delta_rows, 0));
     return MC_OK;
 }
 
@@ -454,32 +696,42 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     if (!aligned16(delta_values) || !aligned16(u_d) || !aligned4(drank) ||
         (reinterpret_cast<uintptr_t>(d_count) & 7u))
         return fail(MC_E_ARG, "misaligned buffer");
-    const Layout L = make_layout(type, 0, delta_rows, false);
-    if (!scratch || scratch_bytes < L.total) return fail(MC_E_CAP, "scratch too small");
+    const ColLayout L = col_layout(type, 0, delta_rows, 0);
+    if (!scratch || scratch_bytes < single_scratch(L)) return fail(MC_E_CAP, "scratch too small");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
-    char *ws = static_cast<char *>(scratch);
-    int rc = launch_fill(ws, L.zero_bytes, d_count, 8, s);
+    char *za = static_cast<char *>(scratch), *zb = za + L.z_size;
+    mc::ColDesc C;
+    memset(&C, 0, sizeof(C));
+    C.type = type;
+    C.delta = delta_values;
+    C.nd = (uint32_t)delta_rows;
+    C.sort_tiles = L.sort_tiles;
+    C.err = reinterpret_cast<uint32_t *>(za + L.err);
+    C.keys0 = zb + L.keys0;
+    C.keys1 = zb + L.keys1;
+    C.vals0 = reinterpret_cast<uint32_t *>(zb + L.vals0);
+    C.vals1 = reinterpret_cast<uint32_t *>(zb + L.vals1);
+    C.gh = reinterpret_cast<uint32_t *>(za + L.gh);
+    C.base = reinterpret_cast<uint32_t *>(zb + L.base);
+    C.trivial = reinterpret_cast<uint32_t *>(za + L.trivial);
+    C.tcount = reinterpret_cast<uint32_t *>(zb + L.tcount);
+    C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
+    C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);
+    C.n_ud = d_count;
+    C.nd_max = delta_rows;
+    C.u_d = u_d;
+    C.drank = drank;
+    int rc = launch_fill(za, L.z_size, d_count, 8, s);
     if (rc) return rc;
-    uint32_t *err = reinterpret_cast<uint32_t *>(ws + L.counters) + 2;
     switch (type) {
-        case MC_U32:
-            return launch_delta_dictionary<mc::TU32>(delta_values, delta_rows, u_d, drank, d_count,
-                                                     ws, L, err, s, nullptr);
-        case MC_U64:
-            return launch_delta_dictionary<mc::TU64>(delta_values, delta_rows, u_d, drank, d_count,
-                                                     ws, L, err, s, nullptr);
-        default:
-            return launch_delta_dictionary<mc::TS16>(delta_values, delta_rows, u_d, drank, d_count,
-                                                     ws, L, err, s, nullptr);
+        case MC_U32: return launch_delta_dictionary<mc::TU32>(C, L, s, nullptr);
+        case MC_U64: return launch_delta_dictionary<mc::TU64>(C, L, s, nullptr);
+        default: return launch_delta_dictionary<mc::TS16>(C, L, s, nullptr);
     }
 }
 
 int mc_merge_dictionaries_scratch(uint64_t n_um, uint64_t n_ud_max, uint64_t *scratch_bytes) {
-    // only the counters and the merge prefix words are used
-    Carver c;
-    c.take(16 * 4);
-    c.take(ceil_div(n_um + n_ud_max, mc::kMergeTile) * 8);
-    if (scratch_bytes) *scratch_bytes = align_up(c.off, 256);
+    if (scratch_bytes) *scratch_bytes = col_layout(MC_U32, n_um, n_ud_max, 0).z_size;
     return MC_OK;
 }
 
@@ -496,28 +748,34 @@ int mc_merge_dictionaries(mc_ctx *ctx, int32_t type, const void *u_m, uint64_t n
         return fail(MC_E_ARG, "null buffer");
     if (!aligned16(u_m) || !aligned16(u_d) || !aligned16(u_new) || !aligned16(result))
         return fail(MC_E_ARG, "misaligned buffer");
-    uint64_t need = 0;
-    mc_merge_dictionaries_scratch(n_um, n_ud_max, &need);
-    if (!scratch || scratch_bytes < need) return fail(MC_E_CAP, "scratch too small");
-    // the merge needs only the counters and its prefix words
-    Layout L;
-    Carver c;
-    L.counters = c.take(16 * 4);
-    L.merge_status = c.take(ceil_div(n_um + n_ud_max, mc::kMergeTile) * 8);
-    L.zero_bytes = align_up(c.off, 256);
-    char *ws = static_cast<char *>(scratch);
-    int rc = launch_fill(ws, L.zero_bytes, result, sizeof(mc_result), s);
+    // the merge uses only the zeroed part of a column layout (counters, prefix words)
+    const ColLayout L = col_layout(MC_U32, n_um, n_ud_max, 0);
+    if (!scratch || scratch_bytes < L.z_size) return fail(MC_E_CAP, "scratch too small");
+    if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
+    char *za = static_cast<char *>(scratch);
+    mc::ColDesc C;
+    memset(&C, 0, sizeof(C));
+    C.type = type;
+    C.u_m = u_m;
+    C.n_um = n_um;
+    C.u_d = const_cast<void *>(u_d);
+    C.n_ud_in = d_n_ud;
+    C.nd_max = n_ud_max;
+    C.u_new = u_new;
+    C.u_new_cap = n_um + n_ud_max;
+    C.x_m = x_m;
+    C.x_d = x_d;
+    C.result = result;
+    C.err = &result->error;
+    C.rows_total = rows_total;
+    C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
+    C.merge_status = reinterpret_cast<uint64_t *>(za + L.merge_status);
+    int rc = launch_fill(za, L.z_size, result, sizeof(mc_result), s);
     if (rc) return rc;
     switch (type) {
-        case MC_U32:
-            return launch_merge<mc::TU32>(u_m, n_um, u_d, d_n_ud, n_ud_max, u_new, x_m, x_d,
-                                          rows_total, result, ws, L, s);
-        case MC_U64:
-            return launch_merge<mc::TU64>(u_m, n_um, u_d, d_n_ud, n_ud_max, u_new, x_m, x_d,
-                                          rows_total, result, ws, L, s);
-        default:
-            return launch_merge<mc::TS16>(u_m, n_um, u_d, d_n_ud, n_ud_max, u_new, x_m, x_d,
-                                          rows_total, result, ws, L, s);
+        case MC_U32: return launch_merge<mc::TU32>(C, L.merge_tiles, s);
+        case MC_U64: return launch_merge<mc::TU64>(C, L.merge_tiles, s);
+        default: return launch_merge<mc::TS16>(C, L.merge_tiles, s);
     }
 }
 
@@ -531,12 +789,28 @@ int mc_reencode(mc_ctx *ctx, const uint64_t *main_codes, uint64_t n_main, uint32
     if ((n_main > 0 && (!main_codes || !x_m)) || (n_delta > 0 && (!drank || !x_d)))
         return fail(MC_E_ARG, "null buffer");
     if (n_main + n_delta > 0 && !out) return fail(MC_E_ARG, "null output");
-    if (!aligned16(main_codes) || !aligned16(out)) return fail(MC_E_ARG, "misaligned buffer");
+    if (!aligned16(main_codes) || !aligned16(out) || !aligned16(result))
+        return fail(MC_E_ARG, "misaligned buffer");
+    if (n_delta >= (1ull << 30)) return fail(MC_E_ARG, "n_delta must be < 2^30");
     if (n_um + n_delta > (1ull << 32)) return fail(MC_E_ARG, "dictionary too large");
+    if (n_main > 0 && n_um > (1ull << w)) return fail(MC_E_ARG, "n_um larger than 2^w");
     if (out_cap_words < codes_words_bound(n_main + n_delta, n_um + n_delta))
         return fail(MC_E_CAP, "output capacity below the bound");
-    return launch_repack(main_codes, n_main, w, x_m, n_um, drank, n_delta, x_d, result, out,
-                         out_cap_words, s);
+    mc::ColDesc C;
+    memset(&C, 0, sizeof(C));
+    C.w = w;
+    C.main_codes = main_codes;
+    C.n_main = n_main;
+    C.x_m = const_cast<uint32_t *>(x_m);
+    C.n_um = n_um;
+    C.drank = const_cast<uint32_t *>(drank);
+    C.nd = (uint32_t)n_delta;
+    C.x_d = const_cast<uint32_t *>(x_d);
+    C.result = result;
+    C.err = &result->error;
+    C.out = out;
+    C.out_cap = out_cap_words;
+    return launch_repack(C, s);
 }
 
 int mc_ctx_set_timing(mc_ctx *ctx, int enable) {
@@ -585,33 +859,10 @@ int mc_copy_bytes(mc_ctx *ctx, const void *src, void *dst, uint64_t bytes, hipSt
 
 int mc_merge_batched_bounds(const mc_column_in *ins, uint32_t ncols, uint64_t *scratch_bytes) {
     if (!ins && ncols) return fail(MC_E_ARG, "null descriptors");
-    uint64_t total = 0;
-    for (uint32_t i = 0; i < ncols; i++) {
-        uint64_t sb = 0;
-        int rc = mc_merge_bounds(&ins[i], nullptr, nullptr, &sb);
-        if (rc) return rc;
-        total += align_up(sb, 256);
-    }
-    if (scratch_bytes) *scratch_bytes = total;
-    return MC_OK;
-}
-
-static int enqueue_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
-                           uint32_t ncols, char *ws, hipStream_t s) {
-    uint64_t off = 0;
-    const int timing = ctx->timing;  // per-column events are not recorded here
-    ctx->timing = 0;
-    for (uint32_t i = 0; i < ncols; i++) {
-        uint64_t sb = 0;
-        int rc = mc_merge_bounds(&ins[i], nullptr, nullptr, &sb);
-        if (rc == MC_OK) rc = merge_column_impl(ctx, &ins[i], &outs[i], ws + off, sb, s);
-        if (rc) {
-            ctx->timing = timing;
-            return rc;
-        }
-        off += align_up(sb, 256);
-    }
-    ctx->timing = timing;
+    BatchPlan P;
+    int rc = plan_batch(ins, ncols, P);
+    if (rc) return rc;
+    if (scratch_bytes) *scratch_bytes = P.total;
     return MC_OK;
 }
 
@@ -619,18 +870,41 @@ int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_colu
                              uint32_t ncols, void *scratch, uint64_t scratch_bytes,
                              hipStream_t stream, mc_graph **graph) {
     if (!ctx) return fail(MC_E_ARG, "null context");
-    if (ncols && (!ins || !outs)) return fail(MC_E_ARG, "null descriptors");
-    uint64_t need = 0;
-    int rc = mc_merge_batched_bounds(ins, ncols, &need);
+    if (ncols == 0) return MC_OK;
+    if (!ins || !outs) return fail(MC_E_ARG, "null descriptors");
+    BatchPlan P;
+    int rc = plan_batch(ins, ncols, P);
     if (rc) return rc;
     for (uint32_t i = 0; i < ncols; i++) {
         rc = check_out(&ins[i], &outs[i]);
         if (rc) return rc;
     }
-    if (!scratch || scratch_bytes < need) return fail(MC_E_CAP, "scratch below the batched bound");
+    if (!scratch || scratch_bytes < P.total) return fail(MC_E_CAP, "scratch below the batched bound");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
     char *ws = static_cast<char *>(scratch);
-    if (!graph) return enqueue_batched(ctx, ins, outs, ncols, ws, stream);
+
+    // descriptors + maps, staged in the context's pinned buffer and copied on
+    // the stream (the previous batch's copy must have left the buffer)
+    const uint64_t meta = P.total - P.desc_off;
+    if (ctx->meta_event) MC_HIP(hipEventSynchronize(ctx->meta_event));
+    if (ctx->meta_cap < meta) {
+        if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
+        ctx->meta_host = nullptr;
+        ctx->meta_cap = 0;
+        MC_HIP(hipHostMalloc(&ctx->meta_host, meta, hipHostMallocDefault));
+        ctx->meta_cap = meta;
+    }
+    if (!ctx->meta_event) MC_HIP(hipEventCreateWithFlags(&ctx->meta_event, hipEventDisableTiming));
+    char *h = static_cast<char *>(ctx->meta_host);
+    memset(h, 0, meta);
+    mc::ColDesc *hd = reinterpret_cast<mc::ColDesc *>(h);
+    for (uint32_t i = 0; i < ncols; i++)
+        hd[i] = make_desc(&ins[i], &outs[i], ws + P.z_off[i], ws + P.z_total + P.b_off[i], P.L[i]);
+    memcpy(h + (P.map_off - P.desc_off), P.maps.data(), P.maps.size() * 4);
+    MC_HIP(hipMemcpyAsync(ws + P.desc_off, h, meta, hipMemcpyHostToDevice, stream));
+    MC_HIP(hipEventRecord(ctx->meta_event, stream));
+
+    if (!graph) return enqueue_batch(P, ncols, ws, stream);
 
     mc_graph *g = new (std::nothrow) mc_graph();
     if (!g) return fail(MC_E_NOMEM, "graph allocation failed");
@@ -642,7 +916,7 @@ int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_colu
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        rc = enqueue_batched(ctx, ins, outs, ncols, ws, cs);
+        rc = enqueue_batch(P, ncols, ws, cs);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &gr);
         if (rc == MC_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");

@@ -197,6 +197,48 @@ __device__ inline uint64_t lookback_wave(uint64_t *status, uint32_t tile, uint64
     return prefix;
 }
 
+// ---------------------------------------------------------------------------
+// Everything one column's merge reads and writes.  The single-column entry
+// points pass it by value as a kernel argument; the batched entry point keeps
+// an array of them in device memory and maps every workgroup of a launch to
+// (column, tile).
+// ---------------------------------------------------------------------------
+struct ColDesc {
+    int32_t type;              // mc_type
+    uint32_t w;                // input code width
+    const void *u_m;           // U_M
+    uint64_t n_um;
+    const uint64_t *main_codes;
+    uint64_t n_main;
+    const void *delta;         // D (append order)
+    uint32_t nd;               // N_D
+    uint32_t sort_tiles;       // ceil(N_D / sort tile)
+    void *u_new;               // U' (capacity u_new_cap)
+    uint64_t u_new_cap;
+    uint64_t *out;             // packed result codes (capacity out_cap words)
+    uint64_t out_cap;
+    uint32_t *x_m;             // X_M (may be null when only Step 1(a) runs)
+    uint32_t *x_d;             // X_D
+    mc_result *result;         // device result scalars
+    uint32_t *err;             // error word (result->error or a scratch word)
+    uint64_t rows_total;       // N_M + N_D
+    // workspace
+    void *keys0, *keys1;       // radix ping-pong values
+    uint32_t *vals0, *vals1;   // radix ping-pong rows
+    uint32_t *gh;              // [passes][256] digit histograms (zeroed)
+    uint32_t *base;            // [passes][256] digit offsets
+    uint32_t *trivial;         // [passes] single-digit flags (zeroed)
+    uint32_t *tcount;          // [256][sort_tiles] tile counts / offsets
+    uint32_t *counters;        // [0] emit tile counter, [1] merge tile counter (zeroed)
+    uint64_t *emit_status;     // emit prefix words (zeroed)
+    uint64_t *merge_status;    // merge prefix words (zeroed)
+    uint64_t *n_ud;            // |U_D| as written by Step 1(a) (zeroed)
+    const uint64_t *n_ud_in;   // |U_D| as read by Step 1(b)
+    uint64_t nd_max;           // capacity of u_d, drank, x_d
+    void *u_d;                 // U_D
+    uint32_t *drank;           // index in U_D of every delta row
+};
+
 // Code width for a dictionary of n entries: ceil(log2 n), at least 1.
 __device__ __host__ inline uint32_t code_width(uint64_t n) {
     uint32_t w = 1;

@@ -22,24 +22,17 @@
 
 namespace mc {
 
-struct MergeJob {
-    const void *u_m;
-    uint64_t n_um;
-    const void *u_d;
-    const uint64_t *d_n_ud;  // |U_D| (device scalar)
-    uint64_t n_ud_max;       // capacity of u_d and x_d
-    void *u_new;
-    uint32_t *x_m;
-    uint32_t *x_d;
-    uint64_t rows_total;     // N_M + N_D, for the result word count
-    mc_result *result;
-    uint64_t *status;        // per-tile prefix words (zeroed)
-    uint32_t *counter;       // tile counter (zeroed)
-    uint32_t *err;
-};
-
 constexpr int kMergeItems = 8;
 constexpr int kMergeTile = kBlock * kMergeItems;
+
+template <class T>
+struct MergeSmem {
+    typename T::N a[kMergeTile + 1];  // a[0] = U_M[i0 - 1] (predecessor)
+    typename T::N b[kMergeTile];
+    uint32_t tile;
+    uint32_t tmp[kWaves];
+    uint64_t i0, i1, prefix;
+};
 
 // Number of U_M entries among the first k merged elements (ties: U_M first).
 template <class T, class GetA, class GetB>
@@ -57,56 +50,50 @@ __device__ __forceinline__ uint64_t co_rank(uint64_t k, uint64_t a, uint64_t b, 
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_merge(MergeJob J) {
-    typedef typename T::N N;
-    __shared__ N s_a[kMergeTile + 1];  // s_a[0] = U_M[i0 - 1] (predecessor)
-    __shared__ N s_b[kMergeTile];
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_i0, s_i1, s_prefix;
-    __shared__ uint32_t s_tmp[kWaves];
-
-    if (threadIdx.x == 0) s_tile = atomicAdd(J.counter, 1u);
+__device__ void merge_tile(const ColDesc &C, char *smem) {
+    MergeSmem<T> &S = *reinterpret_cast<MergeSmem<T> *>(smem);
+    if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[1], 1u);
     __syncthreads();
-    const uint32_t t = s_tile;
-    const uint64_t a = J.n_um;
-    const uint64_t b = min(*J.d_n_ud, J.n_ud_max);  // never read past U_D's buffer
-    const uint64_t cap = a + J.n_ud_max;             // U' capacity
+    const uint32_t t = S.tile;
+    const uint64_t a = C.n_um;
+    const uint64_t b = min(*C.n_ud_in, C.nd_max);  // never read past U_D's buffer
+    const uint64_t cap = C.u_new_cap;
     const uint64_t total = a + b;
     const uint64_t k0 = (uint64_t)t * kMergeTile;
     if (k0 >= total) {
         if (t == 0 && threadIdx.x == 0) {  // nothing to merge at all
-            J.result->new_dict_len = 0;
-            J.result->new_bitwidth = 1;
-            J.result->new_codes_words = (J.rows_total + 63) / 64;
-            J.result->delta_dict_len = b;
+            C.result->new_dict_len = 0;
+            C.result->new_bitwidth = 1;
+            C.result->new_codes_words = (C.rows_total + 63) / 64;
+            C.result->delta_dict_len = b;
         }
         return;
     }
     const uint64_t k1 = min(k0 + kMergeTile, total);
-    auto gA = [&](uint64_t i) { return T::norm(T::load(J.u_m, i)); };
-    auto gB = [&](uint64_t j) { return T::norm(T::load(J.u_d, j)); };
-    if (threadIdx.x == 0) s_i0 = co_rank<T>(k0, a, b, gA, gB);
-    if (threadIdx.x == 64) s_i1 = co_rank<T>(k1, a, b, gA, gB);
+    auto gA = [&](uint64_t i) { return T::norm(T::load(C.u_m, i)); };
+    auto gB = [&](uint64_t j) { return T::norm(T::load(C.u_d, j)); };
+    if (threadIdx.x == 0) S.i0 = co_rank<T>(k0, a, b, gA, gB);
+    if (threadIdx.x == 64) S.i1 = co_rank<T>(k1, a, b, gA, gB);
     __syncthreads();
-    const uint64_t i0 = s_i0, i1 = s_i1;
+    const uint64_t i0 = S.i0, i1 = S.i1;
     const uint64_t j0 = k0 - i0, j1 = k1 - i1;
     const uint32_t na = (uint32_t)(i1 - i0), nb = (uint32_t)(j1 - j0);
     for (uint32_t x = threadIdx.x; x <= na; x += kBlock) {
         if (x == 0) {
-            if (i0 > 0) s_a[0] = gA(i0 - 1);
+            if (i0 > 0) S.a[0] = gA(i0 - 1);
         } else {
-            s_a[x] = gA(i0 + x - 1);
+            S.a[x] = gA(i0 + x - 1);
         }
     }
-    for (uint32_t x = threadIdx.x; x < nb; x += kBlock) s_b[x] = gB(j0 + x);
+    for (uint32_t x = threadIdx.x; x < nb; x += kBlock) S.b[x] = gB(j0 + x);
     __syncthreads();
 
     // this thread's slice of the tile's merged range
     const uint32_t len = (uint32_t)(k1 - k0);
     const uint32_t d0 = min<uint32_t>(threadIdx.x * kMergeItems, len);
     const uint32_t d1 = min<uint32_t>(d0 + kMergeItems, len);
-    auto lA = [&](uint64_t i) { return s_a[i + 1]; };
-    auto lB = [&](uint64_t j) { return s_b[j]; };
+    auto lA = [&](uint64_t i) { return S.a[i + 1]; };
+    auto lB = [&](uint64_t j) { return S.b[j]; };
     const uint32_t ia0 = (uint32_t)co_rank<T>(d0, na, nb, lA, lB);
     const uint32_t jb0 = d0 - ia0;
 
@@ -115,43 +102,43 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeJob J) {
     {
         uint32_t ia = ia0, jb = jb0;
         for (uint32_t d = d0; d < d1; d++) {
-            const bool take_a = jb >= nb || (ia < na && T::le(s_a[ia + 1], s_b[jb]));
+            const bool take_a = jb >= nb || (ia < na && T::le(S.a[ia + 1], S.b[jb]));
             if (take_a) {
                 cnt++;
                 ia++;
             } else {
-                const bool dup = (i0 + ia > 0) && T::eq(s_a[ia], s_b[jb]);
+                const bool dup = (i0 + ia > 0) && T::eq(S.a[ia], S.b[jb]);
                 cnt += dup ? 0u : 1u;
                 jb++;
             }
         }
     }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(cnt, s_tmp, &tot);
+    const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);
     if (wave_id() == 0) {
-        const uint64_t pre = lookback_wave(J.status, t, tot, J.err);
-        if (lane_id() == 0) s_prefix = pre;
+        const uint64_t pre = lookback_wave(C.merge_status, t, tot, C.err);
+        if (lane_id() == 0) S.prefix = pre;
     }
     __syncthreads();
 
     // pass 2: write U', X_M and X_D
-    uint64_t pos = s_prefix + ex;
+    uint64_t pos = S.prefix + ex;
     {
         uint32_t ia = ia0, jb = jb0;
         for (uint32_t d = d0; d < d1; d++) {
-            const bool take_a = jb >= nb || (ia < na && T::le(s_a[ia + 1], s_b[jb]));
+            const bool take_a = jb >= nb || (ia < na && T::le(S.a[ia + 1], S.b[jb]));
             if (take_a) {
-                if (pos < cap) T::store(J.u_new, pos, T::denorm(s_a[ia + 1]));
-                if (J.x_m) J.x_m[i0 + ia] = (uint32_t)pos;
+                if (pos < cap) T::store(C.u_new, pos, T::denorm(S.a[ia + 1]));
+                if (C.x_m) C.x_m[i0 + ia] = (uint32_t)pos;
                 pos++;
                 ia++;
             } else {
-                const bool dup = (i0 + ia > 0) && T::eq(s_a[ia], s_b[jb]);
+                const bool dup = (i0 + ia > 0) && T::eq(S.a[ia], S.b[jb]);
                 if (dup) {
-                    if (J.x_d) J.x_d[j0 + jb] = (uint32_t)(pos - 1);
+                    if (C.x_d) C.x_d[j0 + jb] = (uint32_t)(pos - 1);
                 } else {
-                    if (pos < cap) T::store(J.u_new, pos, T::denorm(s_b[jb]));
-                    if (J.x_d) J.x_d[j0 + jb] = (uint32_t)pos;
+                    if (pos < cap) T::store(C.u_new, pos, T::denorm(S.b[jb]));
+                    if (C.x_d) C.x_d[j0 + jb] = (uint32_t)pos;
                     pos++;
                 }
                 jb++;
@@ -159,12 +146,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeJob J) {
         }
     }
     if (threadIdx.x == 0 && k1 == total) {
-        const uint64_t n = s_prefix + tot;
+        const uint64_t n = S.prefix + tot;
         const uint32_t w = code_width(n);
-        J.result->new_dict_len = n;
-        J.result->new_bitwidth = w;
-        J.result->new_codes_words = (J.rows_total * w + 63) / 64;
-        J.result->delta_dict_len = b;
+        C.result->new_dict_len = n;
+        C.result->new_bitwidth = w;
+        C.result->new_codes_words = (C.rows_total * w + 63) / 64;
+        C.result->delta_dict_len = b;
     }
 }
 

@@ -17,52 +17,42 @@
 
 namespace mc {
 
-struct RepackJob {
-    const uint64_t *main_codes;
-    uint64_t n_main;
-    uint32_t w;
-    const uint32_t *x_m;
-    uint64_t n_um;
-    const uint32_t *drank;
-    uint64_t n_delta;
-    const uint32_t *x_d;
-    const mc_result *result;  // w' and |U_D| (device scalars)
-    uint64_t *out;
-    uint64_t out_cap_words;
-    uint32_t *err;
-};
-
 constexpr int kRepackCodes = 4096;               // rows per tile (64 groups of 64)
 constexpr int kRepackPer = kRepackCodes / kBlock;  // codes per thread
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
-    __shared__ __attribute__((aligned(16))) uint64_t s_in[64 * 32 + 2];
-    __shared__ uint32_t s_code[kRepackCodes];
+struct RepackSmem {
+    uint64_t in[64 * 32 + 2];
+    uint32_t code[kRepackCodes];
+};
 
-    const uint32_t w = J.w;
-    const uint32_t wn = J.result->new_bitwidth;
-    const uint64_t n_ud = J.result->delta_dict_len;
-    const uint64_t n_out = J.n_main + J.n_delta;
-    const uint64_t t = blockIdx.x;
+__device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
+    RepackSmem &S = *reinterpret_cast<RepackSmem *>(smem);
+    uint64_t *s_in = S.in;
+    uint32_t *s_code = S.code;
+
+    const uint32_t w = C.w;
+    const uint32_t wn = C.result->new_bitwidth;
+    const uint64_t n_ud = C.result->delta_dict_len;
+    const uint64_t n_out = C.n_main + C.nd;
     const uint64_t c0 = t * kRepackCodes;
     if (c0 >= n_out) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(kRepackCodes, n_out - c0);
 
     // stage the main words of this tile (streamed once: non-temporal, so the
     // translation tables keep the cache)
-    if (c0 < J.n_main) {
-        const uint64_t win = (J.n_main * w + 63) / 64;  // readable input words
+    if (c0 < C.n_main) {
+        const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
         const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 64
         const uint32_t nw = (uint32_t)min<uint64_t>(64ull * w, win - wbase);
         const uint32_t npair = nw / 2;
-        const u64x2 *src2 = reinterpret_cast<const u64x2 *>(J.main_codes + wbase);
+        const u64x2 *src2 = reinterpret_cast<const u64x2 *>(C.main_codes + wbase);
         u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
         for (uint32_t x = threadIdx.x; x < npair; x += kBlock)
             dst2[x] = __builtin_nontemporal_load(src2 + x);
         if ((nw & 1u) && threadIdx.x == 0)
-            s_in[nw - 1] = __builtin_nontemporal_load(J.main_codes + wbase + nw - 1);
+            s_in[nw - 1] = __builtin_nontemporal_load(C.main_codes + wbase + nw - 1);
     }
     __syncthreads();
 
@@ -78,22 +68,22 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
         tab[j] = nullptr;
         idx[j] = 0;
         if (i < tn) {
-            if (g < J.n_main) {
+            if (g < C.n_main) {
                 const uint32_t bit = i * w;
                 const uint32_t wi = bit >> 6, sh = bit & 63u;
                 uint64_t v = s_in[wi] >> sh;
                 if (sh + w > 64) v |= s_in[wi + 1] << (64 - sh);
                 const uint32_t c = (uint32_t)(v & mask);
-                if (c < J.n_um) {
-                    tab[j] = J.x_m;
+                if (c < C.n_um) {
+                    tab[j] = C.x_m;
                     idx[j] = c;
                 } else {
                     bad |= MC_DEVERR_CODE_RANGE;
                 }
             } else {
-                const uint32_t r = J.drank[g - J.n_main];
+                const uint32_t r = C.drank[g - C.n_main];
                 if (r < n_ud) {
-                    tab[j] = J.x_d;
+                    tab[j] = C.x_d;
                     idx[j] = r;
                 } else {
                     bad |= MC_DEVERR_DELTA_RANGE;
@@ -106,13 +96,13 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
     for (int j = 0; j < kRepackPer; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
 #pragma unroll
     for (int j = 0; j < kRepackPer; j++) s_code[j * kBlock + threadIdx.x] = nc[j];
-    if (bad) flag_error(J.err, bad);
+    if (bad) flag_error(C.err, bad);
     __syncthreads();
 
     // assemble output words: local word k covers tile bits [64k, 64k + 64)
     const uint64_t obase = t * 64ull * wn;
     const uint64_t wres = (n_out * wn + 63) / 64;
-    const uint64_t wlim = min<uint64_t>(J.out_cap_words, (wres + 1) & ~1ull);
+    const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
     const uint32_t nwo = 64u * wn;  // words of a full tile (even)
     // floor(x / wn) for x < 2^17 as a multiply-high by ceil(2^32 / wn): the
     // rounding error of the reciprocal times x stays below 2^32, so it is exact
@@ -138,9 +128,9 @@ __global__ __launch_bounds__(kBlock) void k_repack(RepackJob J) {
             u64x2 v;
             v.x = word[0];
             v.y = word[1];
-            __builtin_nontemporal_store(v, reinterpret_cast<u64x2 *>(J.out + gw));
+            __builtin_nontemporal_store(v, reinterpret_cast<u64x2 *>(C.out + gw));
         } else if (gw < wlim) {
-            J.out[gw] = word[0];
+            C.out[gw] = word[0];
         }
     }
 }

@@ -99,3 +99,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _lib.load()
+
+
+def test_batched_bounds(lib):
+    ins = (_lib.McColumnIn * 3)(_in(), _in(type_=0, w=12, n_um=4000, n_main=10_000, nd=500),
+                                _in(type_=2, w=3, n_um=6, n_main=7, nd=5))
+    sb = ctypes.c_uint64()
+    assert lib.mc_merge_batched_bounds(ins, 3, ctypes.byref(sb)) == 0
+    per = sum(_bounds(lib, ins[i])[3] for i in range(3))
+    # every column's workspace plus the descriptor array and the tile maps
+    assert sb.value >= per
+    bad = (_lib.McColumnIn * 1)(_in(w=0))
+    assert lib.mc_merge_batched_bounds(bad, 1, ctypes.byref(sb)) == -1
