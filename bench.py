@@ -46,12 +46,66 @@ def reencode_bytes(col, n_new, w_new, n_ud):
             + 4 * col.u_m.shape[0] + 4 * n_ud)
 
 
+def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
+    """300 columns of mixed types and sizes: one batched launch sequence
+    replayed from a HIP graph, against one mc_merge_column call per column
+    on the same stream (plain, no graph)."""
+    import time as _t
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    rows = sum(c.n_main + c.n_delta for c in cols)
+    b_alg_in = sum(c.n_main * c.w / 8 + c.u_m.shape[0] * c.value_len + c.n_delta * c.value_len
+                   for c in cols)
+    outs, graph = cm.merge_columns_batched(dcols, graph=True, stream=stream, ctx=ctx)
+    torch.cuda.synchronize()
+    scal = [o.scalars() for o in outs]
+    assert all(s["error"] == 0 for s in scal)
+    b_alg = b_alg_in + sum(s["n_new"] * c.value_len + (c.n_main + c.n_delta) * s["w_new"] / 8
+                           for s, c in zip(scal, cols))
+    for _ in range(warmup):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    t_b = (_t.perf_counter() - t0) / steps
+
+    # plain: one call per column, reusing one scratch sized for the largest
+    scratch = cm.alloc_scratch(max(cm.merge_bounds(d)[2] for d in dcols))
+    pouts = [cm.alloc_output(d) for d in dcols]
+    for _ in range(warmup):
+        for d, o in zip(dcols, pouts):
+            cm.merge_column(d, out=o, scratch=scratch, stream=stream, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        for d, o in zip(dcols, pouts):
+            cm.merge_column(d, out=o, scratch=scratch, stream=stream, ctx=ctx)
+    torch.cuda.synchronize()
+    t_p = (_t.perf_counter() - t0) / steps
+    same = all(torch.equal(a.new_codes[: s["words"]], b.new_codes[: s["words"]])
+               for a, b, s in zip(outs, pouts, scal))
+    del graph, outs, pouts, scratch, dcols
+    torch.cuda.empty_cache()
+    return {"workload": "300 columns, rows log-uniform [1M, 20M], distinct log-uniform [2, 10M], "
+                        "u32/u64/str16, delta 1% of rows (half new values)",
+            "rows": rows, "bytes_alg": b_alg,
+            "batched_graph_ms": t_b * 1e3, "plain_ms": t_p * 1e3,
+            "batched_tuples_s": rows / t_b, "plain_tuples_s": rows / t_p,
+            "batched_gbs_alg": b_alg / t_b / 1e9, "plain_gbs_alg": b_alg / t_p / 1e9,
+            "speedup": t_p / t_b, "batched_equals_plain": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 300-column batched vs plain comparison")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes generating the 300-column workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -70,13 +124,19 @@ def main():
         from paper_1109_6885_amd import build as hipbuild
         hipbuild.build()
 
-    torch.cuda.set_device(0)
-    dev = torch.cuda.get_device_properties(0)
-    log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
-
+    # inputs first: the generator's worker processes start before the GPU is used
     t = time.time()
     col = gen.config_column(2)
     log(f"generated c2 in {time.time() - t:.1f}s")
+    bcols = None
+    if not args.no_batched:
+        t = time.time()
+        bcols = gen.batched_columns(300, workers=args.gen_workers)
+        log(f"generated the 300-column workload in {time.time() - t:.1f}s")
+
+    torch.cuda.set_device(0)
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
     dcol = cm.ColumnInput.from_numpy(col)
     out = cm.alloc_output(dcol, tables=False)
     _, _, sbytes = cm.merge_bounds(dcol)
@@ -124,6 +184,11 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 2 * copy_bytes * 5 / (e0.elapsed_time(e1) / 1000.0) / 1e9
     del src, dst
+
+    batched = None
+    if bcols is not None:
+        batched = bench_batched(cm, torch, bcols, args.steps, args.warmup, stream, ctx)
+        del bcols
 
     n_out = col.n_main + col.n_delta
     value = n_out / (ms_per_step / 1000.0)
@@ -173,6 +238,7 @@ def main():
         "copy_kernel_gbs": copy_gbs,
         "reencode_frac_of_copy": achieved / copy_gbs,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

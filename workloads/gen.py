@@ -48,11 +48,17 @@ class Column:
 # ---------------------------------------------------------------------------
 
 def _str_order(a: np.ndarray) -> np.ndarray:
-    """Argsort of 16-byte strings in unsigned byte order (big-endian halves)."""
+    """Argsort of 16-byte strings in unsigned byte order (big-endian halves).
+    Sorting by the high half alone is exact unless two strings share their
+    first 8 bytes; only then the two-key sort runs."""
     halves = np.ascontiguousarray(a, dtype=np.uint8).view(">u8").reshape(-1, 2)
     hi = halves[:, 0].astype(np.uint64)
-    lo = halves[:, 1].astype(np.uint64)
-    return np.lexsort((lo, hi))
+    order = np.argsort(hi, kind="stable")
+    hs = hi[order]
+    if hs.shape[0] > 1 and np.any(hs[1:] == hs[:-1]):
+        lo = halves[:, 1].astype(np.uint64)
+        return np.lexsort((lo, hi))
+    return order
 
 
 def _str_keys(a: np.ndarray):
@@ -277,14 +283,30 @@ def batched_shapes(ncols: int = 300, scale: float = 1.0, k: int = 4):
     return shapes
 
 
-def batched_columns(ncols: int = 300, scale: float = 1.0, k: int = 4):
+def _batched_one(shape):
+    vtype, rows, kd, sub = shape
+    rng = np.random.default_rng(sub)
+    n_delta = rows // 100
+    u64_high = 2 ** 64 if vtype == "u64" else 2 ** 63
+    return random_column(rng, vtype, kd, rows, n_delta, 0.5, u64_high=u64_high)
+
+
+def batched_columns(ncols: int = 300, scale: float = 1.0, k: int = 4, workers: int = 1):
     """Columns of the batched configuration: delta = 1% of main rows, half
-    drawn from the main dictionary and half new distinct values."""
-    cols = []
-    for vtype, rows, kd, sub in batched_shapes(ncols, scale, k):
-        rng = np.random.default_rng(sub)
-        n_delta = rows // 100
-        u64_high = 2 ** 64 if vtype == "u64" else 2 ** 63
-        cols.append(random_column(rng, vtype, kd, rows, n_delta, 0.5,
-                                  u64_high=u64_high))
-    return cols
+    drawn from the main dictionary and half new distinct values.  Every
+    column has its own seed, so `workers` > 1 (separate processes, started
+    fresh) gives the same columns faster."""
+    shapes = batched_shapes(ncols, scale, k)
+    if workers <= 1:
+        return [_batched_one(sh) for sh in shapes]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    # largest columns first, so the pool's tail is short
+    order = sorted(range(len(shapes)), key=lambda i: -shapes[i][1])
+    out = [None] * len(shapes)
+    with cf.ProcessPoolExecutor(max_workers=workers,
+                                mp_context=mp.get_context("spawn")) as ex:
+        futs = {ex.submit(_batched_one, shapes[i]): i for i in order}
+        for f in cf.as_completed(futs):
+            out[futs[f]] = f.result()
+    return out
