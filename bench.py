@@ -96,6 +96,116 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
             "speedup": t_p / t_b, "batched_equals_plain": bool(same)}
 
 
+def bench_serve(args):
+    """Served merge stream: 64 resident tables (10-200 columns each, column
+    shapes as in the batched workload) built in HBM, appends every 10 ms from
+    pinned pools on an append stream, merge requests arriving as a Poisson
+    process, admission under the memory budget.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6885_amd as cm
+    from paper_1109_6885_amd import serve
+    from workloads import gpu_gen
+
+    scale = args.serve_scale
+    torch.cuda.set_device(0)
+    t = time.time()
+    shapes = gpu_gen.served_shapes(64, scale)
+    ex = serve.GpuExecutor(n_streams=4)
+    budget = int(args.serve_budget_gb * 1e9)
+    srv = serve.Server(ex, budget_bytes=budget, max_inflight=4)
+    tick = 0.01
+    pools = {}
+    host_rng = np.random.default_rng(gpu_gen.BASE_SEED + 5)
+    ncols_total = 0
+    for tid, (seed, cols, rate) in enumerate(shapes):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        dcols = []
+        for vtype, rows, kd in cols:
+            vt, u, packed, n, w = gpu_gen.served_column(g, vtype, rows, kd)
+            dcols.append(cm.ColumnInput(vt, u, packed, n, w, None))
+        main = ex.make_main(dcols)
+        per_tick = max(1, int(round(rate * tick)))
+        srv.add_table(tid, main, delta_capacity=max(1024, per_tick * 64))
+        ncols_total += len(cols)
+        # four pinned batches per table, reused cyclically
+        by_type = {}
+        for c in dcols:
+            by_type.setdefault(c.vtype, 0)
+            by_type[c.vtype] += 1
+        pool = []
+        for _ in range(4):
+            vals = {}
+            for vt, k in by_type.items():
+                if vt == "u32":
+                    vals[vt] = host_rng.integers(0, 2 ** 32, (k, per_tick), dtype=np.uint64).astype(np.uint32)
+                elif vt == "u64":
+                    vals[vt] = host_rng.integers(0, 2 ** 63, (k, per_tick), dtype=np.uint64)
+                else:
+                    vals[vt] = host_rng.integers(0x20, 0x7F, (k, per_tick, 16), dtype=np.uint8)
+            pool.append(serve.append_batch(ex, main, vals, per_tick))
+        pools[tid] = pool
+    torch.cuda.synchronize()
+    resident0 = srv.resident_bytes()
+    log(f"served tables built in {time.time() - t:.1f}s: {ncols_total} columns, "
+        f"{resident0 / 1e9:.1f} GB resident, budget {budget / 1e9:.0f} GB")
+
+    # Poisson arrivals at 5/s over warmup + window, each naming a random table
+    arr_rng = np.random.default_rng(gpu_gen.BASE_SEED + 55)
+    horizon = args.serve_warmup + args.serve_seconds
+    arrivals, tt = [], 0.0
+    while True:
+        tt += arr_rng.exponential(1.0 / args.serve_rate)
+        if tt >= horizon:
+            break
+        arrivals.append((tt, int(arr_rng.integers(0, 64))))
+    srv.t0 = srv.clock()
+    t0 = srv.t0
+    next_tick, ticks, late_ticks, ai = t0, 0, 0, 0
+    reqs = []
+    while True:
+        now = srv.clock()
+        if now - t0 >= horizon:
+            break
+        if now >= next_tick:
+            for tid, pool in pools.items():
+                srv.append(tid, pool[ticks % 4])
+            ticks += 1
+            next_tick += tick
+            if srv.clock() > next_tick:
+                late_ticks += 1
+        while ai < len(arrivals) and arrivals[ai][0] <= now - t0:
+            reqs.append(srv.submit_merge(arrivals[ai][1]))
+            ai += 1
+        srv.poll()
+    t_end = srv.clock()
+    srv.drain(timeout=300)
+    torch.cuda.synchronize()
+    counted = [r for r in reqs if r.arrival - t0 >= args.serve_warmup and r.committed is not None]
+    lat = np.array([r.latency for r in counted]) if counted else np.zeros(0)
+    window = t_end - (t0 + args.serve_warmup)
+    st = srv.stats()
+    out = {
+        "metric": "served merge stream: p50/p99 merge latency and merged tuples/s",
+        "workload": f"64 tables, {ncols_total} columns (10-200 per table, batched column shapes "
+                    f"x{scale}), appends {sum(r for _, _, r in shapes):.3g} rows/s total in 10 ms "
+                    f"ticks, merges Poisson {args.serve_rate}/s on random tables",
+        "scale": scale, "budget_bytes": budget, "resident_bytes_start": resident0,
+        "window_s": window, "requests": len(reqs), "committed_in_window": len(counted),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+        "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+        "max_ms": float(lat.max() * 1e3) if lat.size else None,
+        "merged_tuples_s": sum(r.rows for r in counted) / window if window > 0 else None,
+        "appended_rows_s": st["appended_rows"] / (t_end - t0),
+        "admission_waits": st["admission_waits"], "backpressure": st["backpressure"],
+        "late_ticks": late_ticks, "ticks": ticks,
+        "peak_in_use_bytes": st["peak_in_use_bytes"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,13 +216,22 @@ def main():
                     help="skip the 300-column batched vs plain comparison")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating the 300-column workload")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the served merge stream instead and print its JSON line")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="row and append-rate scale of the served tables")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=5.0, help="merge requests per second")
     args = ap.parse_args()
-
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(columns are independent: a multi-GPU run would shard columns or row ranges, "
               "which is not built)", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return bench_serve(args)
 
     import numpy as np
     import torch

@@ -1,0 +1,431 @@
+"""Served merge stream: resident tables, delta appends, admitted merges.
+
+The merge of Section 3 runs online: it works on a copy, incoming updates go
+to a second delta during the merge, and the merged main is committed
+atomically, the second delta then becoming the primary one.  This module
+keeps that protocol for many tables at once on one GPU:
+
+* every table keeps its main partition (per column: dictionary and packed
+  codes) resident in HBM, plus two delta buffers (active and second);
+* appends go to the active delta (host-to-device copies on an append stream);
+* a merge request is admitted when the worst-case bytes of its outputs and
+  workspace (mc_merge_bounds; the old main stays alive until commit, so the
+  outputs are double-buffered) fit under the memory budget; requests that do
+  not fit wait in arrival order, and so do requests for a table that is
+  already merging;
+* at admission the active delta is frozen as the merge's snapshot and the
+  second delta becomes active, so appends continue during the merge;
+* admitted merges run on a pool of streams and overlap each other and the
+  appends (continuous batching: a request arriving while others run is
+  admitted as soon as memory and a stream are free);
+* commit swaps the table's main for the merge result, frees the old main and
+  clears the snapshot buffer, which becomes the next second delta;
+* latency = commit time - arrival time; p50/p99 and merged tuples/s are
+  reported.
+
+The Server logic talks to an executor (GpuExecutor here; the tests also use
+a CPU executor), so admission, snapshot and commit rules are checked without
+a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class MergeRequest:
+    table: int
+    arrival: float
+    admitted: float | None = None
+    committed: float | None = None
+    rows: int = 0               # merged tuples (all columns)
+    reserved: int = 0           # bytes held from admission to commit
+    status: str = "queued"      # queued | running | committed | cancelled
+    job: object = None
+    snapshot: object = None     # the frozen delta (executor object)
+
+    @property
+    def latency(self):
+        return None if self.committed is None else self.committed - self.arrival
+
+
+@dataclass
+class TableState:
+    main: object                # executor's resident main (all columns)
+    active: object              # delta receiving appends
+    second: object              # empty delta, becomes active at admission
+    merging: MergeRequest | None = None
+    merges: int = 0
+
+
+class Server:
+    """Admission, snapshot and commit for merges of resident tables."""
+
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 4, clock=None):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.clock = clock or time.perf_counter
+        self.tables: dict[int, TableState] = {}
+        self.queue: collections.deque[MergeRequest] = collections.deque()
+        self.running: list[MergeRequest] = []
+        self.done: list[MergeRequest] = []
+        self.reserved = 0
+        self.peak_in_use = 0
+        self.admission_waits = 0    # polls in which the head request could not be admitted
+        self.backpressure = 0       # appends refused because a delta was full
+        self.appended_rows = 0
+        self.t0 = self.clock()
+
+    # ---- tables and appends -------------------------------------------------
+
+    def add_table(self, tid: int, main, delta_capacity: int):
+        self.tables[tid] = TableState(main, self.ex.new_delta(main, delta_capacity),
+                                      self.ex.new_delta(main, delta_capacity))
+        self._note_use()
+
+    def append(self, tid: int, rows) -> bool:
+        """Append a batch (executor format) to the table's active delta,
+        growing it if the budget has room.  Returns False (back-pressure) if
+        the delta cannot take the rows."""
+        t = self.tables[tid]
+        n = self.ex.batch_rows(rows)
+        if not self.ex.append(t.active, rows, self.budget - self.in_use()):
+            self.backpressure += 1
+            return False
+        self.appended_rows += n
+        self._note_use()
+        return True
+
+    # ---- requests -----------------------------------------------------------
+
+    def submit_merge(self, tid: int) -> MergeRequest:
+        r = MergeRequest(tid, self.clock())
+        self.queue.append(r)
+        return r
+
+    def cancel(self, r: MergeRequest) -> bool:
+        """Cancel a request that has not been admitted (nothing changes)."""
+        if r.status == "queued" and r in self.queue:
+            self.queue.remove(r)
+            r.status = "cancelled"
+            return True
+        return False
+
+    def resident_bytes(self) -> int:
+        # while a table merges, its second buffer is the merge's snapshot
+        total = 0
+        for t in self.tables.values():
+            other = t.second if t.second is not None else t.merging.snapshot
+            total += (self.ex.main_bytes(t.main) + self.ex.delta_bytes(t.active)
+                      + self.ex.delta_bytes(other))
+        return total
+
+    def in_use(self) -> int:
+        return self.resident_bytes() + self.reserved
+
+    def _note_use(self):
+        self.peak_in_use = max(self.peak_in_use, self.in_use())
+
+    # ---- progress -----------------------------------------------------------
+
+    def poll(self) -> int:
+        """Commit finished merges, then admit what fits.  Returns the number
+        of commits."""
+        commits = 0
+        still = []
+        for r in self.running:
+            if self.ex.finished(r.job):
+                self._commit(r)
+                commits += 1
+            else:
+                still.append(r)
+        self.running = still
+        self._admit()
+        return commits
+
+    def _admit(self):
+        blocked_tables = set()
+        waited = False
+        for r in list(self.queue):
+            if len(self.running) >= self.max_inflight:
+                waited = True
+                break
+            t = self.tables[r.table]
+            if t.merging is not None or r.table in blocked_tables:
+                blocked_tables.add(r.table)     # one merge per table at a time
+                continue
+            need = self.ex.merge_bytes(t.main, t.active)
+            if self.in_use() + need > self.budget:
+                waited = True
+                break                           # arrival order: nothing overtakes
+            # freeze the active delta as the snapshot, appends go to the second
+            snap, t.active, t.second = t.active, t.second, None
+            r.snapshot = snap
+            r.reserved = need
+            self.reserved += need
+            r.rows = (self.ex.main_rows(t.main)
+                      + self.ex.delta_rows(snap) * self.ex.columns(t.main))
+            r.job = self.ex.launch(t.main, snap)
+            r.admitted = self.clock()
+            r.status = "running"
+            t.merging = r
+            self.queue.remove(r)
+            self.running.append(r)
+            self._note_use()
+        if waited:
+            self.admission_waits += 1
+
+    def _commit(self, r: MergeRequest):
+        t = self.tables[r.table]
+        new_main = self.ex.result(r.job)
+        old = t.main
+        t.main = new_main                       # atomic swap of the table's main
+        self.ex.free_main(old)
+        self.ex.clear_delta(r.snapshot)
+        t.second = r.snapshot                   # the emptied snapshot is the next second delta
+        t.merging = None
+        t.merges += 1
+        self.reserved -= r.reserved
+        r.committed = self.clock()
+        r.status = "committed"
+        r.job = None
+        self.done.append(r)
+        self._note_use()
+
+    def drain(self, timeout: float = 600.0):
+        end = self.clock() + timeout
+        while (self.queue or self.running) and self.clock() < end:
+            if not self.poll():
+                self.ex.idle()
+
+    # ---- statistics ------------------------------------------------------------
+
+    def stats(self) -> dict:
+        lat = np.array([r.latency for r in self.done], dtype=np.float64)
+        wall = self.clock() - self.t0
+        rows = sum(r.rows for r in self.done)
+        return {
+            "merges": len(self.done),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "max_ms": float(lat.max() * 1e3) if lat.size else None,
+            "tuples_s": rows / wall if wall > 0 else None,
+            "merged_rows": rows,
+            "appended_rows": self.appended_rows,
+            "admission_waits": self.admission_waits,
+            "backpressure": self.backpressure,
+            "peak_in_use_bytes": self.peak_in_use,
+            "budget_bytes": self.budget,
+            "wall_s": wall,
+        }
+
+
+# ---------------------------------------------------------------------------
+# GPU executor: tables resident in HBM, merges through the C ABI
+# ---------------------------------------------------------------------------
+
+@dataclass
+class GpuMain:
+    cols: list                   # per column: ColumnInput (u_m, codes, n_main, w, delta unused)
+    nbytes: int = 0
+
+
+@dataclass
+class GpuDelta:
+    groups: dict                 # vtype -> device tensor (n_cols_of_type, cap[, 16])
+    index: list                  # per column: (vtype, row in its group)
+    cap: int
+    rows: int = 0
+    nbytes: int = 0
+    fence: object = None         # event after the last append copy
+    init_cap: int = 0
+    row_bytes: int = 0           # bytes of one row over all columns
+
+
+class GpuExecutor:
+    """Resident tables on one GPU.  Appends are host-to-device copies on an
+    append stream; each admitted merge is one batched launch sequence over the
+    table's columns on the next stream of a pool; commit reads the result
+    scalars once per merge."""
+
+    def __init__(self, n_streams: int = 4, device: int = 0):
+        import torch
+        import paper_1109_6885_amd as cm
+        self.torch, self.cm = torch, cm
+        self.device = device
+        self.append_stream = torch.cuda.Stream(device=device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.next = 0
+        self.ctx = cm.context(device)
+
+    # mains
+    def make_main(self, cols) -> GpuMain:
+        nb = sum(c.u_m.numel() * c.u_m.element_size() + c.main_codes.numel() * 8 for c in cols)
+        return GpuMain(cols, nb)
+
+    def main_bytes(self, m): return m.nbytes
+    def main_rows(self, m): return sum(c.n_main for c in m.cols)
+    def columns(self, m): return len(m.cols)
+    def free_main(self, m): m.cols = []
+
+    # deltas
+    def _alloc_groups(self, counts, cap):
+        torch = self.torch
+        groups, nb = {}, 0
+        for vt, n in counts.items():
+            shape = (n, cap, 16) if vt == "str16" else (n, cap)
+            dt = {"u32": torch.int32, "u64": torch.int64, "str16": torch.uint8}[vt]
+            groups[vt] = torch.empty(shape, dtype=dt, device=f"cuda:{self.device}")
+            nb += groups[vt].numel() * groups[vt].element_size()
+        return groups, nb
+
+    def new_delta(self, m: GpuMain, cap: int) -> GpuDelta:
+        counts = collections.Counter(c.vtype for c in m.cols)
+        groups, nb = self._alloc_groups(counts, cap)
+        index, seen = [], collections.Counter()
+        for c in m.cols:
+            index.append((c.vtype, seen[c.vtype]))
+            seen[c.vtype] += 1
+        row_bytes = sum(self.cm.VALUE_LEN[c.vtype] for c in m.cols)
+        return GpuDelta(groups, index, cap, 0, nb, None, cap, row_bytes)
+
+    def delta_rows(self, d): return d.rows
+    def delta_capacity(self, d): return d.cap
+    def delta_bytes(self, d): return d.nbytes
+    def batch_rows(self, rows): return rows["n"]
+
+    def append(self, d: GpuDelta, rows, room: int) -> bool:
+        """rows: {"n": r, vtype: pinned host tensor (n_cols_of_type, r[, 16])}.
+        Doubles the delta's capacity when needed, if `room` bytes allow."""
+        n = rows["n"]
+        torch = self.torch
+        with torch.cuda.stream(self.append_stream):
+            if d.rows + n > d.cap:
+                new_cap = max(2 * d.cap, d.rows + n)
+                if (new_cap - d.cap) * d.row_bytes > room:
+                    return False
+                counts = {vt: g.shape[0] for vt, g in d.groups.items()}
+                groups, nb = self._alloc_groups(counts, new_cap)
+                for vt, g in d.groups.items():
+                    groups[vt][:, :d.rows].copy_(g[:, :d.rows], non_blocking=True)
+                    g.record_stream(self.append_stream)
+                d.groups, d.cap, d.nbytes = groups, new_cap, nb
+            for vt, g in d.groups.items():
+                g[:, d.rows:d.rows + n].copy_(rows[vt], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.append_stream)
+        d.fence = ev
+        d.rows += n
+        return True
+
+    def clear_delta(self, d: GpuDelta):
+        """Empty the delta; a grown buffer shrinks back to its first size."""
+        d.rows = 0
+        if d.cap > d.init_cap:
+            for g in d.groups.values():
+                g.record_stream(self.append_stream)
+            counts = {vt: g.shape[0] for vt, g in d.groups.items()}
+            d.groups, d.nbytes = self._alloc_groups(counts, d.init_cap)
+            d.cap = d.init_cap
+        d.fence = None
+
+    def _inputs(self, m: GpuMain, d: GpuDelta):
+        out = []
+        for c, (vt, i) in zip(m.cols, d.index):
+            delta = d.groups[vt][i, :d.rows]
+            out.append(self.cm.ColumnInput(c.vtype, c.u_m, c.main_codes, c.n_main, c.w, delta))
+        return out
+
+    def merge_bytes(self, m: GpuMain, d: GpuDelta) -> int:
+        """Worst-case output bytes (U' and codes of every column, from
+        mc_merge_bounds) plus the batched workspace.  Cached per delta size:
+        the admission check repeats while a request waits."""
+        key = (id(m), d.rows)
+        if getattr(m, "_need_key", None) == key:
+            return m._need
+        total = 0
+        cols = self._inputs(m, d)
+        for col in cols:
+            dict_cap, words, _ = self.cm.merge_bounds(col)
+            total += dict_cap * self.cm.VALUE_LEN[col.vtype] + max(words, 2) * 8 + 64
+        total += self.cm.batched_bounds(cols)
+        m._need_key, m._need = key, total
+        return total
+
+    def launch(self, m: GpuMain, d: GpuDelta):
+        torch, cm = self.torch, self.cm
+        s = self.streams[self.next % len(self.streams)]
+        self.next += 1
+        cols = self._inputs(m, d)
+        with torch.cuda.stream(s):
+            if d.fence is not None:
+                s.wait_event(d.fence)          # the snapshot's appends have landed
+            res = torch.zeros(len(cols) * cm.RESULT_BYTES, dtype=torch.uint8,
+                              device=f"cuda:{self.device}")
+            outs = []
+            for j, col in enumerate(cols):
+                dict_cap, words, _ = cm.merge_bounds(col)
+                outs.append(cm.MergeOutput(
+                    col.vtype, cm.value_tensor_empty(col.vtype, dict_cap),
+                    torch.empty(max(words, 2), dtype=torch.int64, device=f"cuda:{self.device}"),
+                    None, None, res[j * cm.RESULT_BYTES:(j + 1) * cm.RESULT_BYTES],
+                    col.n_main + int(col.delta.shape[0])))
+            scratch = cm.alloc_scratch(cm.batched_bounds(cols))
+            cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s, ctx=self.ctx)
+            done = torch.cuda.Event()
+            done.record(s)
+        return {"cols": cols, "outs": outs, "res": res, "scratch": scratch, "done": done,
+                "stream": s}
+
+    def finished(self, job) -> bool:
+        return job["done"].query()
+
+    def result(self, job) -> GpuMain:
+        cm = self.cm
+        raw = job["res"].cpu().numpy()
+        new_cols = []
+        for j, (col, out) in enumerate(zip(job["cols"], job["outs"])):
+            r = cm.McResult.from_buffer_copy(raw[j * cm.RESULT_BYTES:(j + 1) * cm.RESULT_BYTES].tobytes())
+            if r.error:
+                raise RuntimeError(f"merge of column {j} reported device error {r.error}")
+            rows = col.n_main + int(col.delta.shape[0])
+            new_cols.append(cm.ColumnInput(col.vtype, out.new_dict[: r.new_dict_len],
+                                           out.new_codes, rows, int(r.new_bitwidth), None))
+        job["scratch"] = None
+        return self.make_main(new_cols)
+
+    def idle(self):
+        time.sleep(0.0002)
+
+
+# ---------------------------------------------------------------------------
+# Helpers for building resident tables and append batches
+# ---------------------------------------------------------------------------
+
+def gpu_main_from_columns(ex: GpuExecutor, cols) -> GpuMain:
+    """Resident main from host columns (workloads.Column, delta ignored)."""
+    cm = ex.cm
+    dcols = [cm.ColumnInput(c.vtype, cm.to_device(c.u_m), cm.to_device(c.main_packed), c.n_main,
+                            c.w, None) for c in cols]
+    return ex.make_main(dcols)
+
+
+def append_batch(ex: GpuExecutor, main: GpuMain, values_by_type: dict, n: int) -> dict:
+    """An append batch of n rows for every column of `main`: values_by_type
+    maps a value type to a host array (columns of that type, n[, 16]), which
+    is copied into pinned memory once."""
+    torch = ex.torch
+    out = {"n": n}
+    for vt, arr in values_by_type.items():
+        a = np.ascontiguousarray(arr)
+        if a.dtype == np.uint32:
+            a = a.view(np.int32)
+        elif a.dtype == np.uint64:
+            a = a.view(np.int64)
+        out[vt] = torch.from_numpy(a).pin_memory()
+    return out

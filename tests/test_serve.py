@@ -1,0 +1,246 @@
+"""Serving logic without a GPU: the Server's admission, snapshot (second
+delta), commit and statistics rules, driven through a CPU executor whose
+merges are the oracle's and which finishes a merge only after a set number
+of polls (so merges are in flight while appends and requests arrive)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1109_6885_amd.serve import Server
+from workloads import gen
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 0.001
+        return self.t
+
+
+class CpuMain:
+    def __init__(self, cols):
+        self.cols = cols  # list of dict(vtype, u_m, codes, n_main, w)
+
+
+class CpuDelta:
+    def __init__(self, ncols, cap):
+        self.vals = [[] for _ in range(ncols)]
+        self.cap = cap
+        self.rows = 0
+
+
+class CpuExecutor:
+    def __init__(self, polls_to_finish=3):
+        self.k = polls_to_finish
+        self.launched = []
+
+    def main_bytes(self, m):
+        return sum(c["u_m"].nbytes + c["codes"].nbytes for c in m.cols)
+
+    def main_rows(self, m):
+        return sum(c["n_main"] for c in m.cols)
+
+    def columns(self, m):
+        return len(m.cols)
+
+    def free_main(self, m):
+        m.cols = []
+
+    def new_delta(self, m, cap):
+        return CpuDelta(len(m.cols), cap)
+
+    def delta_rows(self, d):
+        return d.rows
+
+    def delta_capacity(self, d):
+        return d.cap
+
+    def delta_bytes(self, d):
+        return d.cap * 16 * len(d.vals)
+
+    def batch_rows(self, rows):
+        return rows["n"]
+
+    def append(self, d, rows, room):
+        # fixed capacity here: a full delta refuses rows (back-pressure)
+        if d.rows + rows["n"] > d.cap:
+            return False
+        for j, v in enumerate(rows["cols"]):
+            d.vals[j].extend(list(v))
+        d.rows += rows["n"]
+        return True
+
+    def clear_delta(self, d):
+        d.vals = [[] for _ in d.vals]
+        d.rows = 0
+
+    def merge_bytes(self, m, d):
+        return sum((c["u_m"].shape[0] + d.rows) * 16 + (c["n_main"] + d.rows) * 4 + 4096
+                   for c in m.cols)
+
+    def launch(self, m, d):
+        job = {"m": m, "snap": [list(v) for v in d.vals], "polls": 0}
+        self.launched.append(job)
+        return job
+
+    def finished(self, job):
+        job["polls"] += 1
+        return job["polls"] >= self.k
+
+    def result(self, job):
+        cols = []
+        for c, vals in zip(job["m"].cols, job["snap"]):
+            vt = c["vtype"]
+            delta = (np.array(vals, np.uint8).reshape(-1, 16) if vt == "str16"
+                     else np.array(vals, dtype=np.uint32 if vt == "u32" else np.uint64))
+            r = oracle.merge_column(vt, c["u_m"], c["codes"], c["n_main"], c["w"], delta)
+            cols.append({"vtype": vt, "u_m": r["u_new"], "codes": r["codes"],
+                         "n_main": c["n_main"] + len(vals), "w": r["w_new"]})
+        return CpuMain(cols)
+
+    def idle(self):
+        pass
+
+
+def decode(c):
+    codes = [oracle.unpack(c["codes"], i, c["w"]) for i in range(c["n_main"])]
+    return [c["u_m"][k].tobytes() if c["vtype"] == "str16" else int(c["u_m"][k]) for k in codes]
+
+
+def make_table(rng, ncols=3, rows=200):
+    cols = []
+    for j in range(ncols):
+        vt = ("u32", "u64", "str16")[j % 3]
+        col = gen.random_column(rng, vt, 20, rows, 0)
+        cols.append({"vtype": vt, "u_m": col.u_m, "codes": col.main_packed, "n_main": rows,
+                     "w": col.w})
+    return CpuMain(cols)
+
+
+def batch(rng, m, n):
+    vals = []
+    for c in m.cols:
+        vals.append(list(gen.random_values(rng, c["vtype"], n)))
+    return {"n": n, "cols": vals}
+
+
+def test_snapshot_second_delta_and_commit():
+    rng = np.random.default_rng(0)
+    ex = CpuExecutor(polls_to_finish=4)
+    s = Server(ex, budget_bytes=10 ** 9, clock=FakeClock())
+    m = make_table(rng)
+    expected = [decode(c) for c in m.cols]
+    s.add_table(0, m, delta_capacity=1000)
+    b1 = batch(rng, m, 50)
+    assert s.append(0, b1)
+    r1 = s.submit_merge(0)
+    s.poll()
+    assert r1.status == "running"
+    # appends during the merge go to the second delta, not the snapshot
+    b2 = batch(rng, m, 30)
+    assert s.append(0, b2)
+    assert len(ex.launched[0]["snap"][0]) == 50
+    r2 = s.submit_merge(0)          # waits: one merge per table
+    s.poll()
+    assert r2.status == "queued"
+    s.drain()
+    assert r1.status == r2.status == "committed"
+    assert r1.committed <= r2.admitted
+    final = s.tables[0].main
+    for j, c in enumerate(final.cols):
+        vt = c["vtype"]
+        add = [(bytes(np.asarray(v, np.uint8)) if vt == "str16" else int(v))
+               for v in b1["cols"][j] + b2["cols"][j]]
+        assert decode(c) == expected[j] + add
+    st = s.stats()
+    assert st["merges"] == 2 and st["p50_ms"] is not None and st["merged_rows"] == 3 * (250 + 280)
+
+
+def test_budget_never_exceeded_and_fifo():
+    rng = np.random.default_rng(1)
+    ex = CpuExecutor(polls_to_finish=5)
+    s = Server(ex, budget_bytes=10 ** 12, max_inflight=8, clock=FakeClock())
+    for t in range(4):
+        m = make_table(rng, 2, 100)
+        s.add_table(t, m, delta_capacity=1000)
+        s.append(t, batch(rng, m, 200))
+    needs = [ex.merge_bytes(s.tables[t].main, s.tables[t].active) for t in range(4)]
+    # room for the first two merges and half of the third
+    s.budget = s.in_use() + needs[0] + needs[1] + needs[2] // 2
+    reqs = [s.submit_merge(t) for t in range(4)]
+    s.poll()
+    assert [r.status for r in reqs] == ["running", "running", "queued", "queued"]
+    assert s.admission_waits == 1
+    peak = 0
+    while s.queue or s.running:
+        s.poll()
+        peak = max(peak, s.in_use())
+        assert s.in_use() <= s.budget
+        # nothing overtakes the head of the queue
+        if reqs[2].status == "queued":
+            assert reqs[3].status == "queued"
+    assert all(r.status == "committed" for r in reqs)
+    assert reqs[2].admitted >= min(reqs[0].committed, reqs[1].committed)
+    assert s.peak_in_use <= s.budget
+
+
+def test_many_tables_random_traffic_stays_in_budget():
+    rng = np.random.default_rng(11)
+    ex = CpuExecutor(polls_to_finish=4)
+    s = Server(ex, budget_bytes=10 ** 12, max_inflight=3, clock=FakeClock())
+    for t in range(5):
+        s.add_table(t, make_table(rng, 2, 60), delta_capacity=400)
+    s.budget = s.in_use() + 150_000
+    reqs = []
+    for step in range(80):
+        t = int(rng.integers(0, 5))
+        s.append(t, batch(rng, s.tables[t].main, 5))
+        if step % 4 == 0:
+            reqs.append(s.submit_merge(int(rng.integers(0, 5))))
+        s.poll()
+        assert s.in_use() <= s.budget
+    s.drain()
+    assert all(r.status == "committed" for r in reqs)
+    assert s.peak_in_use <= s.budget
+    st = s.stats()
+    assert st["merges"] == len(reqs) and st["p99_ms"] >= st["p50_ms"]
+
+
+def test_cancel_queued_request_changes_nothing():
+    rng = np.random.default_rng(2)
+    ex = CpuExecutor()
+    s = Server(ex, budget_bytes=10 ** 9, clock=FakeClock())
+    m = make_table(rng)
+    before = [decode(c) for c in m.cols]
+    s.add_table(0, m, 100)
+    s.append(0, batch(rng, m, 10))
+    r = s.submit_merge(0)
+    assert s.cancel(r) and r.status == "cancelled"
+    s.drain()
+    assert [decode(c) for c in s.tables[0].main.cols] == before
+    assert s.tables[0].active.rows == 10    # the delta keeps its rows
+
+
+def test_backpressure_when_delta_full():
+    rng = np.random.default_rng(3)
+    ex = CpuExecutor()
+    s = Server(ex, budget_bytes=10 ** 9, clock=FakeClock())
+    m = make_table(rng)
+    s.add_table(0, m, 40)
+    assert s.append(0, batch(rng, m, 30))
+    assert not s.append(0, batch(rng, m, 30))
+    assert s.stats()["backpressure"] == 1
+
+
+def test_request_larger_than_budget_waits_forever_without_overtaking():
+    rng = np.random.default_rng(4)
+    ex = CpuExecutor()
+    s = Server(ex, budget_bytes=1, clock=FakeClock())    # nothing fits
+    m = make_table(rng)
+    s.add_table(0, m, 10)
+    r = s.submit_merge(0)
+    for _ in range(5):
+        s.poll()
+    assert r.status == "queued" and s.admission_waits == 5
