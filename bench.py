@@ -147,6 +147,9 @@ def bench_serve(args):
                     vals[vt] = host_rng.integers(0x20, 0x7F, (k, per_tick, 16), dtype=np.uint8)
             pool.append(serve.append_batch(ex, main, vals, per_tick))
         pools[tid] = pool
+        if tid % 8 == 7:
+            torch.cuda.synchronize()
+            log(f"built {tid + 1} tables, {ncols_total} columns, {time.time() - t:.0f}s")
     torch.cuda.synchronize()
     resident0 = srv.resident_bytes()
     log(f"served tables built in {time.time() - t:.1f}s: {ncols_total} columns, "
@@ -164,6 +167,7 @@ def bench_serve(args):
     srv.t0 = srv.clock()
     t0 = srv.t0
     next_tick, ticks, late_ticks, ai = t0, 0, 0, 0
+    next_log = t0 + 1.0
     reqs = []
     while True:
         now = srv.clock()
@@ -180,8 +184,17 @@ def bench_serve(args):
             reqs.append(srv.submit_merge(arrivals[ai][1]))
             ai += 1
         srv.poll()
+        if now >= next_log:
+            next_log += 1.0
+            log(f"t={now - t0:.1f}s: {len(srv.done)} committed, {len(srv.queue)} queued, "
+                f"{len(srv.running)} running, {srv.in_use() / 1e9:.1f} GB in use, "
+                f"backpressure {srv.backpressure}")
     t_end = srv.clock()
-    srv.drain(timeout=300)
+    log(f"arrivals done: {len(reqs)} requests, {len(srv.done)} committed, "
+        f"{len(srv.queue)} queued, {len(srv.running)} running")
+    srv.drain(timeout=120, progress=lambda v: log(
+        f"draining: {len(v.queue)} queued, {len(v.running)} running, "
+        f"{v.in_use() / 1e9:.1f} GB in use"))
     torch.cuda.synchronize()
     counted = [r for r in reqs if r.arrival - t0 >= args.serve_warmup and r.committed is not None]
     lat = np.array([r.latency for r in counted]) if counted else np.zeros(0)
@@ -200,6 +213,7 @@ def bench_serve(args):
         "merged_tuples_s": sum(r.rows for r in counted) / window if window > 0 else None,
         "appended_rows_s": st["appended_rows"] / (t_end - t0),
         "admission_waits": st["admission_waits"], "backpressure": st["backpressure"],
+        "rejected": st["rejected"],
         "late_ticks": late_ticks, "ticks": ticks,
         "peak_in_use_bytes": st["peak_in_use_bytes"],
     }

@@ -44,7 +44,7 @@ class MergeRequest:
     committed: float | None = None
     rows: int = 0               # merged tuples (all columns)
     reserved: int = 0           # bytes held from admission to commit
-    status: str = "queued"      # queued | running | committed | cancelled
+    status: str = "queued"      # queued | running | committed | cancelled | rejected
     job: object = None
     snapshot: object = None     # the frozen delta (executor object)
 
@@ -79,13 +79,18 @@ class Server:
         self.admission_waits = 0    # polls in which the head request could not be admitted
         self.backpressure = 0       # appends refused because a delta was full
         self.appended_rows = 0
+        self.rejected = 0           # requests that cannot fit even with nothing running
+        self.reserve = 0            # headroom kept for merges: largest merge need seen
+        self.waiting_for_memory = False
         self.t0 = self.clock()
 
     # ---- tables and appends -------------------------------------------------
 
     def add_table(self, tid: int, main, delta_capacity: int):
-        self.tables[tid] = TableState(main, self.ex.new_delta(main, delta_capacity),
-                                      self.ex.new_delta(main, delta_capacity))
+        t = TableState(main, self.ex.new_delta(main, delta_capacity),
+                       self.ex.new_delta(main, delta_capacity))
+        self.tables[tid] = t
+        self.reserve = max(self.reserve, self.ex.merge_bytes(t.main, t.active))
         self._note_use()
 
     def append(self, tid: int, rows) -> bool:
@@ -94,7 +99,12 @@ class Server:
         the delta cannot take the rows."""
         t = self.tables[tid]
         n = self.ex.batch_rows(rows)
-        if not self.ex.append(t.active, rows, self.budget - self.in_use()):
+        # Deltas may only grow into memory that merges do not need: never
+        # while a request waits for memory, and always leaving room for the
+        # largest merge seen, so appends cannot starve the merges that would
+        # free their memory.
+        room = 0 if self.waiting_for_memory else self.budget - self.in_use() - self.reserve
+        if not self.ex.append(t.active, rows, max(room, 0)):
             self.backpressure += 1
             return False
         self.appended_rows += n
@@ -160,7 +170,14 @@ class Server:
                 blocked_tables.add(r.table)     # one merge per table at a time
                 continue
             need = self.ex.merge_bytes(t.main, t.active)
+            self.reserve = max(self.reserve, need)
             if self.in_use() + need > self.budget:
+                if not self.running:
+                    # nothing will free memory: this request can never run
+                    self.queue.remove(r)
+                    r.status = "rejected"
+                    self.rejected += 1
+                    continue
                 waited = True
                 break                           # arrival order: nothing overtakes
             # freeze the active delta as the snapshot, appends go to the second
@@ -177,6 +194,7 @@ class Server:
             self.queue.remove(r)
             self.running.append(r)
             self._note_use()
+        self.waiting_for_memory = waited and len(self.running) < self.max_inflight
         if waited:
             self.admission_waits += 1
 
@@ -197,11 +215,17 @@ class Server:
         self.done.append(r)
         self._note_use()
 
-    def drain(self, timeout: float = 600.0):
+    def drain(self, timeout: float = 600.0, progress=None):
+        """Run until every request is committed, rejected or the timeout
+        passes; `progress(server)` is called about once a second."""
         end = self.clock() + timeout
+        last = self.clock()
         while (self.queue or self.running) and self.clock() < end:
             if not self.poll():
                 self.ex.idle()
+            if progress is not None and self.clock() - last >= 1.0:
+                last = self.clock()
+                progress(self)
 
     # ---- statistics ------------------------------------------------------------
 
@@ -219,6 +243,7 @@ class Server:
             "appended_rows": self.appended_rows,
             "admission_waits": self.admission_waits,
             "backpressure": self.backpressure,
+            "rejected": self.rejected,
             "peak_in_use_bytes": self.peak_in_use,
             "budget_bytes": self.budget,
             "wall_s": wall,

@@ -234,13 +234,43 @@ def test_backpressure_when_delta_full():
     assert s.stats()["backpressure"] == 1
 
 
-def test_request_larger_than_budget_waits_forever_without_overtaking():
+def test_request_that_can_never_fit_is_rejected():
     rng = np.random.default_rng(4)
     ex = CpuExecutor()
     s = Server(ex, budget_bytes=1, clock=FakeClock())    # nothing fits
     m = make_table(rng)
     s.add_table(0, m, 10)
     r = s.submit_merge(0)
-    for _ in range(5):
-        s.poll()
-    assert r.status == "queued" and s.admission_waits == 5
+    s.poll()
+    assert r.status == "rejected" and s.stats()["rejected"] == 1
+
+
+def test_appends_cannot_starve_waiting_merges():
+    """While a request waits for memory, deltas may not grow; and growth
+    always leaves room for the largest merge seen."""
+    rng = np.random.default_rng(6)
+
+    class Growing(CpuExecutor):
+        def append(self, d, rows, room):
+            extra = max(0, d.rows + rows["n"] - d.cap) * 64
+            if extra > room:
+                return False
+            d.cap = max(d.cap, d.rows + rows["n"])
+            return super().append(d, rows, room)
+
+    ex = Growing(polls_to_finish=6)
+    s = Server(ex, budget_bytes=10 ** 12, max_inflight=4, clock=FakeClock())
+    for t in range(3):
+        s.add_table(t, make_table(rng, 2, 50), delta_capacity=10)
+        s.append(t, batch(rng, s.tables[t].main, 10))
+    needs = [ex.merge_bytes(s.tables[t].main, s.tables[t].active) for t in range(3)]
+    s.budget = s.in_use() + needs[0] + needs[1] // 2
+    r0, r1 = s.submit_merge(0), s.submit_merge(1)
+    s.poll()
+    assert r0.status == "running" and r1.status == "queued" and s.waiting_for_memory
+    bp = s.backpressure
+    assert not s.append(2, batch(rng, s.tables[2].main, 50))    # growth refused
+    assert s.backpressure == bp + 1
+    s.drain()
+    assert r1.status == "committed"
+    assert s.peak_in_use <= s.budget
