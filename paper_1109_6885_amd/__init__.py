@@ -200,6 +200,23 @@ class MergeOutput:
         return out
 
 
+def bounds_of(desc: McColumnIn):
+    """mc_merge_bounds on a raw descriptor: (dict_cap, codes_words, scratch_bytes)."""
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    check(load().mc_merge_bounds(ctypes.byref(desc), ctypes.byref(a), ctypes.byref(b),
+                                 ctypes.byref(c)), "mc_merge_bounds")
+    return int(a.value), int(b.value), int(c.value)
+
+
+def batched_bounds_of(descs) -> int:
+    """mc_merge_batched_bounds on raw descriptors."""
+    arr = (McColumnIn * len(descs))(*descs)
+    sb = ctypes.c_uint64()
+    check(load().mc_merge_batched_bounds(arr, len(descs), ctypes.byref(sb)),
+          "mc_merge_batched_bounds")
+    return int(sb.value)
+
+
 def merge_bounds(col: ColumnInput):
     """(dict_cap, codes_words, scratch_bytes) for one column (host only)."""
     d = col.descriptor()

@@ -60,6 +60,7 @@ class TableState:
     second: object              # empty delta, becomes active at admission
     merging: MergeRequest | None = None
     merges: int = 0
+    need_cap: int = 0           # worst-case merge bytes with the active delta full
 
 
 class Server:
@@ -90,23 +91,38 @@ class Server:
         t = TableState(main, self.ex.new_delta(main, delta_capacity),
                        self.ex.new_delta(main, delta_capacity))
         self.tables[tid] = t
-        self.reserve = max(self.reserve, self.ex.merge_bytes(t.main, t.active))
+        self._refresh_need(t)
         self._note_use()
+
+    def _refresh_need(self, t: TableState):
+        t.need_cap = self.ex.merge_bytes_at(t.main, self.ex.delta_capacity(t.active))
+        self.reserve = max(x.need_cap for x in self.tables.values())
 
     def append(self, tid: int, rows) -> bool:
         """Append a batch (executor format) to the table's active delta,
-        growing it if the budget has room.  Returns False (back-pressure) if
-        the delta cannot take the rows."""
+        growing it if the budget allows.  Returns False (back-pressure) if
+        the delta cannot take the rows.
+
+        Memory rule: in_use + (largest worst-case merge of any table, with its
+        active delta full) <= budget.  Merge bounds only grow with the delta,
+        so a request can always be admitted once nothing else runs; appends
+        cannot starve the merges that would free their memory.  While a
+        request waits for memory no delta grows at all."""
         t = self.tables[tid]
         n = self.ex.batch_rows(rows)
-        # Deltas may only grow into memory that merges do not need: never
-        # while a request waits for memory, and always leaving room for the
-        # largest merge seen, so appends cannot starve the merges that would
-        # free their memory.
-        room = 0 if self.waiting_for_memory else self.budget - self.in_use() - self.reserve
-        if not self.ex.append(t.active, rows, max(room, 0)):
-            self.backpressure += 1
-            return False
+        grow, new_cap = self.ex.grow_plan(t.active, n)
+        if grow > 0:
+            if self.waiting_for_memory or new_cap is None:
+                self.backpressure += 1
+                return False
+            need_new = self.ex.merge_bytes_at(t.main, new_cap)
+            others = max((x.need_cap for x in self.tables.values() if x is not t), default=0)
+            if self.in_use() + grow + max(need_new, others) > self.budget:
+                self.backpressure += 1
+                return False
+        self.ex.append(t.active, rows)
+        if grow > 0:
+            self._refresh_need(t)
         self.appended_rows += n
         self._note_use()
         return True
@@ -169,8 +185,7 @@ class Server:
             if t.merging is not None or r.table in blocked_tables:
                 blocked_tables.add(r.table)     # one merge per table at a time
                 continue
-            need = self.ex.merge_bytes(t.main, t.active)
-            self.reserve = max(self.reserve, need)
+            need = self.ex.merge_bytes_at(t.main, self.ex.delta_rows(t.active))
             if self.in_use() + need > self.budget:
                 if not self.running:
                     # nothing will free memory: this request can never run
@@ -191,6 +206,7 @@ class Server:
             r.admitted = self.clock()
             r.status = "running"
             t.merging = r
+            self._refresh_need(t)            # the new active delta is the (small) second one
             self.queue.remove(r)
             self.running.append(r)
             self._note_use()
@@ -208,6 +224,7 @@ class Server:
         t.second = r.snapshot                   # the emptied snapshot is the next second delta
         t.merging = None
         t.merges += 1
+        self._refresh_need(t)                # the new main is larger
         self.reserved -= r.reserved
         r.committed = self.clock()
         r.status = "committed"
@@ -324,16 +341,24 @@ class GpuExecutor:
     def delta_bytes(self, d): return d.nbytes
     def batch_rows(self, rows): return rows["n"]
 
-    def append(self, d: GpuDelta, rows, room: int) -> bool:
+    def grow_plan(self, d: GpuDelta, n: int):
+        """(bytes to allocate, new capacity) for appending n rows; (0, cap) if
+        they fit."""
+        if d.rows + n <= d.cap:
+            return 0, d.cap
+        new_cap = max(2 * d.cap, d.rows + n)
+        if new_cap >= (1 << 30):
+            return 1, None                     # past the library's delta limit
+        return (new_cap - d.cap) * d.row_bytes, new_cap
+
+    def append(self, d: GpuDelta, rows):
         """rows: {"n": r, vtype: pinned host tensor (n_cols_of_type, r[, 16])}.
-        Doubles the delta's capacity when needed, if `room` bytes allow."""
+        Doubles the delta's capacity first when needed."""
         n = rows["n"]
         torch = self.torch
         with torch.cuda.stream(self.append_stream):
             if d.rows + n > d.cap:
                 new_cap = max(2 * d.cap, d.rows + n)
-                if (new_cap - d.cap) * d.row_bytes > room:
-                    return False
                 counts = {vt: g.shape[0] for vt, g in d.groups.items()}
                 groups, nb = self._alloc_groups(counts, new_cap)
                 for vt, g in d.groups.items():
@@ -366,20 +391,35 @@ class GpuExecutor:
             out.append(self.cm.ColumnInput(c.vtype, c.u_m, c.main_codes, c.n_main, c.w, delta))
         return out
 
-    def merge_bytes(self, m: GpuMain, d: GpuDelta) -> int:
-        """Worst-case output bytes (U' and codes of every column, from
-        mc_merge_bounds) plus the batched workspace.  Cached per delta size:
-        the admission check repeats while a request waits."""
-        key = (id(m), d.rows)
-        if getattr(m, "_need_key", None) == key:
-            return m._need
+    def merge_bytes_at(self, m: GpuMain, rows: int) -> int:
+        """Worst-case bytes of merging `rows` delta rows into main m: every
+        column's U' and codes capacity (mc_merge_bounds) plus the batched
+        workspace (mc_merge_batched_bounds).  Host-only arithmetic in the
+        library; cached per (main, rows)."""
+        key = (id(m), rows)
+        cache = m.__dict__.setdefault("_need", {})
+        if key in cache:
+            return cache[key]
+        cm = self.cm
+        ins = []
         total = 0
-        cols = self._inputs(m, d)
-        for col in cols:
-            dict_cap, words, _ = self.cm.merge_bounds(col)
-            total += dict_cap * self.cm.VALUE_LEN[col.vtype] + max(words, 2) * 8 + 64
-        total += self.cm.batched_bounds(cols)
-        m._need_key, m._need = key, total
+        for c in m.cols:
+            d = cm.McColumnIn()
+            d.type = cm.TYPE_CODES[c.vtype]
+            d.bitwidth = c.w
+            d.main_dict = 256 if c.u_m.numel() else None     # sizing never reads memory
+            d.main_dict_len = int(c.u_m.shape[0])
+            d.main_codes = 256 if c.n_main else None
+            d.main_rows = c.n_main
+            d.delta_values = 256 if rows else None
+            d.delta_rows = rows
+            ins.append(d)
+            dc, words, _ = cm.bounds_of(d)
+            total += dc * cm.VALUE_LEN[c.vtype] + max(words, 2) * 8 + cm.RESULT_BYTES
+        total += cm.batched_bounds_of(ins)
+        if len(cache) > 64:
+            cache.clear()
+        cache[key] = total
         return total
 
     def launch(self, m: GpuMain, d: GpuDelta):

@@ -63,10 +63,13 @@ class CpuExecutor:
     def batch_rows(self, rows):
         return rows["n"]
 
-    def append(self, d, rows, room):
-        # fixed capacity here: a full delta refuses rows (back-pressure)
-        if d.rows + rows["n"] > d.cap:
-            return False
+    def grow_plan(self, d, n):
+        # fixed capacity here: a full delta cannot grow (back-pressure)
+        if d.rows + n <= d.cap:
+            return 0, d.cap
+        return 1, None
+
+    def append(self, d, rows):
         for j, v in enumerate(rows["cols"]):
             d.vals[j].extend(list(v))
         d.rows += rows["n"]
@@ -76,9 +79,12 @@ class CpuExecutor:
         d.vals = [[] for _ in d.vals]
         d.rows = 0
 
-    def merge_bytes(self, m, d):
-        return sum((c["u_m"].shape[0] + d.rows) * 16 + (c["n_main"] + d.rows) * 4 + 4096
+    def merge_bytes_at(self, m, rows):
+        return sum((c["u_m"].shape[0] + rows) * 16 + (c["n_main"] + rows) * 4 + 4096
                    for c in m.cols)
+
+    def merge_bytes(self, m, d):
+        return self.merge_bytes_at(m, d.rows)
 
     def launch(self, m, d):
         job = {"m": m, "snap": [list(v) for v in d.vals], "polls": 0}
@@ -251,12 +257,14 @@ def test_appends_cannot_starve_waiting_merges():
     rng = np.random.default_rng(6)
 
     class Growing(CpuExecutor):
-        def append(self, d, rows, room):
-            extra = max(0, d.rows + rows["n"] - d.cap) * 64
-            if extra > room:
-                return False
+        def grow_plan(self, d, n):
+            if d.rows + n <= d.cap:
+                return 0, d.cap
+            return (d.rows + n - d.cap) * 64, d.rows + n
+
+        def append(self, d, rows):
             d.cap = max(d.cap, d.rows + rows["n"])
-            return super().append(d, rows, room)
+            return super().append(d, rows)
 
     ex = Growing(polls_to_finish=6)
     s = Server(ex, budget_bytes=10 ** 12, max_inflight=4, clock=FakeClock())
@@ -265,6 +273,7 @@ def test_appends_cannot_starve_waiting_merges():
         s.append(t, batch(rng, s.tables[t].main, 10))
     needs = [ex.merge_bytes(s.tables[t].main, s.tables[t].active) for t in range(3)]
     s.budget = s.in_use() + needs[0] + needs[1] // 2
+    assert s.reserve == max(s.tables[t].need_cap for t in range(3))
     r0, r1 = s.submit_merge(0), s.submit_merge(1)
     s.poll()
     assert r0.status == "running" and r1.status == "queued" and s.waiting_for_memory
@@ -274,3 +283,38 @@ def test_appends_cannot_starve_waiting_merges():
     s.drain()
     assert r1.status == "committed"
     assert s.peak_in_use <= s.budget
+
+
+def test_growth_keeps_room_for_the_largest_merge():
+    rng = np.random.default_rng(8)
+
+    class Growing(CpuExecutor):
+        def grow_plan(self, d, n):
+            if d.rows + n <= d.cap:
+                return 0, d.cap
+            return (2 * d.cap - d.cap) * 64, 2 * d.cap
+
+        def append(self, d, rows):
+            if d.rows + rows["n"] > d.cap:
+                d.cap *= 2
+            return super().append(d, rows)
+
+        def delta_bytes(self, d):
+            return d.cap * 64
+
+    ex = Growing(polls_to_finish=3)
+    s = Server(ex, budget_bytes=10 ** 12, clock=FakeClock())
+    for t in range(3):
+        s.add_table(t, make_table(rng, 2, 40), delta_capacity=8)
+    s.budget = s.in_use() + 3 * s.reserve
+    refused = 0
+    for step in range(300):
+        t = step % 3
+        if not s.append(t, batch(rng, s.tables[t].main, 4)):
+            refused += 1
+        # the rule: whatever is in use, the largest possible merge still fits
+        assert s.in_use() + s.reserve <= s.budget
+    assert refused > 0
+    reqs = [s.submit_merge(t) for t in range(3)]
+    s.drain()
+    assert all(r.status == "committed" for r in reqs) and s.rejected == 0
