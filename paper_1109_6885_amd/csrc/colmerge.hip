@@ -105,13 +105,13 @@ struct Carver {
 
 struct ColLayout {
     // part Z
-    uint64_t counters = 0, n_ud = 0, err = 0, gh = 0, trivial = 0, emit_status = 0,
+    uint64_t counters = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0, emit_status = 0,
              merge_status = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
-             drank = 0, x_d = 0, x_m = 0, b_size = 0;
+             drank = 0, x_d = 0, x_m = 0, xdev = 0, b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
-    uint64_t merge_tiles = 0, repack_tiles = 0;
+    uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
 };
 
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) {
@@ -123,10 +123,12 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) 
     L.hist_tiles = (uint32_t)ceil_div(nd, mc::kHistChunk);
     L.merge_tiles = ceil_div(n_um + nd, mc::kMergeTile);
     L.repack_tiles = ceil_div(n_main + nd, mc::kRepackCodes);
+    L.xc_tiles = n_main ? ceil_div(n_um, mc::kXCompactTile) : 0;
     Carver z;
     L.counters = z.take(16 * 4);
     L.n_ud = z.take(8);
     L.err = z.take(8);
+    L.xflag = z.take(8);
     L.gh = z.take((uint64_t)L.passes * 256 * 4);
     L.trivial = z.take(16 * 4);
     L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
@@ -143,6 +145,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) 
     L.drank = b.take(nd * 4);
     L.x_d = b.take(nd * 4);
     L.x_m = b.take(n_um * 4);
+    L.xdev = b.take(n_um * 2);
     L.b_size = b.size();
     return L;
 }
@@ -188,6 +191,8 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.nd_max = in->delta_rows;
     C.u_d = zb + L.u_d;
     C.drank = reinterpret_cast<uint32_t *>(zb + L.drank);
+    C.xdev = L.xc_tiles ? reinterpret_cast<int16_t *>(zb + L.xdev) : nullptr;
+    C.xflag = reinterpret_cast<uint32_t *>(za + L.xflag);
     return C;
 }
 
@@ -260,6 +265,9 @@ template <class T>
 __global__ __launch_bounds__(256) void k1_merge(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T>)];
     mc::merge_tile<T>(C, smem);
+}
+__global__ __launch_bounds__(256) void k1_xcompact(mc::ColDesc C) {
+    mc::xcompact_tile(C, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void k1_repack(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
@@ -346,6 +354,10 @@ __global__ __launch_bounds__(256) void kn_merge(Batch B) {
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::merge_tile, C, smem);
 }
+__global__ __launch_bounds__(256) void kn_xcompact(Batch B) {
+    const uint32_t j = find_col(B, blockIdx.x);
+    mc::xcompact_tile(B.cols[j], blockIdx.x - B.map[j]);
+}
 __global__ __launch_bounds__(256) void kn_repack(Batch B) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
     const uint32_t j = find_col(B, blockIdx.x);
@@ -400,6 +412,11 @@ int launch_merge(const mc::ColDesc &C, uint64_t merge_tiles, hipStream_t s) {
 }
 
 int launch_repack(const mc::ColDesc &C, hipStream_t s) {
+    if (C.xdev && C.n_um) {
+        hipLaunchKernelGGL(k1_xcompact, dim3((uint32_t)ceil_div(C.n_um, mc::kXCompactTile)),
+                           dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_xcompact");
+    }
     const uint64_t grid = ceil_div(C.n_main + C.nd, mc::kRepackCodes);
     if (grid == 0) return MC_OK;
     hipLaunchKernelGGL(k1_repack, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C);
@@ -510,10 +527,10 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 
 constexpr int kMaxPasses = 16;
 // map slots: 0 hist, 1 hist_scan, 2..17 pass up/down, 18..33 pass scan,
-// 34 emit, 35 merge, 36 repack, 37 zero-results (one entry per column)
+// 34 emit, 35 merge, 36 repack, 37 X_M compaction
 constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 2 + kMaxPasses,
               kMapEmit = 2 + 2 * kMaxPasses, kMapMerge = kMapEmit + 1, kMapRepack = kMapEmit + 2,
-              kNumMaps = kMapEmit + 3;
+              kMapXc = kMapEmit + 3, kNumMaps = kMapEmit + 4;
 
 struct BatchPlan {
     uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, total = 0;
@@ -562,6 +579,7 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P) {
             else if (m == kMapEmit) n = L.emit_tiles;
             else if (m == kMapMerge) n = L.merge_tiles ? L.merge_tiles : 1;
             else if (m == kMapRepack) n = L.repack_tiles;
+            else if (m == kMapXc) n = L.xc_tiles;
             at(m, j) = (uint32_t)acc;
             acc += n;
             if (acc >= (1ull << 31)) return fail(MC_E_ARG, "batch has too many tiles for one launch");
@@ -615,6 +633,10 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
         hipLaunchKernelGGL(kn_merge, dim3(tiles(kMapMerge)), dim3(mc::kBlock), 0, s,
                            batch(kMapMerge));
         MC_LAUNCHED("kn_merge");
+    }
+    if (tiles(kMapXc)) {
+        hipLaunchKernelGGL(kn_xcompact, dim3(tiles(kMapXc)), dim3(mc::kBlock), 0, s, batch(kMapXc));
+        MC_LAUNCHED("kn_xcompact");
     }
     if (tiles(kMapRepack)) {
         hipLaunchKernelGGL(kn_repack, dim3(tiles(kMapRepack)), dim3(mc::kBlock), 0, s,

@@ -237,6 +237,8 @@ struct ColDesc {
     uint64_t nd_max;           // capacity of u_d, drank, x_d
     void *u_d;                 // U_D
     uint32_t *drank;           // index in U_D of every delta row
+    int16_t *xdev;             // compact X_M (see repack.hpp), n_um entries, or null
+    uint32_t *xflag;           // nonzero: a compact entry overflowed, use x_m (zeroed)
 };
 
 // Code width for a dictionary of n entries: ceil(log2 n), at least 1.

@@ -3,11 +3,11 @@
 // is unpacked at the old width w, translated through X_M and repacked at
 // the new width w'; the delta rows follow, translated through X_D.
 //
-// A workgroup owns 4096 consecutive output rows.  Because 64 codes of width
-// w fill exactly w 64-bit words, a tile of 4096 rows starts on a word
-// boundary both in the input (64*w words) and in the output (64*w' words),
+// A workgroup owns 2048 consecutive output rows.  Because 64 codes of width
+// w fill exactly w 64-bit words, a tile of 2048 rows starts on an even word
+// boundary both in the input (32*w words) and in the output (32*w' words),
 // so tiles never share a word and need no atomics.  The tile's input words
-// are staged in LDS with 128-bit loads, each thread decodes 16 codes and
+// are staged in LDS with 128-bit loads, each thread decodes 8 codes and
 // gathers their new codes from X_M (X_D for delta rows) into an LDS code
 // array, and then each thread assembles whole output words from the codes
 // that overlap them and writes them with coalesced 128-bit stores.
@@ -17,15 +17,57 @@
 
 namespace mc {
 
-constexpr int kRepackCodes = 4096;               // rows per tile (64 groups of 64)
+constexpr int kRepackCodes = 2048;               // rows per tile (32 groups of 64)
 constexpr int kRepackPer = kRepackCodes / kBlock;  // codes per thread
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 struct RepackSmem {
-    uint64_t in[64 * 32 + 2];
+    uint64_t in[kRepackCodes / 64 * 32 + 2];
     uint32_t code[kRepackCodes];
 };
+
+// ---------------------------------------------------------------------------
+// Compact X_M.  The gathers X_M[c] dominate Step 2(b), and their cost grows
+// with the table's footprint, not with the bytes used per entry.  X_M is
+// strictly increasing: X_M[c] = c + g(c), where g(c) counts the new delta
+// values below U_M[c] (monotone, from 0 to |U'| - |U_M|).  With
+// a(c) = floor(c * A / 2^32), A = floor(2^32 * (|U'| - |U_M|) / |U_M|) (a
+// fixed-point straight line through g's end points), the table stores the
+// exact deviation d(c) = g(c) - a(c) in 16 bits, and X_M[c] = c + a(c) + d(c)
+// is recomputed with the same integer formula.  If any deviation leaves
+// int16 the flag is set and Step 2(b) gathers from the 32-bit X_M instead.
+// The result is bit-identical either way.
+// ---------------------------------------------------------------------------
+
+constexpr int kXCompactTile = 4096;
+
+__device__ __forceinline__ uint64_t xm_line_slope(const ColDesc &C) {
+    const uint64_t added = C.result->new_dict_len - C.n_um;  // new delta values
+    return C.n_um ? (added << 32) / C.n_um : 0;
+}
+__device__ __forceinline__ uint64_t xm_line(uint64_t c, uint64_t A) {
+    const uint64_t lo = c * A, hi = __umul64hi(c, A);
+    return (hi << 32) | (lo >> 32);
+}
+
+__device__ inline void xcompact_tile(const ColDesc &C, uint64_t t) {
+    const uint64_t A = xm_line_slope(C);
+    bool bad = false;
+    for (uint32_t j = threadIdx.x; j < kXCompactTile; j += kBlock) {
+        const uint64_t c = t * kXCompactTile + j;
+        if (c < C.n_um) {
+            const int64_t dev = (int64_t)C.x_m[c] - (int64_t)c - (int64_t)xm_line(c, A);
+            if (dev < -32768 || dev > 32767) {
+                bad = true;
+                C.xdev[c] = 0;
+            } else {
+                C.xdev[c] = (int16_t)dev;
+            }
+        }
+    }
+    if (bad) atomicOr(C.xflag, 1u);
+}
 
 __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     RepackSmem &S = *reinterpret_cast<RepackSmem *>(smem);
@@ -44,8 +86,8 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     // translation tables keep the cache)
     if (c0 < C.n_main) {
         const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
-        const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 64
-        const uint32_t nw = (uint32_t)min<uint64_t>(64ull * w, win - wbase);
+        const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 32
+        const uint32_t nw = (uint32_t)min<uint64_t>(kRepackCodes / 64 * (uint64_t)w, win - wbase);
         const uint32_t npair = nw / 2;
         const u64x2 *src2 = reinterpret_cast<const u64x2 *>(C.main_codes + wbase);
         u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
@@ -58,6 +100,8 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
 
     // decode every code of this thread first, then issue all gathers together
     const uint64_t mask = (1ull << w) - 1ull;
+    const bool compact = C.xdev != nullptr && *C.xflag == 0;
+    const uint64_t A = compact ? xm_line_slope(C) : 0;
     const uint32_t *tab[kRepackPer];
     uint32_t idx[kRepackPer];
     uint32_t bad = 0;
@@ -92,18 +136,29 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
         }
     }
     uint32_t nc[kRepackPer];
+    if (compact) {
+        // main rows: X_M[c] = c + a(c) + d(c); delta rows gather X_D
 #pragma unroll
-    for (int j = 0; j < kRepackPer; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+        for (int j = 0; j < kRepackPer; j++) {
+            if (tab[j] == C.x_m)
+                nc[j] = idx[j] + (uint32_t)xm_line(idx[j], A) + (uint32_t)(int32_t)C.xdev[idx[j]];
+            else
+                nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRepackPer; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+    }
 #pragma unroll
     for (int j = 0; j < kRepackPer; j++) s_code[j * kBlock + threadIdx.x] = nc[j];
     if (bad) flag_error(C.err, bad);
     __syncthreads();
 
     // assemble output words: local word k covers tile bits [64k, 64k + 64)
-    const uint64_t obase = t * 64ull * wn;
+    const uint64_t obase = t * (uint64_t)(kRepackCodes / 64) * wn;
     const uint64_t wres = (n_out * wn + 63) / 64;
     const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
-    const uint32_t nwo = 64u * wn;  // words of a full tile (even)
+    const uint32_t nwo = (kRepackCodes / 64) * wn;  // words of a full tile (even)
     // floor(x / wn) for x < 2^17 as a multiply-high by ceil(2^32 / wn): the
     // rounding error of the reciprocal times x stays below 2^32, so it is exact
     const uint32_t rcp = (uint32_t)((0x100000000ull + wn - 1) / wn);

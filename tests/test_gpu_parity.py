@@ -249,3 +249,25 @@ def test_config3_full_size():
     got = gpu_merge(col)
     assert got["w_new"] == 24
     check_large(col, got)
+
+
+@pytest.mark.parametrize("where", ["below", "above", "middle"])
+def test_skewed_new_values(where):
+    """New values all on one side of U_M: the translation table is far from a
+    straight line, so the compact table overflows and Step 2(b) falls back to
+    the 32-bit table; results stay exact either way."""
+    rng = np.random.default_rng(77)
+    u_m = np.sort(rng.choice(np.arange(10 ** 6, 2 * 10 ** 6, dtype=np.uint64), 3000, replace=False))
+    if where == "below":
+        new = np.arange(0, 50_000, dtype=np.uint64)
+    elif where == "above":
+        new = np.arange(3 * 10 ** 6, 3 * 10 ** 6 + 50_000, dtype=np.uint64)
+    else:
+        new = np.arange(1_500_000 * 3, 1_500_000 * 3 + 50_000, dtype=np.uint64) // 3
+        new = np.setdiff1d(new, u_m)
+    delta = np.concatenate([new, u_m[rng.integers(0, 3000, 1000)]])
+    delta = delta[rng.permutation(delta.shape[0])]
+    codes = rng.integers(0, 3000, 70_000)
+    col = gen.Column("u64", u_m, gen.pack_codes(codes, 12), 70_000, 12, delta)
+    say(f"case skewed {where}")
+    assert_same(gpu_merge(col), ora_merge(col))
