@@ -220,6 +220,65 @@ def bench_serve(args):
     return out
 
 
+def bench_sweep_fig7(args):
+    """Delta-size sweep of Section 7.1 (Fig. 7): main 100M rows with 10% unique
+    8-byte values, delta 0.5M-8M rows with 10% unique values (half of them
+    already in the main dictionary).  The merge with translation tables (Opt)
+    against the merge with the naive Step 2(b) (UnOpt), both on the GPU."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6885_amd as cm
+    from workloads import gen
+
+    rng = np.random.default_rng(gen.BASE_SEED + 7)
+    t = time.time()
+    n_main, k = 100_000_000, 10_000_000
+    base = gen.random_column(rng, "u64", k, n_main, 0)
+    log(f"main generated in {time.time() - t:.1f}s")
+    torch.cuda.set_device(0)
+    u_m = cm.to_device(base.u_m)
+    codes = cm.to_device(base.main_packed)
+    ctx = cm.context()
+    stream = torch.cuda.current_stream()
+    rows = []
+    for nd in (500_000, 1_000_000, 2_000_000, 4_000_000, 8_000_000):
+        pool_n = nd // 10
+        old = base.u_m[rng.integers(0, k, pool_n // 2)]
+        new = gen.distinct_values(rng, "u64", pool_n - pool_n // 2, base.u_m)
+        pool = np.concatenate([old, new])
+        delta = pool[rng.integers(0, pool.shape[0], nd)]
+        col = cm.ColumnInput("u64", u_m, codes, n_main, base.w, cm.to_device(delta))
+        out = cm.alloc_output(col)
+        scratch = cm.alloc_scratch(cm.merge_bounds(col)[2])
+        res = {}
+        for name, fn, reps in (("opt", cm.merge_column, 5), ("unopt", cm.merge_column_naive, 2)):
+            fn(col, out=out, scratch=scratch, stream=stream, ctx=ctx)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn(col, out=out, scratch=scratch, stream=stream, ctx=ctx)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / reps
+            sc = out.scalars()
+            assert sc["error"] == 0
+            res[name + "_words"] = sc["words"]
+        n_out = n_main + nd
+        rows.append({"delta_rows": nd, "opt_ms": res["opt"], "unopt_ms": res["unopt"],
+                     "speedup": res["unopt"] / res["opt"],
+                     "opt_ns_per_tuple": res["opt"] * 1e6 / n_out,
+                     "unopt_ns_per_tuple": res["unopt"] * 1e6 / n_out,
+                     "merge_update_rate_per_s": nd / (res["opt"] / 1e3)})
+        log(f"N_D={nd}: opt {res['opt']:.2f} ms, unopt {res['unopt']:.2f} ms")
+        del col, out, scratch
+    return {"metric": "delta-size sweep: merge time with translation tables vs naive Step 2(b)",
+            "workload": "u64 column, 100M main rows, 10M distinct (10%), delta 0.5M-8M rows with "
+                        "10% distinct values, half of them new",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +299,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-rate", type=float, default=5.0, help="merge requests per second")
+    ap.add_argument("--sweep", choices=["fig7"], help="run a sweep instead and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -248,6 +308,9 @@ def main():
         sys.exit(2)
     if args.serve:
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.sweep == "fig7":
+        print(json.dumps(bench_sweep_fig7(args)), flush=True)
         return
 
     import numpy as np
@@ -321,6 +384,27 @@ def main():
     copy_gbs = 2 * copy_bytes * 5 / (e0.elapsed_time(e1) / 1000.0) / 1e9
     del src, dst
 
+    # random-gather ceiling for the re-encode: as many uniformly random
+    # lookups as main rows, into a table with the translation table's entry
+    # count, at 4 and 2 bytes per entry (the kernel's 32-bit and compact forms)
+    n_g = col.n_main
+    gen_t = torch.Generator(device="cuda")
+    gen_t.manual_seed(1)
+    idx = torch.randint(0, 2 ** 31 - 1, (n_g,), generator=gen_t, device="cuda", dtype=torch.int32)
+    gout = torch.empty_like(idx)
+    gather_us = {}
+    for eb, dt in ((4, torch.int32), (2, torch.int16)):
+        tab = torch.ones(col.u_m.shape[0], dtype=dt, device="cuda")
+        cm.gather_ref(idx, tab, gout, stream=stream)
+        e0.record(stream)
+        for _ in range(5):
+            cm.gather_ref(idx, tab, gout, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gather_us[eb] = e0.elapsed_time(e1) / 5 * 1000.0
+        del tab
+    del idx, gout
+
     batched = None
     if bcols is not None:
         batched = bench_batched(cm, torch, bcols, args.steps, args.warmup, stream, ctx)
@@ -372,6 +456,9 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": b_re},
         "copy_kernel_gbs": copy_gbs,
+        "gather_ref_us": {"rows": col.n_main, "table_entries": int(col.u_m.shape[0]),
+                          "u32_table": gather_us[4], "u16_table": gather_us[2],
+                          "note": "random lookups + 4-byte index read + 4-byte write per row"},
         "reencode_frac_of_copy": achieved / copy_gbs,
         "cpu_baseline": cpu,
         "batched": batched,

@@ -142,6 +142,16 @@ int mc_merge_column(mc_ctx *ctx, const mc_column_in *in,
                     const mc_column_out *out, void *scratch,
                     uint64_t scratch_bytes, struct ihipStream_t *stream);
 
+/* The same merge with the unoptimized Step 2(b) of Section 5.2 (cost of
+ * Eq. 5): each main row's value is read from U_M and its new code found by
+ * binary search in U'; each delta value is searched directly.  Same inputs,
+ * outputs, scratch and results as mc_merge_column; it exists to measure the
+ * translation tables of Section 5.3 against the route they replace
+ * (Section 7.1).  X_M / X_D outputs, if requested, are still written. */
+int mc_merge_column_naive(mc_ctx *ctx, const mc_column_in *in,
+                          const mc_column_out *out, void *scratch,
+                          uint64_t scratch_bytes, struct ihipStream_t *stream);
+
 /* ---- single steps (the same kernels as mc_merge_column) --------------- */
 
 /* Step 1(a), modified form (Sections 5.1 and 5.3): sorted unique delta
@@ -221,6 +231,16 @@ int mc_ctx_step_times(mc_ctx *ctx, float *ms5);
  * known-traffic kernel that calibrates hardware byte counters. */
 int mc_copy_bytes(mc_ctx *ctx, const void *src, void *dst, uint64_t bytes,
                   struct ihipStream_t *stream);
+
+/* Random-gather reference: out[i] = table[idx[i] % n_table] for i < n,
+ * with 2- or 4-byte table entries (device buffers; idx and out hold n
+ * entries).  Not part of the merge: it measures how fast random lookups
+ * into a table of a given footprint run, which bounds the translation-table
+ * lookups of Step 2(b) (Eq. 11), beside the streaming bound of
+ * mc_copy_bytes. */
+int mc_gather_ref(mc_ctx *ctx, const uint32_t *idx, uint64_t n,
+                  const void *table, uint32_t entry_bytes, uint32_t n_table,
+                  uint32_t *out, struct ihipStream_t *stream);
 
 #ifdef __cplusplus
 }

@@ -260,6 +260,22 @@ def merge_column(col: ColumnInput, out: MergeOutput | None = None,
     return out
 
 
+def merge_column_naive(col: ColumnInput, out: MergeOutput | None = None,
+                       scratch: torch.Tensor | None = None, tables: bool = False,
+                       stream=None, ctx: Context | None = None) -> MergeOutput:
+    """mc_merge_column_naive: the merge with the unoptimized Step 2(b)."""
+    ctx = ctx or context()
+    if out is None:
+        out = alloc_output(col, tables)
+    if scratch is None:
+        scratch = alloc_scratch(merge_bounds(col)[2])
+    din, dout = col.descriptor(), out.descriptor()
+    check(load().mc_merge_column_naive(ctx.handle, ctypes.byref(din), ctypes.byref(dout),
+                                       _ptr(scratch), scratch.numel(), _stream(stream)),
+          "mc_merge_column_naive")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Single steps
 # ---------------------------------------------------------------------------
@@ -321,6 +337,14 @@ def copy_bytes(src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None, 
     n = src.numel() * src.element_size() if nbytes is None else nbytes
     check(load().mc_copy_bytes(ctx.handle, _ptr(src), _ptr(dst), n, _stream(stream)),
           "mc_copy_bytes")
+
+
+def gather_ref(idx: torch.Tensor, table: torch.Tensor, out: torch.Tensor, stream=None, ctx=None):
+    """mc_gather_ref: out[i] = table[idx[i] % len(table)] (random-gather reference)."""
+    ctx = ctx or context()
+    check(load().mc_gather_ref(ctx.handle, _ptr(idx), idx.numel(), _ptr(table),
+                               table.element_size(), table.numel(), _ptr(out), _stream(stream)),
+          "mc_gather_ref")
 
 
 # ---------------------------------------------------------------------------

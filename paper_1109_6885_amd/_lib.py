@@ -28,7 +28,7 @@ EXPORTS = [
     "mc_delta_dictionary", "mc_delta_dictionary_scratch", "mc_merge_dictionaries",
     "mc_merge_dictionaries_scratch", "mc_reencode", "mc_merge_batched_bounds",
     "mc_merge_columns_batched", "mc_graph_launch", "mc_graph_destroy", "mc_ctx_set_timing",
-    "mc_ctx_step_times", "mc_copy_bytes",
+    "mc_ctx_step_times", "mc_copy_bytes", "mc_gather_ref", "mc_merge_column_naive",
 ]
 
 
@@ -79,6 +79,7 @@ def load():
         "mc_last_error": (ctypes.c_char_p, []),
         "mc_merge_bounds": (ctypes.c_int, [pin, pu64, pu64, pu64]),
         "mc_merge_column": (ctypes.c_int, [p, pin, pout, p, u64, p]),
+        "mc_merge_column_naive": (ctypes.c_int, [p, pin, pout, p, u64, p]),
         "mc_delta_dictionary": (ctypes.c_int, [p, i32, p, u64, p, p, p, p, u64, p]),
         "mc_delta_dictionary_scratch": (ctypes.c_int, [i32, u64, pu64]),
         "mc_merge_dictionaries": (ctypes.c_int, [p, i32, p, u64, p, p, u64, p, p, p, u64, p, p,
@@ -93,6 +94,7 @@ def load():
         "mc_ctx_set_timing": (ctypes.c_int, [p, ctypes.c_int]),
         "mc_ctx_step_times": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_float)]),
         "mc_copy_bytes": (ctypes.c_int, [p, p, p, u64, p]),
+        "mc_gather_ref": (ctypes.c_int, [p, p, u64, p, u32, u32, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

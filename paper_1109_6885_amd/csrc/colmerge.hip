@@ -15,6 +15,7 @@
 #include "colmerge.h"
 #include "common.hpp"
 #include "merge.hpp"
+#include "naive.hpp"
 #include "repack.hpp"
 #include "sort.hpp"
 
@@ -266,6 +267,11 @@ __global__ __launch_bounds__(256) void k1_merge(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T>)];
     mc::merge_tile<T>(C, smem);
 }
+template <class T>
+__global__ __launch_bounds__(256) void k1_naive(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
+    mc::naive_tile<T>(C, blockIdx.x, smem);
+}
 __global__ __launch_bounds__(256) void k1_xcompact(mc::ColDesc C) {
     mc::xcompact_tile(C, blockIdx.x);
 }
@@ -362,6 +368,32 @@ __global__ __launch_bounds__(256) void kn_repack(Batch B) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
     const uint32_t j = find_col(B, blockIdx.x);
     mc::repack_tile(B.cols[j], blockIdx.x - B.map[j], smem);
+}
+
+// Random-gather reference: out[i] = table[idx[i] % n_table] for 4- or
+// 2-byte entries, 8 independent gathers in flight per thread.  Measures the
+// ceiling of the re-encode's translation-table lookups for a given table
+// footprint, beside the streaming ceiling of k_copy16.
+template <class E>
+__global__ __launch_bounds__(256) void k_gather_ref(const uint32_t *__restrict__ idx, uint64_t n,
+                                                    const E *__restrict__ table, uint32_t n_table,
+                                                    uint32_t *__restrict__ out) {
+    constexpr int kPer = 8;
+    const uint64_t base = (uint64_t)blockIdx.x * 256 * kPer + threadIdx.x;
+    uint32_t v[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint64_t i = base + (uint64_t)j * 256;
+        v[j] = i < n ? idx[i] % n_table : 0u;
+    }
+    uint32_t r[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) r[j] = (uint32_t)table[v[j]];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint64_t i = base + (uint64_t)j * 256;
+        if (i < n) out[i] = r[j];
+    }
 }
 
 int launch_fill(void *p0, uint64_t bytes0, void *p1, uint64_t bytes1, hipStream_t s) {
@@ -471,8 +503,17 @@ int check_out(const mc_column_in *in, const mc_column_out *out) {
 }
 
 template <class T>
+int launch_naive(const mc::ColDesc &C, hipStream_t s) {
+    const uint64_t grid = ceil_div(C.n_main + C.nd, mc::kRepackCodes);
+    if (grid == 0) return MC_OK;
+    hipLaunchKernelGGL(k1_naive<T>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C);
+    MC_LAUNCHED("k1_naive");
+    return MC_OK;
+}
+
+template <class T>
 int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out, char *ws,
-                   const ColLayout &L, hipStream_t s) {
+                   const ColLayout &L, hipStream_t s, bool naive = false) {
     const mc::ColDesc C = make_desc(in, out, ws, ws + L.z_size, L);
     hipEvent_t *ev = nullptr;
     if (ctx->timing) {
@@ -492,7 +533,7 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
     rc = launch_merge<T>(C, L.merge_tiles, s);
     if (rc) return rc;
     if (ev) MC_HIP(hipEventRecord(ev[3], s));
-    rc = launch_repack(C, s);
+    rc = naive ? launch_naive<T>(C, s) : launch_repack(C, s);
     if (rc) return rc;
     if (ev) {
         MC_HIP(hipEventRecord(ev[4], s));
@@ -502,7 +543,7 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
 }
 
 int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out,
-                      void *scratch, uint64_t scratch_bytes, hipStream_t s) {
+                      void *scratch, uint64_t scratch_bytes, hipStream_t s, bool naive = false) {
     if (!ctx) return fail(MC_E_ARG, "null context");
     int rc = check_in(in);
     if (rc) return rc;
@@ -514,9 +555,9 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
     char *ws = static_cast<char *>(scratch);
     switch (in->type) {
-        case MC_U32: return merge_column_t<mc::TU32>(ctx, in, out, ws, L, s);
-        case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, s);
-        default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, s);
+        case MC_U32: return merge_column_t<mc::TU32>(ctx, in, out, ws, L, s, naive);
+        case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, s, naive);
+        default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, s, naive);
     }
 }
 
@@ -700,6 +741,11 @@ int mc_merge_column(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *ou
     return merge_column_impl(ctx, in, out, scratch, scratch_bytes, stream);
 }
 
+int mc_merge_column_naive(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out,
+                          void *scratch, uint64_t scratch_bytes, hipStream_t stream) {
+    return merge_column_impl(ctx, in, out, scratch, scratch_bytes, stream, true);
+}
+
 int mc_delta_dictionary_scratch(int32_t type, uint64_t delta_rows, uint64_t *scratch_bytes) {
     if (value_len(type) == 0) return fail(MC_E_ARG, "unknown value type");
     if (delta_rows >= (1ull << 30)) return fail(MC_E_ARG, "delta_rows must be < 2^30");
@@ -874,6 +920,24 @@ int mc_copy_bytes(mc_ctx *ctx, const void *src, void *dst, uint64_t bytes, hipSt
     hipLaunchKernelGGL(k_copy16, dim3((uint32_t)grid), dim3(256), 0, s,
                        static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), bytes / 16);
     MC_LAUNCHED("k_copy16");
+    return MC_OK;
+}
+
+int mc_gather_ref(mc_ctx *ctx, const uint32_t *idx, uint64_t n, const void *table,
+                  uint32_t entry_bytes, uint32_t n_table, uint32_t *out, hipStream_t s) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    if (entry_bytes != 2 && entry_bytes != 4) return fail(MC_E_ARG, "entry_bytes must be 2 or 4");
+    if (n == 0) return MC_OK;
+    if (!idx || !table || !out || n_table == 0) return fail(MC_E_ARG, "null buffer or empty table");
+    const uint64_t grid = ceil_div(n, 256 * 8);
+    if (grid >= (1ull << 31)) return fail(MC_E_ARG, "too many indices");
+    if (entry_bytes == 4)
+        hipLaunchKernelGGL(k_gather_ref<uint32_t>, dim3((uint32_t)grid), dim3(256), 0, s, idx, n,
+                           static_cast<const uint32_t *>(table), n_table, out);
+    else
+        hipLaunchKernelGGL(k_gather_ref<uint16_t>, dim3((uint32_t)grid), dim3(256), 0, s, idx, n,
+                           static_cast<const uint16_t *>(table), n_table, out);
+    MC_LAUNCHED("k_gather_ref");
     return MC_OK;
 }
 

@@ -69,6 +69,72 @@ __device__ inline void xcompact_tile(const ColDesc &C, uint64_t t) {
     if (bad) atomicOr(C.xflag, 1u);
 }
 
+// Stage the packed main words of the tile starting at row c0 into LDS with
+// 128-bit loads (streamed once: non-temporal, so the tables keep the cache).
+__device__ inline void stage_main_words(const ColDesc &C, uint64_t c0, uint64_t *s_in) {
+    if (c0 >= C.n_main) return;
+    const uint32_t w = C.w;
+    const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
+    const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 32
+    const uint32_t nw = (uint32_t)min<uint64_t>(kRepackCodes / 64 * (uint64_t)w, win - wbase);
+    const uint32_t npair = nw / 2;
+    const u64x2 *src2 = reinterpret_cast<const u64x2 *>(C.main_codes + wbase);
+    u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
+    for (uint32_t x = threadIdx.x; x < npair; x += kBlock) dst2[x] = __builtin_nontemporal_load(src2 + x);
+    if ((nw & 1u) && threadIdx.x == 0)
+        s_in[nw - 1] = __builtin_nontemporal_load(C.main_codes + wbase + nw - 1);
+}
+
+// Code i (tile-local) of the staged main words.
+__device__ __forceinline__ uint32_t decode_code(const uint64_t *s_in, uint32_t i, uint32_t w,
+                                                uint64_t mask) {
+    const uint32_t bit = i * w;
+    const uint32_t wi = bit >> 6, sh = bit & 63u;
+    uint64_t v = s_in[wi] >> sh;
+    if (sh + w > 64) v |= s_in[wi + 1] << (64 - sh);
+    return (uint32_t)(v & mask);
+}
+
+// Assemble the tile's output words from its new codes (s_code, zero past the
+// last row) and store them with 128-bit writes.
+__device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint32_t *s_code,
+                                       uint32_t wn, uint64_t n_out) {
+    // local word k covers tile bits [64k, 64k + 64)
+    const uint64_t obase = t * (uint64_t)(kRepackCodes / 64) * wn;
+    const uint64_t wres = (n_out * wn + 63) / 64;
+    const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
+    const uint32_t nwo = (kRepackCodes / 64) * wn;  // words of a full tile (even)
+    // floor(x / wn) for x < 2^17 as a multiply-high by ceil(2^32 / wn): the
+    // rounding error of the reciprocal times x stays below 2^32, so it is exact
+    const uint32_t rcp = (uint32_t)((0x100000000ull + wn - 1) / wn);
+    for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
+        uint64_t word[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint32_t k = 2 * k2 + h;
+            const uint32_t b0 = 64u * k;
+            uint32_t q = __umulhi(b0, rcp);
+            const uint32_t qe = min<uint32_t>(__umulhi(b0 + 63, rcp), kRepackCodes - 1);
+            uint64_t acc = 0;
+            for (; q <= qe; q++) {
+                const uint64_t c = s_code[q];
+                const int sh = (int)(q * wn) - (int)b0;
+                acc |= sh < 0 ? (c >> (-sh)) : (c << sh);
+            }
+            word[h] = acc;
+        }
+        const uint64_t gw = obase + 2ull * k2;
+        if (gw + 1 < wlim) {
+            u64x2 v;
+            v.x = word[0];
+            v.y = word[1];
+            __builtin_nontemporal_store(v, reinterpret_cast<u64x2 *>(C.out + gw));
+        } else if (gw < wlim) {
+            C.out[gw] = word[0];
+        }
+    }
+}
+
 __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     RepackSmem &S = *reinterpret_cast<RepackSmem *>(smem);
     uint64_t *s_in = S.in;
@@ -82,20 +148,7 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     if (c0 >= n_out) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(kRepackCodes, n_out - c0);
 
-    // stage the main words of this tile (streamed once: non-temporal, so the
-    // translation tables keep the cache)
-    if (c0 < C.n_main) {
-        const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
-        const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 32
-        const uint32_t nw = (uint32_t)min<uint64_t>(kRepackCodes / 64 * (uint64_t)w, win - wbase);
-        const uint32_t npair = nw / 2;
-        const u64x2 *src2 = reinterpret_cast<const u64x2 *>(C.main_codes + wbase);
-        u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
-        for (uint32_t x = threadIdx.x; x < npair; x += kBlock)
-            dst2[x] = __builtin_nontemporal_load(src2 + x);
-        if ((nw & 1u) && threadIdx.x == 0)
-            s_in[nw - 1] = __builtin_nontemporal_load(C.main_codes + wbase + nw - 1);
-    }
+    stage_main_words(C, c0, s_in);
     __syncthreads();
 
     // decode every code of this thread first, then issue all gathers together
@@ -113,11 +166,7 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
         idx[j] = 0;
         if (i < tn) {
             if (g < C.n_main) {
-                const uint32_t bit = i * w;
-                const uint32_t wi = bit >> 6, sh = bit & 63u;
-                uint64_t v = s_in[wi] >> sh;
-                if (sh + w > 64) v |= s_in[wi + 1] << (64 - sh);
-                const uint32_t c = (uint32_t)(v & mask);
+                const uint32_t c = decode_code(s_in, i, w, mask);
                 if (c < C.n_um) {
                     tab[j] = C.x_m;
                     idx[j] = c;
@@ -154,40 +203,7 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     if (bad) flag_error(C.err, bad);
     __syncthreads();
 
-    // assemble output words: local word k covers tile bits [64k, 64k + 64)
-    const uint64_t obase = t * (uint64_t)(kRepackCodes / 64) * wn;
-    const uint64_t wres = (n_out * wn + 63) / 64;
-    const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
-    const uint32_t nwo = (kRepackCodes / 64) * wn;  // words of a full tile (even)
-    // floor(x / wn) for x < 2^17 as a multiply-high by ceil(2^32 / wn): the
-    // rounding error of the reciprocal times x stays below 2^32, so it is exact
-    const uint32_t rcp = (uint32_t)((0x100000000ull + wn - 1) / wn);
-    for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
-        uint64_t word[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const uint32_t k = 2 * k2 + h;
-            const uint32_t b0 = 64u * k;
-            uint32_t q = __umulhi(b0, rcp);
-            const uint32_t qe = min<uint32_t>(__umulhi(b0 + 63, rcp), kRepackCodes - 1);
-            uint64_t acc = 0;
-            for (; q <= qe; q++) {
-                const uint64_t c = s_code[q];
-                const int sh = (int)(q * wn) - (int)b0;
-                acc |= sh < 0 ? (c >> (-sh)) : (c << sh);
-            }
-            word[h] = acc;
-        }
-        const uint64_t gw = obase + 2ull * k2;
-        if (gw + 1 < wlim) {
-            u64x2 v;
-            v.x = word[0];
-            v.y = word[1];
-            __builtin_nontemporal_store(v, reinterpret_cast<u64x2 *>(C.out + gw));
-        } else if (gw < wlim) {
-            C.out[gw] = word[0];
-        }
-    }
+    pack_store_tile(C, t, s_code, wn, n_out);
 }
 
 }  // namespace mc

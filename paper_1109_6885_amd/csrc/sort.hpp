@@ -27,11 +27,11 @@ namespace mc {
 template <class T>
 struct SortCfg;
 template <>
-struct SortCfg<TU32> { static constexpr int kItems = 16; };
+struct SortCfg<TU32> { static constexpr int kItems = 8; };
 template <>
-struct SortCfg<TU64> { static constexpr int kItems = 12; };
+struct SortCfg<TU64> { static constexpr int kItems = 8; };
 template <>
-struct SortCfg<TS16> { static constexpr int kItems = 8; };
+struct SortCfg<TS16> { static constexpr int kItems = 6; };
 
 template <class T>
 __host__ __device__ constexpr int sort_tile() { return kBlock * SortCfg<T>::kItems; }

@@ -271,3 +271,15 @@ def test_skewed_new_values(where):
     col = gen.Column("u64", u_m, gen.pack_codes(codes, 12), 70_000, 12, delta)
     say(f"case skewed {where}")
     assert_same(gpu_merge(col), ora_merge(col))
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+def test_naive_step2_matches_oracle(vtype):
+    """The unoptimized Step 2(b) (binary search in U', Section 5.2) gives
+    the same bytes as the translation-table route and the oracle."""
+    rng = np.random.default_rng(31)
+    col = gen.random_column(rng, vtype, 5000, 100_003, 20_011, 0.5)
+    say(f"case naive {vtype}")
+    out = cm.merge_column_naive(cm.ColumnInput.from_numpy(col), tables=True)
+    torch.cuda.synchronize()
+    assert_same(out.fetch(), ora_merge(col))
