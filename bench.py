@@ -22,6 +22,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
+# Files whose contents define the re-encode kernel; the committed byte-counter
+# profile records their hash, and its traffic figure is reported only while
+# the kernel is unchanged.
+REENCODE_SOURCES = ["paper_1109_6885_amd/csrc/repack.hpp", "paper_1109_6885_amd/csrc/common.hpp"]
+TRAFFIC_PROFILE = "profiles/k1_repack_c2_u64_100M_hbm_bytes.md"
+
+
+def reencode_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in REENCODE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the re-encode kernel from the committed
+    FETCH_SIZE / WRITE_SIZE profile, if it was taken on the current source."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    src, nbytes = None, None
+    for line in open(path):
+        if line.startswith("source_sha256:"):
+            src = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            nbytes = float(line.split(":", 1)[1].strip())
+    return nbytes if src == reencode_source_hash() else None
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -285,6 +315,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3],
+                    help="single-column workload (2 is the reported one; 1 and 3 for profiling)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 300-column batched vs plain comparison")
     ap.add_argument("--gen-workers", type=int, default=16,
@@ -325,8 +357,8 @@ def main():
 
     # inputs first: the generator's worker processes start before the GPU is used
     t = time.time()
-    col = gen.config_column(2)
-    log(f"generated c2 in {time.time() - t:.1f}s")
+    col = gen.config_column(args.config)
+    log(f"generated config {args.config} in {time.time() - t:.1f}s")
     bcols = None
     if not args.no_batched:
         t = time.time()
@@ -422,7 +454,8 @@ def main():
         import oracle
         oracle.build(force=False)
         t = time.perf_counter()
-        ref = oracle.merge_column("u64", col.u_m, col.main_packed, col.n_main, col.w, col.delta)
+        ref = oracle.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w,
+                                  col.delta)
         dt = time.perf_counter() - t
         assert ref["n_new"] == sc["n_new"]
         cpu = {"value": n_out / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
@@ -440,10 +473,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": col.vtype,
         "data": "synthetic (seeded numpy PCG64)",
-        "config": {"workload": "single u64 column: 100M main rows at 20 bits, 1,048,000-entry "
-                               "dictionary, 1M delta rows (90% new) -> 1,948,000 entries at 21 bits",
+        "config": {"workload": gen.CONFIG_NAMES[args.config],
                    "main_rows": col.n_main, "delta_rows": col.n_delta,
                    "dict": int(col.u_m.shape[0]), "w": col.w, "w_new": sc["w_new"],
                    "new_dict": sc["n_new"]},
@@ -454,7 +486,8 @@ def main():
                     "reencode": steps_ms[3], "whole": steps_ms[4]},
         "roofline": {"kernel": "k_repack (Step 2(b))", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": b_re},
+                     "traffic": measured_traffic() if args.config == 2 else None,
+                     "bytes_per_launch": b_re},
         "copy_kernel_gbs": copy_gbs,
         "gather_ref_us": {"rows": col.n_main, "table_entries": int(col.u_m.shape[0]),
                           "u32_table": gather_us[4], "u16_table": gather_us[2],
