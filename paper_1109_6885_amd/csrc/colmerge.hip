@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int p) {
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem)];
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<T>)];
     mc::emit_tile<T>(C, smem);
 }
 template <class T>
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void kn_sort_down(Batch B, int p) {
     MC_DISPATCH(C, mc::sort_down_tile, C, p, blockIdx.x - B.map[j], smem);
 }
 __global__ __launch_bounds__(256) void kn_emit(Batch B) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem)];
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::emit_tile, C, smem);

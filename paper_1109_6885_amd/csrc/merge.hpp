@@ -49,6 +49,40 @@ __device__ __forceinline__ uint64_t co_rank(uint64_t k, uint64_t a, uint64_t b, 
     return lo;
 }
 
+// The same co-rank found by one wave in about log64 rounds: each round the
+// 64 lanes test 64 evenly spaced candidates of the remaining range at once
+// (the predicate "A[i] <= B[k-1-i]" is true below the answer and false from
+// it on), and the ballot narrows the range to one step.  Every lane returns
+// the answer.  Used for the tile boundaries, where the arrays are in global
+// memory and a sequential search would wait on ~20 dependent loads.
+template <class T, class GetA, class GetB>
+__device__ __forceinline__ uint64_t co_rank_wave(uint64_t k, uint64_t a, uint64_t b, GetA A,
+                                                 GetB B) {
+    uint64_t lo = k > b ? k - b : 0;
+    uint64_t hi = k < a ? k : a;  // answer in [lo, hi]
+    const int lane = lane_id();
+    while (hi > lo) {
+        const uint64_t span = hi - lo;  // candidates lo .. hi-1
+        // lane l tests candidate lo + floor(span * (l + 1) / 65)  (< hi)
+        const uint64_t step = span / 65, rem = span % 65;
+        const uint64_t cand = lo + step * (lane + 1) + (rem * (lane + 1)) / 65;
+        bool pred = false;  // true: the answer lies above cand
+        if (cand < hi) pred = T::le(A(cand), B(k - 1 - cand));
+        const uint64_t yes = __ballot(pred);
+        // predicate is monotone in cand: the lanes that say "above" form a prefix
+        const int nyes = __popcll(yes);
+        const uint64_t new_lo = nyes ? (lo + step * nyes + (rem * nyes) / 65) + 1 : lo;
+        const uint64_t new_hi = nyes < 64 ? lo + step * (nyes + 1) + (rem * (nyes + 1)) / 65 : hi;
+        lo = new_lo;
+        hi = new_hi < hi ? new_hi : hi;
+        if (span <= 64) {
+            // every candidate was tested: lo is the answer
+            hi = lo;
+        }
+    }
+    return lo;
+}
+
 template <class T>
 __device__ void merge_tile(const ColDesc &C, char *smem) {
     MergeSmem<T> &S = *reinterpret_cast<MergeSmem<T> *>(smem);
@@ -72,8 +106,13 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     const uint64_t k1 = min(k0 + kMergeTile, total);
     auto gA = [&](uint64_t i) { return T::norm(T::load(C.u_m, i)); };
     auto gB = [&](uint64_t j) { return T::norm(T::load(C.u_d, j)); };
-    if (threadIdx.x == 0) S.i0 = co_rank<T>(k0, a, b, gA, gB);
-    if (threadIdx.x == 64) S.i1 = co_rank<T>(k1, a, b, gA, gB);
+    if (wave_id() == 0) {
+        const uint64_t r = co_rank_wave<T>(k0, a, b, gA, gB);
+        if (lane_id() == 0) S.i0 = r;
+    } else if (wave_id() == 1) {
+        const uint64_t r = co_rank_wave<T>(k1, a, b, gA, gB);
+        if (lane_id() == 0) S.i1 = r;
+    }
     __syncthreads();
     const uint64_t i0 = S.i0, i1 = S.i1;
     const uint64_t j0 = k0 - i0, j1 = k1 - i1;

@@ -256,7 +256,9 @@ __device__ void sort_down_tile(const ColDesc &C, int p, uint32_t t, char *smem) 
 constexpr int kEmitItems = 8;
 constexpr int kEmitTile = kBlock * kEmitItems;
 
+template <class T>
 struct EmitSmem {
+    typename T::K keys[kEmitTile + 1];  // keys[0]: the value before the tile
     uint32_t tile;
     uint32_t tmp[kWaves];
     uint64_t prefix;
@@ -265,27 +267,32 @@ struct EmitSmem {
 template <class T>
 __device__ void emit_tile(const ColDesc &C, char *smem) {
     typedef typename T::K K;
-    EmitSmem &S = *reinterpret_cast<EmitSmem *>(smem);
+    EmitSmem<T> &S = *reinterpret_cast<EmitSmem<T> *>(smem);
     constexpr int P = T::kBytes;
     const void *keys = kbuf(C, P - 1);  // sorted values after the last pass
     const uint32_t *rows = vbuf(C, P - 1);
     if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[0], 1u);
     __syncthreads();
     const uint32_t t = S.tile;
-    const uint64_t i0 = (uint64_t)t * kEmitTile + (uint64_t)threadIdx.x * kEmitItems;
+    const uint64_t tb = (uint64_t)t * kEmitTile;
+    // coalesced staging of the tile (and its predecessor value) in LDS
+    for (uint32_t x = threadIdx.x; x <= (uint32_t)kEmitTile; x += kBlock) {
+        const uint64_t i = tb + x;  // LDS slot x holds sorted position i - 1
+        if (i >= 1 && i - 1 < C.nd) S.keys[x] = T::load(keys, i - 1);
+    }
+    __syncthreads();
+    const uint64_t i0 = tb + (uint64_t)threadIdx.x * kEmitItems;
+    const uint32_t l0 = threadIdx.x * kEmitItems;
 
     K k[kEmitItems];
     uint32_t head = 0;  // bit j: position i0 + j starts a new value
-    K prev;
-    if (i0 > 0 && i0 < C.nd) prev = T::load(keys, i0 - 1);
 #pragma unroll
     for (int j = 0; j < kEmitItems; j++) {
         const uint64_t i = i0 + j;
         if (i < C.nd) {
-            k[j] = T::load(keys, i);
-            const bool h = (i == 0) || !T::keq(k[j], prev);
+            k[j] = S.keys[l0 + j + 1];
+            const bool h = (i == 0) || !T::keq(k[j], S.keys[l0 + j]);
             head |= (uint32_t)h << j;
-            prev = k[j];
         }
     }
     const uint32_t cnt = __popc(head);
