@@ -241,6 +241,61 @@ struct ColDesc {
     uint32_t *xflag;           // nonzero: a compact entry overflowed, use x_m (zeroed)
 };
 
+// The same prefix with the whole workgroup looking back: each round the 256
+// threads read the statuses of the 256 nearest unvisited predecessors at
+// once, so a tile far from the last published inclusive prefix needs
+// (distance / 256) rounds instead of (distance / 64).  Every thread of the
+// block must call it; every thread gets the exclusive prefix.  s_u64 needs
+// kWaves + 1 entries and s_i32 kWaves entries of LDS.
+__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t tile, uint64_t agg,
+                                          uint32_t *err, uint64_t *s_u64, int *s_i32) {
+    if (tile == 0) {
+        if (threadIdx.x == 0) st_rel(&status[0], kFlagPre | agg);
+        return 0;
+    }
+    if (threadIdx.x == 0) st_rel(&status[tile], kFlagAgg | agg);
+    const int lane = lane_id(), wv = wave_id();
+    uint64_t prefix = 0;
+    int64_t base = (int64_t)tile - 1;
+    while (true) {
+        const int64_t t = base - (int64_t)threadIdx.x;  // thread 0: nearest predecessor
+        uint64_t s = kFlagPre;                         // before tile 0: zero prefix
+        if (t >= 0) {
+            uint32_t spins = 0;
+            s = ld_acq(&status[t]);
+            while ((s >> 62) == 0) {
+                if (++spins > kSpinLimit) {
+                    flag_error(err, MC_DEVERR_SPIN);
+                    s = kFlagPre;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                s = ld_acq(&status[t]);
+            }
+        }
+        // nearest predecessor (smallest thread index) holding an inclusive prefix
+        const uint64_t pre = __ballot((s & kFlagPre) != 0);
+        if (lane == 0) s_i32[wv] = pre ? wv * 64 + (__ffsll((long long)pre) - 1) : kBlock;
+        __syncthreads();
+        int stop = kBlock;
+#pragma unroll
+        for (int x = 0; x < kWaves; x++) stop = min(stop, s_i32[x]);
+        const uint64_t v = (int)threadIdx.x <= stop ? (s & kValMask) : 0;
+        const uint64_t ws = wave_sum(v);
+        if (lane == 0) s_u64[wv] = ws;
+        __syncthreads();
+        uint64_t round = 0;
+#pragma unroll
+        for (int x = 0; x < kWaves; x++) round += s_u64[x];
+        prefix += round;
+        __syncthreads();  // s_i32 / s_u64 are reused next round
+        if (stop < kBlock) break;
+        base -= kBlock;
+    }
+    if (threadIdx.x == 0) st_rel(&status[tile], kFlagPre | (prefix + agg));
+    return prefix;
+}
+
 // Code width for a dictionary of n entries: ceil(log2 n), at least 1.
 __device__ __host__ inline uint32_t code_width(uint64_t n) {
     uint32_t w = 1;

@@ -31,7 +31,9 @@ struct MergeSmem {
     typename T::N b[kMergeTile];
     uint32_t tile;
     uint32_t tmp[kWaves];
-    uint64_t i0, i1, prefix;
+    uint64_t i0, i1;
+    uint64_t lb64[kWaves + 1];
+    int lb32[kWaves];
 };
 
 // Number of U_M entries among the first k merged elements (ties: U_M first).
@@ -154,14 +156,10 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);
-    if (wave_id() == 0) {
-        const uint64_t pre = lookback_wave(C.merge_status, t, tot, C.err);
-        if (lane_id() == 0) S.prefix = pre;
-    }
-    __syncthreads();
+    const uint64_t tile_prefix = lookback_block(C.merge_status, t, tot, C.err, S.lb64, S.lb32);
 
     // pass 2: write U', X_M and X_D
-    uint64_t pos = S.prefix + ex;
+    uint64_t pos = tile_prefix + ex;
     {
         uint32_t ia = ia0, jb = jb0;
         for (uint32_t d = d0; d < d1; d++) {
@@ -185,7 +183,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
         }
     }
     if (threadIdx.x == 0 && k1 == total) {
-        const uint64_t n = S.prefix + tot;
+        const uint64_t n = tile_prefix + tot;
         const uint32_t w = code_width(n);
         C.result->new_dict_len = n;
         C.result->new_bitwidth = w;

@@ -261,7 +261,8 @@ struct EmitSmem {
     typename T::K keys[kEmitTile + 1];  // keys[0]: the value before the tile
     uint32_t tile;
     uint32_t tmp[kWaves];
-    uint64_t prefix;
+    uint64_t lb64[kWaves + 1];
+    int lb32[kWaves];
 };
 
 template <class T>
@@ -298,12 +299,8 @@ __device__ void emit_tile(const ColDesc &C, char *smem) {
     const uint32_t cnt = __popc(head);
     uint32_t tot;
     const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);
-    if (wave_id() == 0) {
-        const uint64_t pre = lookback_wave(C.emit_status, t, tot, C.err);
-        if (lane_id() == 0) S.prefix = pre;
-    }
-    __syncthreads();
-    uint64_t idx = S.prefix + ex;  // heads seen so far, over the whole array
+    const uint64_t tile_prefix = lookback_block(C.emit_status, t, tot, C.err, S.lb64, S.lb32);
+    uint64_t idx = tile_prefix + ex;  // heads seen so far, over the whole array
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < kEmitItems; j++) {
@@ -323,7 +320,7 @@ __device__ void emit_tile(const ColDesc &C, char *smem) {
     if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
     const uint64_t tile_end = (uint64_t)(t + 1) * kEmitTile;
     if (threadIdx.x == 0 && tile_end >= C.nd && (uint64_t)t * kEmitTile < C.nd)
-        *C.n_ud = S.prefix + tot;
+        *C.n_ud = tile_prefix + tot;
 }
 
 }  // namespace mc
