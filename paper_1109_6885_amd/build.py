@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libcolmerge.so")
 SRC = os.path.join(PKG, "csrc", "colmerge.hip")
-HEADERS = [os.path.join(PKG, "csrc", f) for f in ("common.hpp", "sort.hpp", "merge.hpp", "repack.hpp", "naive.hpp")]
+HEADERS = [os.path.join(PKG, "csrc", f) for f in ("common.hpp", "sort.hpp", "merge.hpp", "repack.hpp", "naive.hpp", "hash.hpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -14,6 +14,7 @@
 
 #include "colmerge.h"
 #include "common.hpp"
+#include "hash.hpp"
 #include "merge.hpp"
 #include "naive.hpp"
 #include "repack.hpp"
@@ -107,17 +108,34 @@ struct Carver {
 struct ColLayout {
     // part Z
     uint64_t counters = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0, emit_status = 0,
-             merge_status = 0, z_size = 0;
+             merge_status = 0, dcount = 0, hstatus = 0, htab = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
-             drank = 0, x_d = 0, x_m = 0, xdev = 0, b_size = 0;
+             drank = 0, x_d = 0, x_m = 0, xdev = 0, rep = 0, dindex = 0, dkeys = 0, drankd = 0,
+             b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
+    bool hashed = false;       // Step 1(a) deduplicates by hashing first
+    uint64_t hmask = 0;
+    uint32_t hash_tiles = 0;
 };
 
-ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) {
+// Deltas with at least this many rows take the hashing route of Step 1(a):
+// the radix passes then only see distinct values.  Smaller deltas sort
+// directly (their passes are latency-bound, and hashing would add work).
+constexpr uint64_t kHashMinRows = 1ull << 21;
+
+ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
+                     bool allow_hash = true) {
     ColLayout L;
     const uint32_t E = value_len(type);
+    L.hashed = allow_hash && nd >= kHashMinRows;
+    if (L.hashed) {
+        uint64_t h = 1024;
+        while (h < 2 * nd) h <<= 1;
+        L.hmask = h - 1;
+        L.hash_tiles = (uint32_t)ceil_div(nd, mc::kHashTile);
+    }
     L.passes = E;  // one 8-bit digit per value byte
     L.sort_tiles = (uint32_t)ceil_div(nd, sort_tile_of(type));
     L.emit_tiles = (uint32_t)ceil_div(nd, mc::kEmitTile);
@@ -134,6 +152,11 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) 
     L.trivial = z.take(16 * 4);
     L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
     L.merge_status = z.take(L.merge_tiles * 8);
+    if (L.hashed) {
+        L.dcount = z.take(8);
+        L.hstatus = z.take(ceil_div(nd, mc::kCompactTile) * 8);
+        L.htab = z.take((L.hmask + 1) * 4);
+    }
     L.z_size = z.size();
     Carver b;
     L.base = b.take((uint64_t)L.passes * 256 * 4);
@@ -147,11 +170,34 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main) 
     L.x_d = b.take(nd * 4);
     L.x_m = b.take(n_um * 4);
     L.xdev = b.take(n_um * 2);
+    if (L.hashed) {
+        L.rep = b.take(nd * 4);
+        L.dindex = b.take(nd * 4);
+        L.dkeys = b.take(nd * E);
+        L.drankd = b.take(nd * 4);
+    }
     L.b_size = b.size();
     return L;
 }
 
 uint64_t single_scratch(const ColLayout &L) { return L.z_size + L.b_size; }
+
+// Step 1(a) fields for the hashing route (or the plain radix route).
+void set_hash_fields(mc::ColDesc &C, char *za, char *zb, const ColLayout &L) {
+    C.sort_src = C.delta;
+    C.sort_n = nullptr;
+    if (!L.hashed) return;
+    C.htab = reinterpret_cast<uint32_t *>(za + L.htab);
+    C.hmask = L.hmask;
+    C.rep = reinterpret_cast<uint32_t *>(zb + L.rep);
+    C.dindex = reinterpret_cast<uint32_t *>(zb + L.dindex);
+    C.dkeys = zb + L.dkeys;
+    C.drankd = reinterpret_cast<uint32_t *>(zb + L.drankd);
+    C.dcount = reinterpret_cast<uint64_t *>(za + L.dcount);
+    C.hstatus = reinterpret_cast<uint64_t *>(za + L.hstatus);
+    C.sort_src = C.dkeys;
+    C.sort_n = C.dcount;
+}
 
 // Descriptor of one column with its workspace at za (part Z) and zb (part B).
 mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za, char *zb,
@@ -194,6 +240,7 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.drank = reinterpret_cast<uint32_t *>(zb + L.drank);
     C.xdev = L.xc_tiles ? reinterpret_cast<int16_t *>(zb + L.xdev) : nullptr;
     C.xflag = reinterpret_cast<uint32_t *>(za + L.xflag);
+    set_hash_fields(C, za, zb, L);
     return C;
 }
 
@@ -261,6 +308,22 @@ template <class T>
 __global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<T>)];
     mc::emit_tile<T>(C, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_hash_insert(mc::ColDesc C) {
+    mc::hash_insert_tile<T>(C, blockIdx.x);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_compact(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::CompactSmem)];
+    mc::compact_tile<T>(C, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_emit_distinct(mc::ColDesc C) {
+    mc::emit_distinct_tile<T>(C, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k1_rank_rows(mc::ColDesc C) {
+    mc::rank_rows_tile(C, blockIdx.x);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_merge(mc::ColDesc C) {
@@ -417,6 +480,13 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
         if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
         return MC_OK;
     }
+    if (L.hashed) {
+        hipLaunchKernelGGL(k1_hash_insert<T>, dim3(L.hash_tiles), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_hash_insert");
+        hipLaunchKernelGGL(k1_compact<T>, dim3((uint32_t)ceil_div(C.nd, mc::kCompactTile)),
+                           dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_compact");
+    }
     hipLaunchKernelGGL(k1_hist<T>, dim3(L.hist_tiles), dim3(mc::kBlock), 0, s, C);
     MC_LAUNCHED("k1_hist");
     hipLaunchKernelGGL(k1_hist_scan<T>, dim3(1), dim3(mc::kBlock), 0, s, C);
@@ -430,6 +500,13 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
         MC_LAUNCHED("k1_sort_down");
     }
     if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
+    if (L.hashed) {
+        hipLaunchKernelGGL(k1_emit_distinct<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_emit_distinct");
+        hipLaunchKernelGGL(k1_rank_rows, dim3(L.hash_tiles), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_rank_rows");
+        return MC_OK;
+    }
     hipLaunchKernelGGL(k1_emit<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
     MC_LAUNCHED("k1_emit");
     return MC_OK;
@@ -591,7 +668,7 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P) {
         int rc = check_in(&ins[i]);
         if (rc) return rc;
         P.L[i] = col_layout(ins[i].type, ins[i].main_dict_len, ins[i].delta_rows,
-                            ins[i].main_rows);
+                            ins[i].main_rows, /*allow_hash=*/false);
         P.z_off[i] = z;
         z += P.L[i].z_size;
         P.b_off[i] = b;
@@ -789,6 +866,7 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     C.nd_max = delta_rows;
     C.u_d = u_d;
     C.drank = drank;
+    set_hash_fields(C, za, zb, L);
     int rc = launch_fill(za, L.z_size, d_count, 8, s);
     if (rc) return rc;
     switch (type) {

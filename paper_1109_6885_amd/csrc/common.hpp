@@ -239,6 +239,17 @@ struct ColDesc {
     uint32_t *drank;           // index in U_D of every delta row
     int16_t *xdev;             // compact X_M (see repack.hpp), n_um entries, or null
     uint32_t *xflag;           // nonzero: a compact entry overflowed, use x_m (zeroed)
+    // Step 1(a) by hashing first (see hash.hpp); unused when htab is null
+    const void *sort_src;      // input of radix pass 0 (delta, or the distinct values)
+    const uint64_t *sort_n;    // device count of values to sort, or null for nd
+    uint32_t *htab;            // open-addressing table of representative rows + 1 (zeroed)
+    uint64_t hmask;            // table size - 1 (power of two >= 2 * nd)
+    uint32_t *rep;             // representative row of every delta row
+    uint32_t *dindex;          // position of a representative in the distinct list
+    void *dkeys;               // distinct values, in row order of their representatives
+    uint32_t *drankd;          // rank in U_D of every distinct value (by distinct position)
+    uint64_t *dcount;          // number of distinct values (zeroed)
+    uint64_t *hstatus;         // prefix words of the compaction (zeroed)
 };
 
 // The same prefix with the whole workgroup looking back: each round the 256

@@ -1,0 +1,159 @@
+// hash.hpp -- Step 1(a) for large deltas: deduplicate by hashing first, then
+// radix-sort only the distinct values (Sections 5.1 and 5.3 ask for the
+// sorted unique delta values and every row's index among them; the paper
+// gets them from its CSB+ tree, which holds each value once).
+//
+//   hash_insert_tile   every row finds or claims its value's slot in an
+//                      open-addressing table; the claiming row is the
+//                      value's representative (rep[row] = representative)
+//   compact_tile       representatives, in row order, become the distinct
+//                      list (dkeys) with a cross-tile prefix; dindex[rep] is a
+//                      representative's position in it; *dcount = its length
+//   (radix passes over dkeys, count read on the device)
+//   emit_distinct_tile sorted position i holds distinct value i of U_D;
+//                      drankd[distinct position] = i
+//   rank_rows_tile     drank[row] = drankd[dindex[rep[row]]]
+//
+// A slot holds (representative row + 1) and is written once, by one
+// compare-and-swap from zero, so a plain load that sees a nonzero slot sees
+// its final value; a stale zero only leads to a failing compare-and-swap
+// that returns the real value.  Probing is linear and bounded by the table
+// size, which is a power of two of at least twice the rows.
+#pragma once
+
+#include "sort.hpp"
+
+namespace mc {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    // finalizer of a 64-bit multiplicative hash (xor-shift / multiply rounds)
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+__device__ __forceinline__ uint64_t hash_key(uint32_t k) { return mix64(k); }
+__device__ __forceinline__ uint64_t hash_key(uint64_t k) { return mix64(k); }
+__device__ __forceinline__ uint64_t hash_key(Raw16 k) { return mix64(k.a ^ mix64(k.b)); }
+
+constexpr int kHashItems = 8;
+constexpr int kHashTile = kBlock * kHashItems;
+
+template <class T>
+__device__ void hash_insert_tile(const ColDesc &C, uint64_t t) {
+    typedef typename T::K K;
+    bool overflow = false;
+    for (int j = 0; j < kHashItems; j++) {
+        const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+        if (row >= C.nd) break;
+        const K key = T::load(C.delta, row);
+        uint64_t h = hash_key(key) & C.hmask;
+        uint32_t rep = (uint32_t)row;
+        bool found = false;
+        for (uint64_t probe = 0; probe <= C.hmask; probe++) {
+            uint32_t s = C.htab[h];
+            if (s == 0) {
+                s = atomicCAS(&C.htab[h], 0u, (uint32_t)row + 1u);
+                if (s == 0) {  // claimed: this row represents its value
+                    found = true;
+                    break;
+                }
+            }
+            const uint32_t r = s - 1u;
+            if (T::keq(T::load(C.delta, r), key)) {
+                rep = r;
+                found = true;
+                break;
+            }
+            h = (h + 1) & C.hmask;
+        }
+        if (!found) overflow = true;
+        C.rep[row] = rep;
+    }
+    if (overflow) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+}
+
+struct CompactSmem {
+    uint32_t tile;
+    uint32_t tmp[kWaves];
+    uint64_t lb64[kWaves + 1];
+    int lb32[kWaves];
+};
+
+constexpr int kCompactItems = 8;
+constexpr int kCompactTile = kBlock * kCompactItems;
+
+template <class T>
+__device__ void compact_tile(const ColDesc &C, char *smem) {
+    CompactSmem &S = *reinterpret_cast<CompactSmem *>(smem);
+    if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[2], 1u);
+    __syncthreads();
+    const uint32_t t = S.tile;
+    const uint64_t r0 = (uint64_t)t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+    uint32_t flags = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactItems; j++) {
+        const uint64_t row = r0 + j;
+        if (row < C.nd && C.rep[row] == (uint32_t)row) flags |= 1u << j;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan((uint32_t)__popc(flags), S.tmp, &tot);
+    const uint64_t pre = lookback_block(C.hstatus, t, tot, C.err, S.lb64, S.lb32);
+    uint64_t pos = pre + ex;
+#pragma unroll
+    for (int j = 0; j < kCompactItems; j++) {
+        if ((flags >> j) & 1u) {
+            const uint64_t row = r0 + j;
+            T::store(C.dkeys, pos, T::load(C.delta, row));
+            C.dindex[row] = (uint32_t)pos;
+            pos++;
+        }
+    }
+    const uint64_t tb = (uint64_t)t * kCompactTile;
+    if (threadIdx.x == 0 && tb < C.nd && tb + kCompactTile >= C.nd) *C.dcount = pre + tot;
+}
+
+// After the radix passes over the distinct values: every sorted position
+// starts a new value.
+template <class T>
+__device__ void emit_distinct_tile(const ColDesc &C, uint64_t t) {
+    constexpr int P = T::kBytes;
+    const void *keys = kbuf(C, P - 1);
+    const uint32_t *rows = vbuf(C, P - 1);
+    const uint64_t n = sort_n(C);
+    bool bad = false;
+    for (uint32_t x = threadIdx.x; x < (uint32_t)kEmitTile; x += kBlock) {
+        const uint64_t i = t * kEmitTile + x;
+        if (i >= n) break;
+        T::store(C.u_d, i, T::load(keys, i));
+        const uint32_t d = rows[i];
+        if (d < n)
+            C.drankd[d] = (uint32_t)i;
+        else
+            bad = true;
+    }
+    if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+    if (t == 0 && threadIdx.x == 0) *C.n_ud = n;
+}
+
+__device__ inline void rank_rows_tile(const ColDesc &C, uint64_t t) {
+    const uint64_t n = sort_n(C);
+    bool bad = false;
+    for (int j = 0; j < kHashItems; j++) {
+        const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+        if (row >= C.nd) break;
+        const uint32_t r = C.rep[row];
+        const uint32_t d = r < C.nd ? C.dindex[r] : 0xffffffffu;
+        if (d < n) {
+            C.drank[row] = C.drankd[d];
+        } else {
+            C.drank[row] = 0;
+            bad = true;
+        }
+    }
+    if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+}
+
+}  // namespace mc

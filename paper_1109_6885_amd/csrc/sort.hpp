@@ -42,7 +42,12 @@ constexpr int kHistChunk = 4096;  // delta values per workgroup in hist_tile
 __device__ __forceinline__ void *kbuf(const ColDesc &C, int i) { return (i & 1) ? C.keys1 : C.keys0; }
 __device__ __forceinline__ uint32_t *vbuf(const ColDesc &C, int i) { return (i & 1) ? C.vals1 : C.vals0; }
 __device__ __forceinline__ const void *pass_src(const ColDesc &C, int p) {
-    return p == 0 ? C.delta : kbuf(C, p - 1);
+    return p == 0 ? C.sort_src : kbuf(C, p - 1);
+}
+// Number of values the radix passes sort: the delta rows, or the distinct
+// values counted on the device when Step 1(a) hashes first.
+__device__ __forceinline__ uint64_t sort_n(const ColDesc &C) {
+    return C.sort_n ? min<uint64_t>(*C.sort_n, C.nd) : C.nd;
 }
 
 // ---- LDS layouts -------------------------------------------------------------
@@ -69,10 +74,11 @@ __device__ void hist_tile(const ColDesc &C, uint32_t blk, char *smem) {
     for (int i = threadIdx.x; i < P * 256; i += kBlock) S.h[i] = 0;
     __syncthreads();
     const uint64_t b0 = (uint64_t)blk * kHistChunk;
+    const uint64_t n = sort_n(C);
     for (uint32_t j = threadIdx.x; j < kHistChunk; j += kBlock) {
         const uint64_t i = b0 + j;
-        if (i < C.nd) {
-            typename T::K k = T::load(C.delta, i);
+        if (i < n) {
+            typename T::K k = T::load(C.sort_src, i);
 #pragma unroll
             for (int p = 0; p < P; p++) atomicAdd(&S.h[p * 256 + T::digit(k, p)], 1u);
         }
@@ -86,12 +92,13 @@ template <class T>
 __device__ void hist_scan_col(const ColDesc &C, char *smem) {
     constexpr int P = T::kBytes;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
+    const uint64_t n = sort_n(C);
     for (int p = 0; p < P; p++) {
         const uint32_t v = C.gh[p * 256 + threadIdx.x];
         uint32_t tot;
         const uint32_t ex = block_excl_scan(v, tmp, &tot);
         C.base[p * 256 + threadIdx.x] = ex;
-        if (v == C.nd) C.trivial[p] = 1u;
+        if (v == n) C.trivial[p] = 1u;
     }
 }
 
@@ -106,10 +113,11 @@ __device__ void sort_up_tile(const ColDesc &C, int p, uint32_t t, char *smem) {
     __syncthreads();
     const uint64_t b0 = (uint64_t)t * TILE;
     const void *src = pass_src(C, p);
+    const uint64_t n = sort_n(C);
 #pragma unroll 4
     for (int j = 0; j < SortCfg<T>::kItems; j++) {
         const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
-        if (i < C.nd) atomicAdd(&h[T::digit(T::load(src, i), p)], 1u);
+        if (i < n) atomicAdd(&h[T::digit(T::load(src, i), p)], 1u);
     }
     __syncthreads();
     C.tcount[(uint64_t)threadIdx.x * C.sort_tiles + t] = h[threadIdx.x];
@@ -156,7 +164,9 @@ __device__ void sort_down_tile(const ColDesc &C, int p, uint32_t t, char *smem) 
     DownSmem<T> &S = *reinterpret_cast<DownSmem<T> *>(smem);
 
     const uint64_t b0 = (uint64_t)t * TILE;
-    const uint32_t tn = (uint32_t)min<uint64_t>(TILE, C.nd - b0);
+    const uint64_t n = sort_n(C);
+    if (b0 >= n) return;  // only when hashing left fewer values than rows
+    const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - b0);
     const void *src = pass_src(C, p);
     const uint32_t *vsrc = p == 0 ? nullptr : vbuf(C, p - 1);
     void *kdst = kbuf(C, p);
@@ -241,7 +251,7 @@ __device__ void sort_down_tile(const ColDesc &C, int p, uint32_t t, char *smem) 
         const K k = S.keys[i];
         const uint32_t d = T::digit(k, p);
         const uint64_t pos = (uint64_t)S.gpos[d] + (i - S.dex[d]);
-        if (pos < C.nd) {  // always true for consistent counts; never write outside
+        if (pos < n) {  // always true for consistent counts; never write outside
             T::store(kdst, pos, k);
             vdst[pos] = S.vals[i];
         } else {

@@ -283,3 +283,30 @@ def test_naive_step2_matches_oracle(vtype):
     out = cm.merge_column_naive(cm.ColumnInput.from_numpy(col), tables=True)
     torch.cuda.synchronize()
     assert_same(out.fetch(), ora_merge(col))
+
+
+@pytest.mark.parametrize("vtype,frac_new,pool", [("u64", 0.3, 50_000), ("str16", 0.3, 300_000),
+                                                  ("u32", 1.0, None), ("u64", 0.0, None)])
+def test_hash_route_large_delta(vtype, frac_new, pool):
+    """Deltas of 2^21 rows and more deduplicate by hashing before the radix
+    passes: heavy duplicates, all-distinct and all-old deltas."""
+    rng = np.random.default_rng(4242)
+    nd = (1 << 21) + 12_345
+    say(f"case hash route {vtype} frac_new={frac_new} pool={pool}")
+    col = gen.random_column(rng, vtype, 200_000, 300_000, nd, frac_new, zipf_s=1.1 if pool else None,
+                            new_pool=pool)
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+def test_hash_route_step_entry():
+    rng = np.random.default_rng(4243)
+    vals = gen.random_values(rng, "u64", 40_000)
+    delta = vals[rng.integers(0, 40_000, (1 << 21) + 3)]
+    say("case hash route delta dictionary entry")
+    u_d, drank, cnt = cm.delta_dictionary("u64", cm.to_device(delta))
+    torch.cuda.synchronize()
+    ref_ud, ref_drank = oracle.delta_dictionary("u64", delta)
+    n = int(cnt[0].item())
+    assert n == ref_ud.shape[0]
+    assert np.array_equal(u_d[:n].cpu().numpy().view(np.uint64), ref_ud)
+    assert np.array_equal(drank.cpu().numpy().view(np.uint32), ref_drank)
