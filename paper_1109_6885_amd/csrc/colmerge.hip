@@ -295,9 +295,10 @@ __global__ __launch_bounds__(256) void k1_sort_up(mc::ColDesc C, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
     mc::sort_up_tile<T>(C, p, blockIdx.x, smem);
 }
+template <class T>
 __global__ __launch_bounds__(256) void k1_sort_scan(mc::ColDesc C, int p) {
     __shared__ __attribute__((aligned(16))) char smem[64];
-    mc::sort_scan_digit(C, p, blockIdx.x, smem);
+    mc::sort_scan_digit<T>(C, p, blockIdx.x, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int p) {
@@ -403,7 +404,8 @@ __global__ __launch_bounds__(256) void kn_sort_up(Batch B, int p) {
 __global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int p) {
     __shared__ __attribute__((aligned(16))) char smem[64];
     const uint32_t j = find_col(B, blockIdx.x);
-    mc::sort_scan_digit(B.cols[j], p, blockIdx.x - B.map[j], smem);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::sort_scan_digit, C, p, blockIdx.x - B.map[j], smem);
 }
 __global__ __launch_bounds__(256) void kn_sort_down(Batch B, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
@@ -494,7 +496,7 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
     for (int p = 0; p < T::kBytes; p++) {
         hipLaunchKernelGGL(k1_sort_up<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, p);
         MC_LAUNCHED("k1_sort_up");
-        hipLaunchKernelGGL(k1_sort_scan, dim3(256), dim3(mc::kBlock), 0, s, C, p);
+        hipLaunchKernelGGL(k1_sort_scan<T>, dim3(256), dim3(mc::kBlock), 0, s, C, p);
         MC_LAUNCHED("k1_sort_scan");
         hipLaunchKernelGGL(k1_sort_down<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, p);
         MC_LAUNCHED("k1_sort_down");

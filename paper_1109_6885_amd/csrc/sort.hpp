@@ -108,6 +108,7 @@ template <class T>
 __device__ void sort_up_tile(const ColDesc &C, int p, uint32_t t, char *smem) {
     if (C.trivial[p]) return;
     constexpr int TILE = sort_tile<T>();
+    if ((uint64_t)t * TILE >= sort_n(C)) return;  // past the values: never scanned
     uint32_t *h = reinterpret_cast<uint32_t *>(smem);
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -127,26 +128,30 @@ __device__ void sort_up_tile(const ColDesc &C, int p, uint32_t t, char *smem) {
 // Adds the digit's global base, so tcount then holds the first output
 // position of every (digit, tile).
 
-__device__ inline void sort_scan_digit(const ColDesc &C, int p, uint32_t d, char *smem) {
+template <class T>
+__device__ void sort_scan_digit(const ColDesc &C, int p, uint32_t d, char *smem) {
     if (C.trivial[p]) return;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
     uint32_t *row = C.tcount + (uint64_t)d * C.sort_tiles;
     uint32_t carry = C.base[p * 256 + d];
+    // tiles holding values (fewer than sort_tiles when hashing removed duplicates)
+    const uint32_t nt = (uint32_t)min<uint64_t>(C.sort_tiles,
+                                                (sort_n(C) + sort_tile<T>() - 1) / sort_tile<T>());
     constexpr int kPer = 8;
-    for (uint32_t c0 = 0; c0 < C.sort_tiles; c0 += kBlock * kPer) {
+    for (uint32_t c0 = 0; c0 < nt; c0 += kBlock * kPer) {
         uint32_t v[kPer];
         uint32_t sum = 0;
         const uint32_t i0 = c0 + threadIdx.x * kPer;
 #pragma unroll
         for (int j = 0; j < kPer; j++) {
-            v[j] = (i0 + j < C.sort_tiles) ? row[i0 + j] : 0u;
+            v[j] = (i0 + j < nt) ? row[i0 + j] : 0u;
             sum += v[j];
         }
         uint32_t tot;
         uint32_t ex = block_excl_scan(sum, tmp, &tot) + carry;
 #pragma unroll
         for (int j = 0; j < kPer; j++) {
-            if (i0 + j < C.sort_tiles) row[i0 + j] = ex;
+            if (i0 + j < nt) row[i0 + j] = ex;
             ex += v[j];
         }
         carry += tot;
