@@ -15,10 +15,12 @@
 //   rank_rows_tile     drank[row] = drankd[dindex[rep[row]]]
 //
 // A slot holds (representative row + 1) and is written once, by one
-// compare-and-swap from zero, so a plain load that sees a nonzero slot sees
-// its final value; a stale zero only leads to a failing compare-and-swap
-// that returns the real value.  Probing is linear and bounded by the table
-// size, which is a power of two of at least twice the rows.
+// compare-and-swap from zero.  Slots are read with device-coherent loads:
+// the compare-and-swap takes effect beyond the per-XCD L2, so a plain load
+// could keep returning a cached zero and send every later row of a frequent
+// value into a (serialized) compare-and-swap on the same slot.  Probing is
+// linear and bounded by the table size, a power of two of at least twice
+// the rows.
 #pragma once
 
 #include "sort.hpp"
@@ -53,7 +55,7 @@ __device__ void hash_insert_tile(const ColDesc &C, uint64_t t) {
         uint32_t rep = (uint32_t)row;
         bool found = false;
         for (uint64_t probe = 0; probe <= C.hmask; probe++) {
-            uint32_t s = C.htab[h];
+            uint32_t s = __hip_atomic_load(&C.htab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (s == 0) {
                 s = atomicCAS(&C.htab[h], 0u, (uint32_t)row + 1u);
                 if (s == 0) {  // claimed: this row represents its value
