@@ -312,7 +312,8 @@ __global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C) {
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_hash_insert(mc::ColDesc C) {
-    mc::hash_insert_tile<T>(C, blockIdx.x);
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::HashSmem<T>)];
+    mc::hash_insert_tile<T>(C, blockIdx.x, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_compact(mc::ColDesc C) {

@@ -5,7 +5,8 @@
 //
 //   hash_insert_tile   every row finds or claims its value's slot in an
 //                      open-addressing table; the claiming row is the
-//                      value's representative (rep[row] = representative)
+//                      value's representative (rep[row] = representative);
+//                      rows first meet their tile's equal values in LDS
 //   compact_tile       representatives, in row order, become the distinct
 //                      list (dkeys) with a cross-tile prefix; dindex[rep] is a
 //                      representative's position in it; *dcount = its length
@@ -42,39 +43,73 @@ __device__ __forceinline__ uint64_t hash_key(Raw16 k) { return mix64(k.a ^ mix64
 
 constexpr int kHashItems = 8;
 constexpr int kHashTile = kBlock * kHashItems;
+constexpr int kLocalSlots = 2 * kHashTile;  // LDS table of the tile's first occurrences
 
 template <class T>
-__device__ void hash_insert_tile(const ColDesc &C, uint64_t t) {
+struct HashSmem {
+    typename T::K keys[kHashTile];
+    uint32_t slot[kLocalSlots];  // tile-local index + 1 of a value's first occurrence
+    uint32_t lrep[kHashTile];    // first occurrence inside the tile of each row's value
+    uint32_t grep[kHashTile];    // representative row of a first occurrence
+};
+
+// Find or claim the slot of `key` in the global table; returns the
+// representative row, or `row` itself if it claimed the slot.
+template <class T>
+__device__ __forceinline__ uint32_t global_rep(const ColDesc &C, typename T::K key, uint32_t row,
+                                               bool *ok) {
+    uint64_t h = hash_key(key) & C.hmask;
+    for (uint64_t probe = 0; probe <= C.hmask; probe++) {
+        uint32_t s = __hip_atomic_load(&C.htab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s == 0) {
+            s = atomicCAS(&C.htab[h], 0u, row + 1u);
+            if (s == 0) return row;  // claimed: this row represents its value
+        }
+        const uint32_t r = s - 1u;
+        if (T::keq(T::load(C.delta, r), key)) return r;
+        h = (h + 1) & C.hmask;
+    }
+    *ok = false;
+    return row;
+}
+
+// Rows of one tile: equal values inside the tile first meet in an LDS table,
+// so only the first occurrence of each value probes the global table (a
+// frequent value then costs one global probe per tile, not one per row).
+template <class T>
+__device__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
     typedef typename T::K K;
-    bool overflow = false;
-    for (int j = 0; j < kHashItems; j++) {
-        const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
-        if (row >= C.nd) break;
-        const K key = T::load(C.delta, row);
-        uint64_t h = hash_key(key) & C.hmask;
-        uint32_t rep = (uint32_t)row;
-        bool found = false;
-        for (uint64_t probe = 0; probe <= C.hmask; probe++) {
-            uint32_t s = __hip_atomic_load(&C.htab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (s == 0) {
-                s = atomicCAS(&C.htab[h], 0u, (uint32_t)row + 1u);
-                if (s == 0) {  // claimed: this row represents its value
-                    found = true;
-                    break;
-                }
+    HashSmem<T> &S = *reinterpret_cast<HashSmem<T> *>(smem);
+    const uint64_t r0 = t * kHashTile;
+    const uint32_t tn = (uint32_t)min<uint64_t>(kHashTile, C.nd - r0);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kLocalSlots; i += kBlock) S.slot[i] = 0;
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) S.keys[i] = T::load(C.delta, r0 + i);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
+        const K key = S.keys[i];
+        uint32_t h = (uint32_t)(hash_key(key) >> 20) & (kLocalSlots - 1);
+        uint32_t first = i;
+        for (int probe = 0; probe < kLocalSlots; probe++) {
+            uint32_t sl = S.slot[h];
+            if (sl == 0) {
+                sl = atomicCAS(&S.slot[h], 0u, i + 1u);
+                if (sl == 0) break;  // first occurrence inside the tile
             }
-            const uint32_t r = s - 1u;
-            if (T::keq(T::load(C.delta, r), key)) {
-                rep = r;
-                found = true;
+            if (T::keq(S.keys[sl - 1u], key)) {
+                first = sl - 1u;
                 break;
             }
-            h = (h + 1) & C.hmask;
+            h = (h + 1) & (kLocalSlots - 1);
         }
-        if (!found) overflow = true;
-        C.rep[row] = rep;
+        S.lrep[i] = first;
     }
-    if (overflow) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+    __syncthreads();
+    bool ok = true;
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock)
+        if (S.lrep[i] == i) S.grep[i] = global_rep<T>(C, S.keys[i], (uint32_t)(r0 + i), &ok);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) C.rep[r0 + i] = S.grep[S.lrep[i]];
+    if (!ok) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
 }
 
 struct CompactSmem {
