@@ -7,6 +7,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <new>
 #include <string>
@@ -75,6 +76,13 @@ uint32_t value_len(int32_t type) {
     }
 }
 
+uint32_t merge_tile_of(int32_t type) {
+    switch (type) {
+        case MC_U32: return mc::merge_tile<mc::TU32>();
+        case MC_U64: return mc::merge_tile<mc::TU64>();
+        default: return mc::merge_tile<mc::TS16>();
+    }
+}
 uint32_t sort_tile_of(int32_t type) {
     switch (type) {
         case MC_U32: return mc::sort_tile<mc::TU32>();
@@ -108,13 +116,14 @@ struct Carver {
 struct ColLayout {
     // part Z
     uint64_t counters = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0, emit_status = 0,
-             merge_status = 0, dcount = 0, hstatus = 0, htab = 0, z_size = 0;
+             merge_status = 0, mbound = 0, dcount = 0, hstatus = 0, htab = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
              drank = 0, x_d = 0, x_m = 0, xdev = 0, rep = 0, dindex = 0, dkeys = 0, drankd = 0,
              b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
+    bool partitioned = false;  // merge tile boundaries come from merge_partition
     bool hashed = false;       // Step 1(a) deduplicates by hashing first
     uint64_t hmask = 0;
     uint32_t hash_tiles = 0;
@@ -124,6 +133,15 @@ struct ColLayout {
 // the radix passes then only see distinct values.  Smaller deltas sort
 // directly (their passes are latency-bound, and hashing would add work).
 constexpr uint64_t kHashMinRows = 1ull << 21;
+
+// Merges of at least this many tiles find the tile boundaries in a launch of
+// their own (one wave per boundary, all at once) instead of at the start of
+// every tile, where the search's dependent global loads would delay each
+// round of resident tiles.
+constexpr uint64_t kMergePartMinTiles = 512;
+
+// Workgroups of merge_partition: one wave per tile boundary (tiles + 1).
+uint64_t merge_part_blocks(uint64_t merge_tiles) { return ceil_div(merge_tiles + 1, mc::kWaves); }
 
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
                      bool allow_hash = true) {
@@ -140,7 +158,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.sort_tiles = (uint32_t)ceil_div(nd, sort_tile_of(type));
     L.emit_tiles = (uint32_t)ceil_div(nd, mc::kEmitTile);
     L.hist_tiles = (uint32_t)ceil_div(nd, mc::kHistChunk);
-    L.merge_tiles = ceil_div(n_um + nd, mc::kMergeTile);
+    L.merge_tiles = ceil_div(n_um + nd, merge_tile_of(type));
     L.repack_tiles = ceil_div(n_main + nd, mc::kRepackCodes);
     L.xc_tiles = n_main ? ceil_div(n_um, mc::kXCompactTile) : 0;
     Carver z;
@@ -152,6 +170,8 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.trivial = z.take(16 * 4);
     L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
     L.merge_status = z.take(L.merge_tiles * 8);
+    L.partitioned = L.merge_tiles >= kMergePartMinTiles;
+    if (L.partitioned) L.mbound = z.take((L.merge_tiles + 1) * 8);
     if (L.hashed) {
         L.dcount = z.take(8);
         L.hstatus = z.take(ceil_div(nd, mc::kCompactTile) * 8);
@@ -181,6 +201,12 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
 }
 
 uint64_t single_scratch(const ColLayout &L) { return L.z_size + L.b_size; }
+
+// Step 1(b) alone uses only the zeroed part of a column layout (counters,
+// prefix words, tile boundaries).
+ColLayout merge_only_layout(int32_t type, uint64_t n_um, uint64_t n_ud_max) {
+    return col_layout(type, n_um, n_ud_max, 0, /*allow_hash=*/false);
+}
 
 // Step 1(a) fields for the hashing route (or the plain radix route).
 void set_hash_fields(mc::ColDesc &C, char *za, char *zb, const ColLayout &L) {
@@ -233,6 +259,7 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
     C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);
     C.merge_status = reinterpret_cast<uint64_t *>(za + L.merge_status);
+    C.mbound = L.partitioned ? reinterpret_cast<uint64_t *>(za + L.mbound) : nullptr;
     C.n_ud = reinterpret_cast<uint64_t *>(za + L.n_ud);
     C.n_ud_in = C.n_ud;
     C.nd_max = in->delta_rows;
@@ -328,6 +355,10 @@ __global__ __launch_bounds__(256) void k1_rank_rows(mc::ColDesc C) {
     mc::rank_rows_tile(C, blockIdx.x);
 }
 template <class T>
+__global__ __launch_bounds__(256) void k1_merge_part(mc::ColDesc C) {
+    mc::merge_partition<T>(C, blockIdx.x);
+}
+template <class T>
 __global__ __launch_bounds__(256) void k1_merge(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T>)];
     mc::merge_tile<T>(C, smem);
@@ -419,6 +450,11 @@ __global__ __launch_bounds__(256) void kn_emit(Batch B) {
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::emit_tile, C, smem);
+}
+__global__ __launch_bounds__(256) void kn_merge_part(Batch B) {
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::merge_partition, C, blockIdx.x - B.map[j]);
 }
 __global__ __launch_bounds__(256) void kn_merge(Batch B) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemMerge];
@@ -518,6 +554,11 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
 template <class T>
 int launch_merge(const mc::ColDesc &C, uint64_t merge_tiles, hipStream_t s) {
     const uint64_t grid = merge_tiles ? merge_tiles : 1;
+    if (C.mbound) {
+        hipLaunchKernelGGL(k1_merge_part<T>, dim3((uint32_t)merge_part_blocks(merge_tiles)),
+                           dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_merge_part");
+    }
     hipLaunchKernelGGL(k1_merge<T>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C);
     MC_LAUNCHED("k1_merge");
     return MC_OK;
@@ -648,10 +689,10 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 
 constexpr int kMaxPasses = 16;
 // map slots: 0 hist, 1 hist_scan, 2..17 pass up/down, 18..33 pass scan,
-// 34 emit, 35 merge, 36 repack, 37 X_M compaction
+// 34 emit, 35 merge, 36 repack, 37 X_M compaction, 38 merge tile boundaries
 constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 2 + kMaxPasses,
               kMapEmit = 2 + 2 * kMaxPasses, kMapMerge = kMapEmit + 1, kMapRepack = kMapEmit + 2,
-              kMapXc = kMapEmit + 3, kNumMaps = kMapEmit + 4;
+              kMapXc = kMapEmit + 3, kMapMergePart = kMapEmit + 4, kNumMaps = kMapEmit + 5;
 
 struct BatchPlan {
     uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, total = 0;
@@ -701,6 +742,7 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P) {
             else if (m == kMapMerge) n = L.merge_tiles ? L.merge_tiles : 1;
             else if (m == kMapRepack) n = L.repack_tiles;
             else if (m == kMapXc) n = L.xc_tiles;
+            else if (m == kMapMergePart) n = L.partitioned ? merge_part_blocks(L.merge_tiles) : 0;
             at(m, j) = (uint32_t)acc;
             acc += n;
             if (acc >= (1ull << 31)) return fail(MC_E_ARG, "batch has too many tiles for one launch");
@@ -749,6 +791,11 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
     if (tiles(kMapEmit)) {
         hipLaunchKernelGGL(kn_emit, dim3(tiles(kMapEmit)), dim3(mc::kBlock), 0, s, batch(kMapEmit));
         MC_LAUNCHED("kn_emit");
+    }
+    if (tiles(kMapMergePart)) {
+        hipLaunchKernelGGL(kn_merge_part, dim3(tiles(kMapMergePart)), dim3(mc::kBlock), 0, s,
+                           batch(kMapMergePart));
+        MC_LAUNCHED("kn_merge_part");
     }
     if (tiles(kMapMerge)) {
         hipLaunchKernelGGL(kn_merge, dim3(tiles(kMapMerge)), dim3(mc::kBlock), 0, s,
@@ -880,7 +927,11 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
 }
 
 int mc_merge_dictionaries_scratch(uint64_t n_um, uint64_t n_ud_max, uint64_t *scratch_bytes) {
-    if (scratch_bytes) *scratch_bytes = col_layout(MC_U32, n_um, n_ud_max, 0).z_size;
+    // the largest over the value types (their merge tiles differ)
+    uint64_t z = 0;
+    for (int32_t t : {MC_U32, MC_U64, MC_STR16})
+        z = std::max<uint64_t>(z, merge_only_layout(t, n_um, n_ud_max).z_size);
+    if (scratch_bytes) *scratch_bytes = z;
     return MC_OK;
 }
 
@@ -897,8 +948,7 @@ int mc_merge_dictionaries(mc_ctx *ctx, int32_t type, const void *u_m, uint64_t n
         return fail(MC_E_ARG, "null buffer");
     if (!aligned16(u_m) || !aligned16(u_d) || !aligned16(u_new) || !aligned16(result))
         return fail(MC_E_ARG, "misaligned buffer");
-    // the merge uses only the zeroed part of a column layout (counters, prefix words)
-    const ColLayout L = col_layout(MC_U32, n_um, n_ud_max, 0);
+    const ColLayout L = merge_only_layout(type, n_um, n_ud_max);
     if (!scratch || scratch_bytes < L.z_size) return fail(MC_E_CAP, "scratch too small");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
     char *za = static_cast<char *>(scratch);
@@ -919,6 +969,7 @@ int mc_merge_dictionaries(mc_ctx *ctx, int32_t type, const void *u_m, uint64_t n
     C.rows_total = rows_total;
     C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
     C.merge_status = reinterpret_cast<uint64_t *>(za + L.merge_status);
+    C.mbound = L.partitioned ? reinterpret_cast<uint64_t *>(za + L.mbound) : nullptr;
     int rc = launch_fill(za, L.z_size, result, sizeof(mc_result), s);
     if (rc) return rc;
     switch (type) {

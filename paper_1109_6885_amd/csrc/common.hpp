@@ -232,6 +232,7 @@ struct ColDesc {
     uint32_t *counters;        // [0] emit tile counter, [1] merge tile counter (zeroed)
     uint64_t *emit_status;     // emit prefix words (zeroed)
     uint64_t *merge_status;    // merge prefix words (zeroed)
+    uint64_t *mbound;          // U_M entries before each merge tile's start, or null
     uint64_t *n_ud;            // |U_D| as written by Step 1(a) (zeroed)
     const uint64_t *n_ud_in;   // |U_D| as read by Step 1(b)
     uint64_t nd_max;           // capacity of u_d, drank, x_d
@@ -258,13 +259,15 @@ struct ColDesc {
 // (distance / 256) rounds instead of (distance / 64).  Every thread of the
 // block must call it; every thread gets the exclusive prefix.  s_u64 needs
 // kWaves + 1 entries and s_i32 kWaves entries of LDS.
-__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t tile, uint64_t agg,
-                                          uint32_t *err, uint64_t *s_u64, int *s_i32) {
-    if (tile == 0) {
-        if (threadIdx.x == 0) st_rel(&status[0], kFlagPre | agg);
-        return 0;
-    }
-    if (threadIdx.x == 0) st_rel(&status[tile], kFlagAgg | agg);
+//
+// Split in two so that a tile can publish its own total first, do other work
+// while its predecessors finish, and only then wait for their prefix.
+__device__ inline void lookback_publish(uint64_t *status, uint32_t tile, uint64_t agg) {
+    if (threadIdx.x == 0) st_rel(&status[tile], (tile == 0 ? kFlagPre : kFlagAgg) | agg);
+}
+__device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uint64_t agg,
+                                            uint32_t *err, uint64_t *s_u64, int *s_i32) {
+    if (tile == 0) return 0;
     const int lane = lane_id(), wv = wave_id();
     uint64_t prefix = 0;
     int64_t base = (int64_t)tile - 1;
@@ -305,6 +308,11 @@ __device__ inline uint64_t lookback_block(uint64_t *status, uint32_t tile, uint6
     }
     if (threadIdx.x == 0) st_rel(&status[tile], kFlagPre | (prefix + agg));
     return prefix;
+}
+__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t tile, uint64_t agg,
+                                          uint32_t *err, uint64_t *s_u64, int *s_i32) {
+    lookback_publish(status, tile, agg);
+    return lookback_resolve(status, tile, agg, err, s_u64, s_i32);
 }
 
 // Code width for a dictionary of n entries: ceil(log2 n), at least 1.

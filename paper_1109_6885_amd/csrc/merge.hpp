@@ -16,19 +16,38 @@
 // new iff it does not equal that predecessor; the U_D copy of a shared value
 // takes the index of the U_M copy (the rule "equal values get the same
 // index in both tables").
+//
+// Each thread merges 8 (16-byte values: 4) consecutive merged positions
+// once, remembering what every step took; the tile then publishes its count
+// of new values, replays the steps into LDS (which input each output comes
+// from, tile-relative X entries) while its predecessors finish, and once its
+// offset is known writes U', X_M and X_D as contiguous runs (coalesced
+// stores).
 #pragma once
 
 #include "common.hpp"
 
 namespace mc {
 
-constexpr int kMergeItems = 8;
-constexpr int kMergeTile = kBlock * kMergeItems;
+// Merged positions per thread.  16-byte values use half the tile so that
+// four workgroups fit one CU's LDS instead of two.
+template <class T>
+struct MergeCfg { static constexpr int kItems = 8; };
+template <>
+struct MergeCfg<TS16> { static constexpr int kItems = 8; };
+template <class T>
+__host__ __device__ constexpr int merge_tile() { return kBlock * MergeCfg<T>::kItems; }
+
+constexpr uint32_t kStepA = 0, kStepNew = 1, kStepDup = 2;
+constexpr uint32_t kFromB = 0x8000u;  // > any merge tile: marks an index into b
 
 template <class T>
 struct MergeSmem {
-    typename T::N a[kMergeTile + 1];  // a[0] = U_M[i0 - 1] (predecessor)
-    typename T::N b[kMergeTile];
+    typename T::N a[merge_tile<T>() + 1];  // a[0] = U_M[i0 - 1] (predecessor)
+    typename T::N b[merge_tile<T>()];
+    uint16_t src[merge_tile<T>()];  // output r of the tile: index in a, or kFromB | index in b
+    int16_t xm[merge_tile<T>()];    // tile-relative U' index of a[1 + x]
+    int16_t xd[merge_tile<T>()];    // tile-relative U' index of b[y] (-1: the tile before's last)
     uint32_t tile;
     uint32_t tmp[kWaves];
     uint64_t i0, i1;
@@ -85,6 +104,25 @@ __device__ __forceinline__ uint64_t co_rank_wave(uint64_t k, uint64_t a, uint64_
     return lo;
 }
 
+// Tile boundaries ahead of the merge: wave q of the launch finds how many
+// U_M entries precede merged position q * merge_tile (q = 0 .. tiles), so the
+// merge tiles start without a search through global memory.  Each wave
+// returns on its own; there is no barrier.
+template <class T>
+__device__ void merge_partition(const ColDesc &C, uint32_t blk) {
+    const uint64_t q = (uint64_t)blk * kWaves + wave_id();
+    const uint64_t a = C.n_um;
+    const uint64_t b = min(*C.n_ud_in, C.nd_max);
+    const uint64_t total = a + b;
+    constexpr uint64_t TILE = merge_tile<T>();
+    if (q > (total + TILE - 1) / TILE) return;
+    const uint64_t k = min<uint64_t>(q * TILE, total);
+    auto gA = [&](uint64_t i) { return T::norm(T::load(C.u_m, i)); };
+    auto gB = [&](uint64_t j) { return T::norm(T::load(C.u_d, j)); };
+    const uint64_t r = co_rank_wave<T>(k, a, b, gA, gB);
+    if (lane_id() == 0) C.mbound[q] = r;
+}
+
 template <class T>
 __device__ void merge_tile(const ColDesc &C, char *smem) {
     MergeSmem<T> &S = *reinterpret_cast<MergeSmem<T> *>(smem);
@@ -95,7 +133,8 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     const uint64_t b = min(*C.n_ud_in, C.nd_max);  // never read past U_D's buffer
     const uint64_t cap = C.u_new_cap;
     const uint64_t total = a + b;
-    const uint64_t k0 = (uint64_t)t * kMergeTile;
+    constexpr int ITEMS = MergeCfg<T>::kItems;
+    const uint64_t k0 = (uint64_t)t * merge_tile<T>();
     if (k0 >= total) {
         if (t == 0 && threadIdx.x == 0) {  // nothing to merge at all
             C.result->new_dict_len = 0;
@@ -105,18 +144,25 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
         }
         return;
     }
-    const uint64_t k1 = min(k0 + kMergeTile, total);
+    const uint64_t k1 = min<uint64_t>(k0 + merge_tile<T>(), total);
     auto gA = [&](uint64_t i) { return T::norm(T::load(C.u_m, i)); };
     auto gB = [&](uint64_t j) { return T::norm(T::load(C.u_d, j)); };
-    if (wave_id() == 0) {
-        const uint64_t r = co_rank_wave<T>(k0, a, b, gA, gB);
-        if (lane_id() == 0) S.i0 = r;
-    } else if (wave_id() == 1) {
-        const uint64_t r = co_rank_wave<T>(k1, a, b, gA, gB);
-        if (lane_id() == 0) S.i1 = r;
+    uint64_t i0, i1;
+    if (C.mbound) {  // tile boundaries found by merge_partition
+        i0 = C.mbound[t];
+        i1 = C.mbound[t + 1];
+    } else {
+        if (wave_id() == 0) {
+            const uint64_t r = co_rank_wave<T>(k0, a, b, gA, gB);
+            if (lane_id() == 0) S.i0 = r;
+        } else if (wave_id() == 1) {
+            const uint64_t r = co_rank_wave<T>(k1, a, b, gA, gB);
+            if (lane_id() == 0) S.i1 = r;
+        }
+        __syncthreads();
+        i0 = S.i0;
+        i1 = S.i1;
     }
-    __syncthreads();
-    const uint64_t i0 = S.i0, i1 = S.i1;
     const uint64_t j0 = k0 - i0, j1 = k1 - i1;
     const uint32_t na = (uint32_t)(i1 - i0), nb = (uint32_t)(j1 - j0);
     for (uint32_t x = threadIdx.x; x <= na; x += kBlock) {
@@ -131,57 +177,72 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
 
     // this thread's slice of the tile's merged range
     const uint32_t len = (uint32_t)(k1 - k0);
-    const uint32_t d0 = min<uint32_t>(threadIdx.x * kMergeItems, len);
-    const uint32_t d1 = min<uint32_t>(d0 + kMergeItems, len);
+    const uint32_t d0 = min<uint32_t>(threadIdx.x * ITEMS, len);
+    const uint32_t d1 = min<uint32_t>(d0 + ITEMS, len);
     auto lA = [&](uint64_t i) { return S.a[i + 1]; };
     auto lB = [&](uint64_t j) { return S.b[j]; };
     const uint32_t ia0 = (uint32_t)co_rank<T>(d0, na, nb, lA, lB);
     const uint32_t jb0 = d0 - ia0;
 
-    // pass 1: count new values
-    uint32_t cnt = 0;
+    // one merge walk: 2 bits per step (kStepA: U_M element, kStepNew: new U_D
+    // element, kStepDup: U_D element equal to its U_M predecessor)
+    const uint32_t nsteps = d1 - d0;
+    uint32_t steps = 0, cnt = 0;
     {
         uint32_t ia = ia0, jb = jb0;
-        for (uint32_t d = d0; d < d1; d++) {
+        for (uint32_t s = 0; s < nsteps; s++) {
             const bool take_a = jb >= nb || (ia < na && T::le(S.a[ia + 1], S.b[jb]));
+            uint32_t kind;
             if (take_a) {
-                cnt++;
+                kind = kStepA;
                 ia++;
             } else {
-                const bool dup = (i0 + ia > 0) && T::eq(S.a[ia], S.b[jb]);
-                cnt += dup ? 0u : 1u;
+                kind = ((i0 + ia > 0) && T::eq(S.a[ia], S.b[jb])) ? kStepDup : kStepNew;
                 jb++;
             }
+            steps |= kind << (2 * s);
+            cnt += kind != kStepDup;
         }
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);
-    const uint64_t tile_prefix = lookback_block(C.merge_status, t, tot, C.err, S.lb64, S.lb32);
+    lookback_publish(C.merge_status, t, tot);
 
-    // pass 2: write U', X_M and X_D
-    uint64_t pos = tile_prefix + ex;
+    // replay into LDS with tile-relative output indices
     {
-        uint32_t ia = ia0, jb = jb0;
-        for (uint32_t d = d0; d < d1; d++) {
-            const bool take_a = jb >= nb || (ia < na && T::le(S.a[ia + 1], S.b[jb]));
-            if (take_a) {
-                if (pos < cap) T::store(C.u_new, pos, T::denorm(S.a[ia + 1]));
-                if (C.x_m) C.x_m[i0 + ia] = (uint32_t)pos;
-                pos++;
+        uint32_t ia = ia0, jb = jb0, lo = ex;
+        for (uint32_t s = 0; s < nsteps; s++) {
+            const uint32_t kind = (steps >> (2 * s)) & 3u;
+            if (kind == kStepA) {
+                S.src[lo] = (uint16_t)(ia + 1);
+                S.xm[ia] = (int16_t)lo;
+                lo++;
                 ia++;
+            } else if (kind == kStepNew) {
+                S.src[lo] = (uint16_t)(kFromB | jb);
+                S.xd[jb] = (int16_t)lo;
+                lo++;
+                jb++;
             } else {
-                const bool dup = (i0 + ia > 0) && T::eq(S.a[ia], S.b[jb]);
-                if (dup) {
-                    if (C.x_d) C.x_d[j0 + jb] = (uint32_t)(pos - 1);
-                } else {
-                    if (pos < cap) T::store(C.u_new, pos, T::denorm(S.b[jb]));
-                    if (C.x_d) C.x_d[j0 + jb] = (uint32_t)pos;
-                    pos++;
-                }
+                S.xd[jb] = (int16_t)((int)lo - 1);
                 jb++;
             }
         }
     }
+    const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, tot, C.err, S.lb64, S.lb32);
+    __syncthreads();  // staging complete (the look-back may return without a barrier)
+
+    for (uint32_t r = threadIdx.x; r < tot; r += kBlock) {
+        const uint32_t sv = S.src[r];
+        const uint64_t pos = tile_prefix + r;
+        if (pos < cap) T::store(C.u_new, pos, T::denorm((sv & kFromB) ? S.b[sv & ~kFromB] : S.a[sv]));
+    }
+    if (C.x_m)
+        for (uint32_t x = threadIdx.x; x < na; x += kBlock)
+            C.x_m[i0 + x] = (uint32_t)(tile_prefix + (uint64_t)(int64_t)S.xm[x]);
+    if (C.x_d)
+        for (uint32_t y = threadIdx.x; y < nb; y += kBlock)
+            C.x_d[j0 + y] = (uint32_t)(tile_prefix + (uint64_t)(int64_t)S.xd[y]);
     if (threadIdx.x == 0 && k1 == total) {
         const uint64_t n = tile_prefix + tot;
         const uint32_t w = code_width(n);

@@ -47,6 +47,22 @@ def test_batched_direct():
         check_col(c, o.fetch())
 
 
+def test_batched_partitioned_merge():
+    """Columns whose dictionaries merge over 2^20 positions find the merge
+    tile boundaries in a launch of their own; mixed with small columns."""
+    rng = np.random.default_rng(6)
+    cols = [gen.random_column(rng, "u64", 1_040_000, 60_000, 20_000, 0.5),
+            gen.random_column(rng, "u32", 300, 2000, 100, 0.5),
+            gen.random_column(rng, "str16", 600_000, 30_000, 500_000, 0.9),
+            gen.random_column(rng, "u32", 1_100_000, 10_000, 0)]
+    say(f"case batched partitioned merge, {len(cols)} columns")
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, _ = cm.merge_columns_batched(dcols)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+
+
 def test_batched_graph_replays():
     cols = small_batch(24, 0.001)
     say(f"case batched graph, {len(cols)} columns")

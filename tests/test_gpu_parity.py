@@ -273,6 +273,19 @@ def test_skewed_new_values(where):
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+@pytest.mark.parametrize("vtype,n_um,nd,frac_new", [("u64", 1_000_000, 100_003, 0.5),
+                                                    ("str16", 700_000, 400_001, 0.9),
+                                                    ("u32", 1_048_575, 1, 0.0),
+                                                    ("u32", 3, 1_100_000, 1.0)])
+def test_partitioned_merge(vtype, n_um, nd, frac_new):
+    """Merges of over 2^20 positions take their tile boundaries from a
+    launch of their own; the result must not change."""
+    rng = np.random.default_rng(77)
+    col = gen.random_column(rng, vtype, n_um, 50_000, nd, frac_new)
+    say(f"case partitioned merge {vtype} n_um={n_um} nd={nd}")
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
 def test_naive_step2_matches_oracle(vtype):
     """The unoptimized Step 2(b) (binary search in U', Section 5.2) gives
