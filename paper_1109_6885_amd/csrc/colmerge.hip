@@ -115,7 +115,8 @@ struct Carver {
 
 struct ColLayout {
     // part Z
-    uint64_t counters = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0, emit_status = 0,
+    uint64_t counters = 0, sflags = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0,
+             emit_status = 0, emit_status2 = 0,
              merge_status = 0, mbound = 0, dcount = 0, hstatus = 0, htab = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
@@ -163,12 +164,14 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.xc_tiles = n_main ? ceil_div(n_um, mc::kXCompactTile) : 0;
     Carver z;
     L.counters = z.take(16 * 4);
+    L.sflags = z.take(mc::kSfSlots * 4);
     L.n_ud = z.take(8);
     L.err = z.take(8);
     L.xflag = z.take(8);
     L.gh = z.take((uint64_t)L.passes * 256 * 4);
     L.trivial = z.take(16 * 4);
     L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
+    L.emit_status2 = z.take((uint64_t)L.emit_tiles * 8);
     L.merge_status = z.take(L.merge_tiles * 8);
     L.partitioned = L.merge_tiles >= kMergePartMinTiles;
     if (L.partitioned) L.mbound = z.take((L.merge_tiles + 1) * 8);
@@ -257,7 +260,9 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.trivial = reinterpret_cast<uint32_t *>(za + L.trivial);
     C.tcount = reinterpret_cast<uint32_t *>(zb + L.tcount);
     C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
+    C.sflags = reinterpret_cast<uint32_t *>(za + L.sflags);
     C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);
+    C.emit_status2 = reinterpret_cast<uint64_t *>(za + L.emit_status2);
     C.merge_status = reinterpret_cast<uint64_t *>(za + L.merge_status);
     C.mbound = L.partitioned ? reinterpret_cast<uint64_t *>(za + L.mbound) : nullptr;
     C.n_ud = reinterpret_cast<uint64_t *>(za + L.n_ud);
@@ -288,6 +293,7 @@ constexpr size_t kSmemMerge = max3(sizeof(mc::MergeSmem<mc::TU32>),
                                    sizeof(mc::MergeSmem<mc::TU64>),
                                    sizeof(mc::MergeSmem<mc::TS16>));
 constexpr size_t kSmemSmall = 1024;
+constexpr size_t kSmemHistScan = (mc::kWaves + 16) * 4;  // scan scratch + digits per position
 
 __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, uint32_t *p1,
                                                    uint64_t n1) {
@@ -314,28 +320,51 @@ __global__ __launch_bounds__(256) void k1_hist(mc::ColDesc C) {
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_hist_scan(mc::ColDesc C) {
-    __shared__ __attribute__((aligned(16))) char smem[64];
+    __shared__ __attribute__((aligned(16))) char smem[kSmemHistScan];
     mc::hist_scan_col<T>(C, smem);
 }
+// Radix pass kinds: one of the prefix passes (p = slot), or pass p of
+// the full LSD sort, which runs only when the prefix sort left the values
+// out of order (otherwise the launch returns at once).
+constexpr int kPassPrefix = 0, kPassFull = 1;
+
+__device__ __forceinline__ bool pass_io(const mc::ColDesc &C, int kind, int p, mc::PassIO *io) {
+    if (kind == kPassPrefix) {
+        *io = mc::prefix_io(C, p);
+        return true;
+    }
+    if (C.sflags[mc::kSfUnsorted] == 0) return false;
+    *io = mc::lsd_io(C, p);
+    return true;
+}
+
 template <class T>
-__global__ __launch_bounds__(256) void k1_sort_up(mc::ColDesc C, int p) {
+__global__ __launch_bounds__(256) void k1_sort_up(mc::ColDesc C, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
-    mc::sort_up_tile<T>(C, p, blockIdx.x, smem);
+    mc::PassIO io;
+    if (pass_io(C, kind, p, &io)) mc::sort_up_tile<T>(C, io, blockIdx.x, smem);
 }
 template <class T>
-__global__ __launch_bounds__(256) void k1_sort_scan(mc::ColDesc C, int p) {
+__global__ __launch_bounds__(256) void k1_sort_scan(mc::ColDesc C, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[64];
-    mc::sort_scan_digit<T>(C, p, blockIdx.x, smem);
+    mc::PassIO io;
+    if (pass_io(C, kind, p, &io)) mc::sort_scan_digit<T>(C, io, blockIdx.x, smem);
 }
 template <class T>
-__global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int p) {
+__global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
-    mc::sort_down_tile<T>(C, p, blockIdx.x, smem);
+    mc::PassIO io;
+    if (pass_io(C, kind, p, &io)) mc::sort_down_tile<T>(C, io, blockIdx.x, smem);
 }
 template <class T>
-__global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C) {
+__global__ __launch_bounds__(256) void k1_window(mc::ColDesc C, int round) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
+    mc::window_sort_tile<T>(C, round, blockIdx.x, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C, int again) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<T>)];
-    mc::emit_tile<T>(C, smem);
+    mc::emit_tile<T>(C, smem, again != 0);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_hash_insert(mc::ColDesc C) {
@@ -348,8 +377,8 @@ __global__ __launch_bounds__(256) void k1_compact(mc::ColDesc C) {
     mc::compact_tile<T>(C, smem);
 }
 template <class T>
-__global__ __launch_bounds__(256) void k1_emit_distinct(mc::ColDesc C) {
-    mc::emit_distinct_tile<T>(C, blockIdx.x);
+__global__ __launch_bounds__(256) void k1_emit_distinct(mc::ColDesc C, int again) {
+    mc::emit_distinct_tile<T>(C, blockIdx.x, again != 0);
 }
 __global__ __launch_bounds__(256) void k1_rank_rows(mc::ColDesc C) {
     mc::rank_rows_tile(C, blockIdx.x);
@@ -422,34 +451,45 @@ __global__ __launch_bounds__(256) void kn_hist(Batch B) {
     MC_DISPATCH(C, mc::hist_tile, C, blockIdx.x - B.map[j], smem);
 }
 __global__ __launch_bounds__(256) void kn_hist_scan(Batch B) {
-    __shared__ __attribute__((aligned(16))) char smem[64];
+    __shared__ __attribute__((aligned(16))) char smem[kSmemHistScan];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::hist_scan_col, C, smem);
 }
-__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int p) {
+__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::sort_up_tile, C, p, blockIdx.x - B.map[j], smem);
+    mc::PassIO io;
+    if (pass_io(C, kind, p, &io)) MC_DISPATCH(C, mc::sort_up_tile, C, io, blockIdx.x - B.map[j], smem);
 }
-__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int p) {
+__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[64];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::sort_scan_digit, C, p, blockIdx.x - B.map[j], smem);
+    mc::PassIO io;
+    if (pass_io(C, kind, p, &io))
+        MC_DISPATCH(C, mc::sort_scan_digit, C, io, blockIdx.x - B.map[j], smem);
 }
-__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int p) {
+__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::sort_down_tile, C, p, blockIdx.x - B.map[j], smem);
+    mc::PassIO io;
+    if (pass_io(C, kind, p, &io))
+        MC_DISPATCH(C, mc::sort_down_tile, C, io, blockIdx.x - B.map[j], smem);
 }
-__global__ __launch_bounds__(256) void kn_emit(Batch B) {
+__global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::window_sort_tile, C, round, blockIdx.x - B.map[j], smem);
+}
+__global__ __launch_bounds__(256) void kn_emit(Batch B, int again) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::emit_tile, C, smem);
+    MC_DISPATCH(C, mc::emit_tile, C, smem, again != 0);
 }
 __global__ __launch_bounds__(256) void kn_merge_part(Batch B) {
     const uint32_t j = find_col(B, blockIdx.x);
@@ -513,8 +553,22 @@ int launch_fill(void *p0, uint64_t bytes0, void *p1, uint64_t bytes1, hipStream_
 // ---------------------------------------------------------------------------
 
 template <class T>
+int launch_passes(const mc::ColDesc &C, const ColLayout &L, int kind, int passes, hipStream_t s) {
+    for (int p = 0; p < passes; p++) {
+        hipLaunchKernelGGL(k1_sort_up<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, kind, p);
+        MC_LAUNCHED("k1_sort_up");
+        hipLaunchKernelGGL(k1_sort_scan<T>, dim3(256), dim3(mc::kBlock), 0, s, C, kind, p);
+        MC_LAUNCHED("k1_sort_scan");
+        hipLaunchKernelGGL(k1_sort_down<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, kind, p);
+        MC_LAUNCHED("k1_sort_down");
+    }
+    return MC_OK;
+}
+
+template <class T>
 int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_t s,
                             hipEvent_t after_sort) {
+    int rc = MC_OK;
     if (C.nd == 0) {
         if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
         return MC_OK;
@@ -530,24 +584,34 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
     MC_LAUNCHED("k1_hist");
     hipLaunchKernelGGL(k1_hist_scan<T>, dim3(1), dim3(mc::kBlock), 0, s, C);
     MC_LAUNCHED("k1_hist_scan");
-    for (int p = 0; p < T::kBytes; p++) {
-        hipLaunchKernelGGL(k1_sort_up<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, p);
-        MC_LAUNCHED("k1_sort_up");
-        hipLaunchKernelGGL(k1_sort_scan<T>, dim3(256), dim3(mc::kBlock), 0, s, C, p);
-        MC_LAUNCHED("k1_sort_scan");
-        hipLaunchKernelGGL(k1_sort_down<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, p);
-        MC_LAUNCHED("k1_sort_down");
+    // prefix sort: up to three passes, then windows sorted in LDS
+    rc = launch_passes<T>(C, L, kPassPrefix, mc::kPrefixSlots, s);
+    if (rc) return rc;
+    for (int round = 0; round < 2; round++) {
+        hipLaunchKernelGGL(k1_window<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, round);
+        MC_LAUNCHED("k1_window");
     }
     if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
+    // emit (checks the order), then the full sort and a second emit, which
+    // return at once unless the check failed
+    for (int again = 0; again < 2; again++) {
+        if (again) {
+            rc = launch_passes<T>(C, L, kPassFull, T::kBytes, s);
+            if (rc) return rc;
+        }
+        if (L.hashed) {
+            hipLaunchKernelGGL(k1_emit_distinct<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C,
+                               again);
+            MC_LAUNCHED("k1_emit_distinct");
+        } else {
+            hipLaunchKernelGGL(k1_emit<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C, again);
+            MC_LAUNCHED("k1_emit");
+        }
+    }
     if (L.hashed) {
-        hipLaunchKernelGGL(k1_emit_distinct<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
-        MC_LAUNCHED("k1_emit_distinct");
         hipLaunchKernelGGL(k1_rank_rows, dim3(L.hash_tiles), dim3(mc::kBlock), 0, s, C);
         MC_LAUNCHED("k1_rank_rows");
-        return MC_OK;
     }
-    hipLaunchKernelGGL(k1_emit<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
-    MC_LAUNCHED("k1_emit");
     return MC_OK;
 }
 
@@ -775,22 +839,44 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
                            batch(kMapHistScan));
         MC_LAUNCHED("kn_hist_scan");
     }
-    for (uint32_t p = 0; p < P.max_passes; p++) {
-        const uint32_t tp = tiles(kMapPass + p);
-        if (!tp) continue;
-        hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + p),
-                           (int)p);
-        MC_LAUNCHED("kn_sort_up");
-        hipLaunchKernelGGL(kn_sort_scan, dim3(tiles(kMapScan + p)), dim3(mc::kBlock), 0, s,
-                           batch(kMapScan + p), (int)p);
-        MC_LAUNCHED("kn_sort_scan");
-        hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + p),
-                           (int)p);
-        MC_LAUNCHED("kn_sort_down");
+    // passes of kind `kind`: the prefix passes use pass 0's maps (every column
+    // with a delta has sort tiles there)
+    auto passes = [&](int kind, uint32_t n) -> int {
+        for (uint32_t p = 0; p < n; p++) {
+            const int m = kind == kPassPrefix ? 0 : (int)p;
+            const uint32_t tp = tiles(kMapPass + m);
+            if (!tp) continue;
+            hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + m),
+                               kind, (int)p);
+            MC_LAUNCHED("kn_sort_up");
+            hipLaunchKernelGGL(kn_sort_scan, dim3(tiles(kMapScan + m)), dim3(mc::kBlock), 0, s,
+                               batch(kMapScan + m), kind, (int)p);
+            MC_LAUNCHED("kn_sort_scan");
+            hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + m),
+                               kind, (int)p);
+            MC_LAUNCHED("kn_sort_down");
+        }
+        return MC_OK;
+    };
+    if (P.max_passes) {
+        rc = passes(kPassPrefix, mc::kPrefixSlots);
+        if (rc) return rc;
+        for (int round = 0; round < 2; round++) {
+            hipLaunchKernelGGL(kn_window, dim3(tiles(kMapPass)), dim3(mc::kBlock), 0, s,
+                               batch(kMapPass), round);
+            MC_LAUNCHED("kn_window");
+        }
     }
     if (tiles(kMapEmit)) {
-        hipLaunchKernelGGL(kn_emit, dim3(tiles(kMapEmit)), dim3(mc::kBlock), 0, s, batch(kMapEmit));
-        MC_LAUNCHED("kn_emit");
+        for (int again = 0; again < 2; again++) {
+            if (again) {
+                rc = passes(kPassFull, P.max_passes);
+                if (rc) return rc;
+            }
+            hipLaunchKernelGGL(kn_emit, dim3(tiles(kMapEmit)), dim3(mc::kBlock), 0, s,
+                               batch(kMapEmit), again);
+            MC_LAUNCHED("kn_emit");
+        }
     }
     if (tiles(kMapMergePart)) {
         hipLaunchKernelGGL(kn_merge_part, dim3(tiles(kMapMergePart)), dim3(mc::kBlock), 0, s,
@@ -911,7 +997,9 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     C.trivial = reinterpret_cast<uint32_t *>(za + L.trivial);
     C.tcount = reinterpret_cast<uint32_t *>(zb + L.tcount);
     C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
+    C.sflags = reinterpret_cast<uint32_t *>(za + L.sflags);
     C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);
+    C.emit_status2 = reinterpret_cast<uint64_t *>(za + L.emit_status2);
     C.n_ud = d_count;
     C.nd_max = delta_rows;
     C.u_d = u_d;

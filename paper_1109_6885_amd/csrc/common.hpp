@@ -12,6 +12,14 @@ namespace mc {
 constexpr int kBlock = 256;       // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 
+// Slots of ColDesc::sflags: the digit positions (+ 1, 0 = unused) of the
+// prefix passes, the flag "the prefix sort left the values out of order",
+// and the tile tickets of the two emits.
+constexpr int kPrefixSlots = 3;     // at most this many prefix passes
+constexpr double kPrefixRun = 32.0;  // wanted values per run of equal prefix
+constexpr int kSfPrefix = 0, kSfUnsorted = kPrefixSlots, kSfEmitTicket = kPrefixSlots + 1,
+              kSfEmitTicket2 = kPrefixSlots + 2, kSfSlots = 8;
+
 // ---------------------------------------------------------------------------
 // Value traits.  Stored values are always the caller's raw bytes.  For
 // ordering, a value is mapped to a "normalized" key whose unsigned
@@ -229,8 +237,10 @@ struct ColDesc {
     uint32_t *base;            // [passes][256] digit offsets
     uint32_t *trivial;         // [passes] single-digit flags (zeroed)
     uint32_t *tcount;          // [256][sort_tiles] tile counts / offsets
-    uint32_t *counters;        // [0] emit tile counter, [1] merge tile counter (zeroed)
+    uint32_t *counters;        // [1] merge tile counter, [2] compaction tile counter (zeroed)
+    uint32_t *sflags;          // Step 1(a) words, slots kSf* below (zeroed)
     uint64_t *emit_status;     // emit prefix words (zeroed)
+    uint64_t *emit_status2;    // prefix words of the emit after the full LSD sort (zeroed)
     uint64_t *merge_status;    // merge prefix words (zeroed)
     uint64_t *mbound;          // U_M entries before each merge tile's start, or null
     uint64_t *n_ud;            // |U_D| as written by Step 1(a) (zeroed)

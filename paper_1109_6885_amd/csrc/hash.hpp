@@ -153,18 +153,22 @@ __device__ void compact_tile(const ColDesc &C, char *smem) {
 }
 
 // After the radix passes over the distinct values: every sorted position
-// starts a new value.
+// starts a new value.  again: as for emit_tile (the run after the full LSD
+// sort, only when the first run found the order wrong).
 template <class T>
-__device__ void emit_distinct_tile(const ColDesc &C, uint64_t t) {
-    constexpr int P = T::kBytes;
-    const void *keys = kbuf(C, P - 1);
-    const uint32_t *rows = vbuf(C, P - 1);
+__device__ void emit_distinct_tile(const ColDesc &C, uint64_t t, bool again) {
+    if (again && C.sflags[kSfUnsorted] == 0) return;
+    const void *keys = C.keys1;  // sorted values (both sorts end in keys1 / vals1)
+    const uint32_t *rows = C.vals1;
     const uint64_t n = sort_n(C);
-    bool bad = false;
+    bool bad = false, unsorted = false;
     for (uint32_t x = threadIdx.x; x < (uint32_t)kEmitTile; x += kBlock) {
         const uint64_t i = t * kEmitTile + x;
         if (i >= n) break;
-        T::store(C.u_d, i, T::load(keys, i));
+        const typename T::K k = T::load(keys, i);
+        // distinct values: strictly increasing
+        if (i > 0 && !T::lt(T::norm(T::load(keys, i - 1)), T::norm(k))) unsorted = true;
+        T::store(C.u_d, i, k);
         const uint32_t d = rows[i];
         if (d < n)
             C.drankd[d] = (uint32_t)i;
@@ -172,6 +176,7 @@ __device__ void emit_distinct_tile(const ColDesc &C, uint64_t t) {
             bad = true;
     }
     if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+    if (unsorted && !again) C.sflags[kSfUnsorted] = 1u;
     if (t == 0 && threadIdx.x == 0) *C.n_ud = n;
 }
 

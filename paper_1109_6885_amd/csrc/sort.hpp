@@ -2,16 +2,30 @@
 // of every delta row in it (Sections 5.1 and 5.3, modified Step 1(a)).
 //
 // The paper walks the leaves of a CSB+ tree kept beside the delta; here the
-// delta is a plain append-order array, so the sorted order comes from an LSD
-// radix sort of (value, row) pairs with 8-bit digits, one digit per pass:
+// delta is a plain append-order array, so the sorted order comes from radix
+// passes over (value, row) pairs with 8-bit digits, one digit per pass:
 //   hist_tile      one read of the delta: histograms of every digit position
 //   hist_scan_col  exclusive digit offsets per position; flags positions where
-//                  every value has the same digit (those passes only copy)
+//                  every value has the same digit (those passes only copy);
+//                  picks the positions of the prefix passes
 //   per pass:  sort_up_tile    per-tile digit counts (digit-major)
 //              sort_scan_digit per-digit exclusive scan over tiles
 //              sort_down_tile  stable rank inside the tile (wave ballots),
 //                              staging through LDS, coalesced scatter
-// then emit_tile marks run heads of the sorted values, numbers them with a
+//
+// One to three global passes over the most significant varying digits (as
+// many as it takes for runs of about 32 values on average, judged from the
+// histograms) leave the values ordered by their leading bytes ("prefix"), in
+// runs of equal prefix.
+// window_sort_tile then sorts windows of one tile in LDS by the whole value,
+// first windows aligned to tiles, then windows shifted by half a tile: a run
+// of equal prefix no longer than half a tile lies inside one window of one of
+// the two rounds, so the array ends up sorted.  emit_tile checks every
+// adjacent pair; if a long run (heavy duplicates, clustered values) left the
+// order wrong, the full LSD sort over every digit runs after it (its launches
+// return at once otherwise) and emit runs again.
+//
+// emit_tile marks run heads of the sorted values, numbers them with a
 // cross-tile prefix, writes U_D and scatters each row's index (the paper's
 // tuple-id update).  Equal values collapse, so row order inside a run is
 // irrelevant; the passes are stable anyway, as LSD radix sort needs.
@@ -48,6 +62,43 @@ __device__ __forceinline__ const void *pass_src(const ColDesc &C, int p) {
 // values counted on the device when Step 1(a) hashes first.
 __device__ __forceinline__ uint64_t sort_n(const ColDesc &C) {
     return C.sort_n ? min<uint64_t>(*C.sort_n, C.nd) : C.nd;
+}
+
+// Source and destination of one radix pass, and its digit position (< 0:
+// the pass only copies).
+struct PassIO {
+    int p;
+    const void *src;
+    const uint32_t *vsrc;  // null: the rows are the identity
+    void *kdst;
+    uint32_t *vdst;
+};
+// Pass p of the full LSD sort (every digit position, least significant first).
+__device__ __forceinline__ PassIO lsd_io(const ColDesc &C, int p) {
+    PassIO io;
+    io.p = C.trivial[p] ? -1 : p;
+    io.src = pass_src(C, p);
+    io.vsrc = p == 0 ? nullptr : vbuf(C, p - 1);
+    io.kdst = kbuf(C, p);
+    io.vdst = vbuf(C, p);
+    return io;
+}
+// Slot s (0 .. kPrefixSlots - 1) of the prefix sort.  Used slots are the
+// last ones, their digit positions rising; the last slot ends in the buffers
+// the last LSD pass writes (keys1 / vals1) and copies there if no digit
+// varies.  An unused slot (p == kPassSkip) does nothing.
+constexpr int kPassCopy = -1, kPassSkip = -2;
+__device__ __forceinline__ PassIO prefix_io(const ColDesc &C, int s) {
+    PassIO io;
+    const int p = (int)C.sflags[kSfPrefix + s] - 1;
+    const bool first = s == 0 || C.sflags[kSfPrefix + s - 1] == 0;
+    const bool to1 = ((kPrefixSlots - 1 - s) & 1) == 0;  // slots alternate, the last into keys1
+    io.p = p >= 0 ? p : (s == kPrefixSlots - 1 ? kPassCopy : kPassSkip);
+    io.src = first ? C.sort_src : (to1 ? C.keys0 : C.keys1);
+    io.vsrc = first ? nullptr : (to1 ? C.vals0 : C.vals1);
+    io.kdst = to1 ? C.keys1 : C.keys0;
+    io.vdst = to1 ? C.vals1 : C.vals0;
+    return io;
 }
 
 // ---- LDS layouts -------------------------------------------------------------
@@ -92,6 +143,7 @@ template <class T>
 __device__ void hist_scan_col(const ColDesc &C, char *smem) {
     constexpr int P = T::kBytes;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *ndig = tmp + kWaves;  // distinct digits per position
     const uint64_t n = sort_n(C);
     for (int p = 0; p < P; p++) {
         const uint32_t v = C.gh[p * 256 + threadIdx.x];
@@ -99,21 +151,44 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
         const uint32_t ex = block_excl_scan(v, tmp, &tot);
         C.base[p * 256 + threadIdx.x] = ex;
         if (v == n) C.trivial[p] = 1u;
+        uint32_t nz;
+        block_excl_scan(v ? 1u : 0u, tmp, &nz);
+        if (threadIdx.x == 0) ndig[p] = nz;
+    }
+    __syncthreads();  // the flags above, written by other threads of the block
+    if (threadIdx.x == 0) {
+        // prefix digits: the most significant varying positions, as many as
+        // it takes (at most kPrefixSlots) for n / (product of their numbers
+        // of distinct digits) <= kPrefixRun
+        int pos[kPrefixSlots];
+        int k = 0;
+        double combos = 1.0;
+        for (int p = P - 1; p >= 0 && k < kPrefixSlots; p--) {
+            if (C.trivial[p]) continue;
+            pos[k++] = p;
+            combos *= (double)ndig[p];
+            if ((double)n <= combos * kPrefixRun) break;
+        }
+        for (int s = 0; s < kPrefixSlots; s++) {
+            const int from_top = kPrefixSlots - 1 - s;  // the last slot takes the top digit
+            C.sflags[kSfPrefix + s] = from_top < k ? (uint32_t)(pos[from_top] + 1) : 0u;
+        }
     }
 }
 
 // ---- one pass: per-tile counts -------------------------------------------
 
 template <class T>
-__device__ void sort_up_tile(const ColDesc &C, int p, uint32_t t, char *smem) {
-    if (C.trivial[p]) return;
+__device__ void sort_up_tile(const ColDesc &C, const PassIO &io, uint32_t t, char *smem) {
+    const int p = io.p;
+    if (p < 0) return;
     constexpr int TILE = sort_tile<T>();
     if ((uint64_t)t * TILE >= sort_n(C)) return;  // past the values: never scanned
     uint32_t *h = reinterpret_cast<uint32_t *>(smem);
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t b0 = (uint64_t)t * TILE;
-    const void *src = pass_src(C, p);
+    const void *src = io.src;
     const uint64_t n = sort_n(C);
 #pragma unroll 4
     for (int j = 0; j < SortCfg<T>::kItems; j++) {
@@ -129,8 +204,9 @@ __device__ void sort_up_tile(const ColDesc &C, int p, uint32_t t, char *smem) {
 // position of every (digit, tile).
 
 template <class T>
-__device__ void sort_scan_digit(const ColDesc &C, int p, uint32_t d, char *smem) {
-    if (C.trivial[p]) return;
+__device__ void sort_scan_digit(const ColDesc &C, const PassIO &io, uint32_t d, char *smem) {
+    const int p = io.p;
+    if (p < 0) return;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
     uint32_t *row = C.tcount + (uint64_t)d * C.sort_tiles;
     uint32_t carry = C.base[p * 256 + d];
@@ -158,10 +234,63 @@ __device__ void sort_scan_digit(const ColDesc &C, int p, uint32_t d, char *smem)
     }
 }
 
+// ---- stable rank of a tile's digits ------------------------------------------
+// Item j of thread (wave wv, lane) is tile entry wv * 64 * ITEMS + j * 64 +
+// lane (each wave owns a contiguous chunk).  Returns in slot[j] the entry's
+// position in the tile stably ordered by digit (entries >= tn are ignored),
+// and leaves in dex[d] the tile's first position of digit d.  Lanes with the
+// same digit find each other by intersecting the ballots of the digit's 8
+// bits.  Every thread of the block must call it; it ends with a barrier.
+template <int ITEMS>
+__device__ __forceinline__ void rank_digits(const uint32_t (&dig)[ITEMS], uint32_t tn,
+                                            uint32_t (*wcnt)[256], uint32_t *dex,
+                                            uint32_t *tmp, uint32_t (&slot)[ITEMS]) {
+    constexpr int WCHUNK = 64 * ITEMS;
+    const int lane = lane_id(), wv = wave_id();
+#pragma unroll
+    for (int x = 0; x < kWaves; x++) wcnt[x][threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t rank[ITEMS];
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const bool valid = (uint32_t)(wv * WCHUNK + j * 64 + lane) < tn;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (dig[j] >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t before = 0;
+        if (valid) before = wcnt[wv][dig[j]];
+        const uint32_t r = __popcll(peers & lane_lt);
+        if (valid && r == 0) wcnt[wv][dig[j]] = before + (uint32_t)__popcll(peers);
+        rank[j] = before + r;
+    }
+    __syncthreads();
+    {
+        // per digit: offsets of the waves (wave-major), then the tile prefix
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int x = 0; x < kWaves; x++) {
+            const uint32_t c = wcnt[x][d];
+            wcnt[x][d] = run;
+            run += c;
+        }
+        uint32_t all;
+        dex[d] = block_excl_scan(run, tmp, &all);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) slot[j] = dex[dig[j]] + wcnt[wv][dig[j]] + rank[j];
+}
+
 // ---- one pass: rank and scatter --------------------------------------------
 
 template <class T>
-__device__ void sort_down_tile(const ColDesc &C, int p, uint32_t t, char *smem) {
+__device__ void sort_down_tile(const ColDesc &C, const PassIO &io, uint32_t t, char *smem) {
     typedef typename T::K K;
     constexpr int ITEMS = SortCfg<T>::kItems;
     constexpr int TILE = sort_tile<T>();
@@ -172,81 +301,39 @@ __device__ void sort_down_tile(const ColDesc &C, int p, uint32_t t, char *smem) 
     const uint64_t n = sort_n(C);
     if (b0 >= n) return;  // only when hashing left fewer values than rows
     const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - b0);
-    const void *src = pass_src(C, p);
-    const uint32_t *vsrc = p == 0 ? nullptr : vbuf(C, p - 1);
-    void *kdst = kbuf(C, p);
-    uint32_t *vdst = vbuf(C, p);
+    const int p = io.p;
+    if (p == kPassSkip) return;
 
-    if (C.trivial[p]) {
+    if (p < 0) {
         // every value has the same digit here: the stable order is unchanged
         for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
-            T::store(kdst, b0 + i, T::load(src, b0 + i));
-            vdst[b0 + i] = vsrc ? vsrc[b0 + i] : (uint32_t)(b0 + i);
+            T::store(io.kdst, b0 + i, T::load(io.src, b0 + i));
+            io.vdst[b0 + i] = io.vsrc ? io.vsrc[b0 + i] : (uint32_t)(b0 + i);
         }
         return;
     }
 
     const int lane = lane_id(), wv = wave_id();
-#pragma unroll
-    for (int x = 0; x < kWaves; x++) S.wcnt[x][threadIdx.x] = 0;
-    __syncthreads();
-
     K key[ITEMS];
-    uint32_t val[ITEMS];
-    uint32_t rank[ITEMS];
-    uint32_t dig[ITEMS];
-    const uint64_t lane_lt = (1ull << lane) - 1ull;
+    uint32_t val[ITEMS], dig[ITEMS], slot[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const uint32_t li = wv * WCHUNK + j * 64 + lane;  // index inside the tile
-        const bool valid = li < tn;
-        if (valid) {
-            key[j] = T::load(src, b0 + li);
-            val[j] = vsrc ? vsrc[b0 + li] : (uint32_t)(b0 + li);
+        dig[j] = 0;
+        if (li < tn) {
+            key[j] = T::load(io.src, b0 + li);
+            val[j] = io.vsrc ? io.vsrc[b0 + li] : (uint32_t)(b0 + li);
             dig[j] = T::digit(key[j], p);
-        } else {
-            dig[j] = 0;
         }
-        // lanes with the same digit: intersect the ballots of its 8 bits
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const bool bit = (dig[j] >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
-        uint32_t before = 0;
-        if (valid) before = S.wcnt[wv][dig[j]];
-        const uint32_t r = __popcll(peers & lane_lt);
-        if (valid && r == 0) S.wcnt[wv][dig[j]] = before + (uint32_t)__popcll(peers);
-        rank[j] = before + r;
     }
-    __syncthreads();
-
-    // per digit: offsets of the waves (wave-major), tile total, tile prefix
-    {
-        const int d = threadIdx.x;
-        uint32_t run = 0;
-#pragma unroll
-        for (int x = 0; x < kWaves; x++) {
-            const uint32_t c = S.wcnt[x][d];
-            S.wcnt[x][d] = run;
-            run += c;
-        }
-        uint32_t all;
-        const uint32_t ex = block_excl_scan(run, S.tmp, &all);
-        S.dex[d] = ex;
-        S.gpos[d] = C.tcount[(uint64_t)d * C.sort_tiles + t];
-    }
-    __syncthreads();
+    S.gpos[threadIdx.x] = C.tcount[(uint64_t)threadIdx.x * C.sort_tiles + t];
+    rank_digits<ITEMS>(dig, tn, S.wcnt, S.dex, S.tmp, slot);
 
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        const uint32_t li = wv * WCHUNK + j * 64 + lane;
-        if (li < tn) {
-            const uint32_t slot = S.dex[dig[j]] + S.wcnt[wv][dig[j]] + rank[j];
-            S.keys[slot] = key[j];
-            S.vals[slot] = val[j];
+        if ((uint32_t)(wv * WCHUNK + j * 64 + lane) < tn) {
+            S.keys[slot[j]] = key[j];
+            S.vals[slot[j]] = val[j];
         }
     }
     __syncthreads();
@@ -257,13 +344,155 @@ __device__ void sort_down_tile(const ColDesc &C, int p, uint32_t t, char *smem) 
         const uint32_t d = T::digit(k, p);
         const uint64_t pos = (uint64_t)S.gpos[d] + (i - S.dex[d]);
         if (pos < n) {  // always true for consistent counts; never write outside
-            T::store(kdst, pos, k);
-            vdst[pos] = S.vals[i];
+            T::store(io.kdst, pos, k);
+            io.vdst[pos] = S.vals[i];
         } else {
             bad = true;
         }
     }
     if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+}
+
+// ---- windows sorted in LDS after the prefix passes --------------------------
+// Round 0 sorts [t*TILE, (t+1)*TILE), round 1 [t*TILE + TILE/2, ...), in place
+// in keys1 / vals1.  The window is already ordered by prefix, so only runs of
+// equal prefix need ordering: a value's place in its run is the number of
+// run members that are smaller (or equal and before it).  Runs longer than
+// kRunLimit keep their place if already ordered (runs of one repeated value);
+// a long run out of order makes the whole window take LDS radix passes over
+// every varying digit.
+
+constexpr uint32_t kRunLimit = 256;
+
+// The prefix of a value: its digits at the used prefix slots (pp[s] < 0: unused).
+template <class T>
+__device__ __forceinline__ uint32_t prefix_of(const typename T::K &k, const int (&pp)[kPrefixSlots]) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int s = 0; s < kPrefixSlots; s++)
+        if (pp[s] >= 0) v = (v << 8) | T::digit(k, pp[s]);
+    return v;
+}
+
+template <class T>
+__device__ void window_radix(const ColDesc &C, DownSmem<T> &S, uint32_t tn) {
+    typedef typename T::K K;
+    constexpr int P = T::kBytes;
+    constexpr int ITEMS = SortCfg<T>::kItems;
+    constexpr int WCHUNK = 64 * ITEMS;
+    const int lane = lane_id(), wv = wave_id();
+    for (int p = 0; p < P; p++) {
+        if (C.trivial[p]) continue;  // the same for the whole block
+        K key[ITEMS];
+        uint32_t val[ITEMS], dig[ITEMS], slot[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            const uint32_t li = wv * WCHUNK + j * 64 + lane;
+            dig[j] = 0;
+            if (li < tn) {
+                key[j] = S.keys[li];
+                val[j] = S.vals[li];
+                dig[j] = T::digit(key[j], p);
+            }
+        }
+        rank_digits<ITEMS>(dig, tn, S.wcnt, S.dex, S.tmp, slot);  // ends with a barrier
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            if ((uint32_t)(wv * WCHUNK + j * 64 + lane) < tn) {
+                S.keys[slot[j]] = key[j];
+                S.vals[slot[j]] = val[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__device__ void window_sort_tile(const ColDesc &C, int round, uint32_t t, char *smem) {
+    typedef typename T::K K;
+    constexpr int ITEMS = SortCfg<T>::kItems;
+    constexpr int TILE = sort_tile<T>();
+    constexpr int NW = TILE / 64;  // words of the run-head mask
+    DownSmem<T> &S = *reinterpret_cast<DownSmem<T> *>(smem);
+    uint64_t *heads = reinterpret_cast<uint64_t *>(&S.wcnt[0][0]);  // NW words, counting path only
+    const uint64_t n = sort_n(C);
+    const uint64_t b0 = (uint64_t)t * TILE + (round ? TILE / 2 : 0);
+    if (b0 >= n) return;
+    const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - b0);
+    int pp[kPrefixSlots];
+#pragma unroll
+    for (int s = 0; s < kPrefixSlots; s++) pp[s] = (int)C.sflags[kSfPrefix + s] - 1;
+    if (pp[kPrefixSlots - 1] < 0) return;  // no digit varies: every value is the same
+    if (threadIdx.x == 0) S.tmp[0] = 0;  // "a long run is out of order"
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
+        S.keys[i] = T::load(C.keys1, b0 + i);
+        S.vals[i] = C.vals1[b0 + i];
+    }
+    __syncthreads();
+    // run heads: bit i set where a run of equal prefix starts (positions past
+    // the window count as heads, so every run ends inside the mask)
+    const int lane = lane_id(), wv = wave_id();
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t i = j * kBlock + wv * 64 + lane;
+        bool h = true;
+        if (i < tn && i > 0)
+            h = prefix_of<T>(S.keys[i], pp) != prefix_of<T>(S.keys[i - 1], pp);
+        const uint64_t bal = __ballot(h);
+        if (lane == 0) heads[i / 64] = bal;
+    }
+    __syncthreads();
+
+    uint32_t npos[ITEMS];
+    bool disorder = false;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t i = j * kBlock + wv * 64 + lane;
+        npos[j] = i;
+        if (i >= tn) continue;
+        // run [s, e) around i
+        uint32_t w = i / 64;
+        const uint32_t bit = i & 63u;
+        uint64_t m = heads[w] & (bit == 63 ? ~0ull : ((2ull << bit) - 1ull));
+        while (m == 0) m = heads[--w];  // position 0 is a head
+        const uint32_t s = w * 64 + 63 - (uint32_t)__clzll((long long)m);
+        w = i / 64;
+        m = bit == 63 ? 0ull : (heads[w] & ~((2ull << bit) - 1ull));
+        while (m == 0 && ++w < (uint32_t)NW) m = heads[w];
+        const uint32_t e = m ? min<uint32_t>(w * 64 + (uint32_t)(__ffsll((long long)m) - 1), tn) : tn;
+        const K k = S.keys[i];
+        const typename T::N kn = T::norm(k);
+        if (e - s - 1 > kRunLimit) {
+            // long run: keeps its place if already in order
+            if (i > s && T::lt(kn, T::norm(S.keys[i - 1]))) disorder = true;
+            continue;
+        }
+        uint32_t rank = 0;
+#pragma unroll 4
+        for (uint32_t q = s; q < i; q++) rank += T::le(T::norm(S.keys[q]), kn) ? 1u : 0u;
+#pragma unroll 4
+        for (uint32_t q = i + 1; q < e; q++) rank += T::lt(T::norm(S.keys[q]), kn) ? 1u : 0u;
+        npos[j] = s + rank;
+    }
+    if (disorder) S.tmp[0] = 1u;
+    __syncthreads();
+    if (S.tmp[0] == 0) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            const uint32_t i = j * kBlock + wv * 64 + lane;
+            if (i < tn && npos[j] != i) {
+                T::store(C.keys1, b0 + npos[j], S.keys[i]);
+                C.vals1[b0 + npos[j]] = S.vals[i];
+            }
+        }
+        return;
+    }
+    __syncthreads();  // every thread has read S.tmp[0] and the mask before the radix passes
+    window_radix<T>(C, S, tn);
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
+        T::store(C.keys1, b0 + i, S.keys[i]);
+        C.vals1[b0 + i] = S.vals[i];
+    }
 }
 
 // ---- run heads -> U_D and the delta rows' indices ---------------------------
@@ -274,20 +503,25 @@ constexpr int kEmitTile = kBlock * kEmitItems;
 template <class T>
 struct EmitSmem {
     typename T::K keys[kEmitTile + 1];  // keys[0]: the value before the tile
+    uint16_t head[kEmitTile];           // LDS slot of the tile's r-th run head
     uint32_t tile;
     uint32_t tmp[kWaves];
     uint64_t lb64[kWaves + 1];
     int lb32[kWaves];
 };
 
+// again = false: the emit after the prefix sort, which also checks the
+// order; again = true: the emit after the full LSD sort, only when that check
+// failed (its own tile counter and prefix words).
 template <class T>
-__device__ void emit_tile(const ColDesc &C, char *smem) {
+__device__ void emit_tile(const ColDesc &C, char *smem, bool again) {
     typedef typename T::K K;
     EmitSmem<T> &S = *reinterpret_cast<EmitSmem<T> *>(smem);
-    constexpr int P = T::kBytes;
-    const void *keys = kbuf(C, P - 1);  // sorted values after the last pass
-    const uint32_t *rows = vbuf(C, P - 1);
-    if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[0], 1u);
+    if (again && C.sflags[kSfUnsorted] == 0) return;
+    const void *keys = C.keys1;  // sorted values (both sorts end in keys1 / vals1)
+    const uint32_t *rows = C.vals1;
+    uint64_t *status = again ? C.emit_status2 : C.emit_status;
+    if (threadIdx.x == 0) S.tile = atomicAdd(&C.sflags[again ? kSfEmitTicket2 : kSfEmitTicket], 1u);
     __syncthreads();
     const uint32_t t = S.tile;
     const uint64_t tb = (uint64_t)t * kEmitTile;
@@ -300,31 +534,42 @@ __device__ void emit_tile(const ColDesc &C, char *smem) {
     const uint64_t i0 = tb + (uint64_t)threadIdx.x * kEmitItems;
     const uint32_t l0 = threadIdx.x * kEmitItems;
 
-    K k[kEmitItems];
     uint32_t head = 0;  // bit j: position i0 + j starts a new value
+    bool unsorted = false;
 #pragma unroll
     for (int j = 0; j < kEmitItems; j++) {
         const uint64_t i = i0 + j;
         if (i < C.nd) {
-            k[j] = S.keys[l0 + j + 1];
-            const bool h = (i == 0) || !T::keq(k[j], S.keys[l0 + j]);
+            const K k = S.keys[l0 + j + 1], prev = S.keys[l0 + j];
+            const bool h = (i == 0) || !T::keq(k, prev);
             head |= (uint32_t)h << j;
+            if (i > 0 && T::lt(T::norm(k), T::norm(prev))) unsorted = true;
         }
     }
+    if (unsorted && !again) C.sflags[kSfUnsorted] = 1u;
     const uint32_t cnt = __popc(head);
     uint32_t tot;
     const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);
-    const uint64_t tile_prefix = lookback_block(C.emit_status, t, tot, C.err, S.lb64, S.lb32);
+    lookback_publish(status, t, tot);
+    {
+        uint32_t lo = ex;
+#pragma unroll
+        for (int j = 0; j < kEmitItems; j++)
+            if ((head >> j) & 1u) S.head[lo++] = (uint16_t)(l0 + j + 1);
+    }
+    const uint64_t tile_prefix = lookback_resolve(status, t, tot, C.err, S.lb64, S.lb32);
+    __syncthreads();  // head slots complete
+    for (uint32_t r = threadIdx.x; r < tot; r += kBlock) {
+        const uint64_t idx = tile_prefix + r;
+        if (idx < C.nd) T::store(C.u_d, idx, S.keys[S.head[r]]);
+    }
     uint64_t idx = tile_prefix + ex;  // heads seen so far, over the whole array
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < kEmitItems; j++) {
         const uint64_t i = i0 + j;
         if (i < C.nd) {
-            if ((head >> j) & 1u) {
-                if (idx < C.nd) T::store(C.u_d, idx, k[j]);
-                idx++;
-            }
+            if ((head >> j) & 1u) idx++;
             const uint32_t row = rows[i];
             if (row < C.nd && idx - 1 < C.nd)
                 C.drank[row] = (uint32_t)(idx - 1);

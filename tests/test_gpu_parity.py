@@ -286,6 +286,60 @@ def test_partitioned_merge(vtype, n_um, nd, frac_new):
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+def _clustered_delta(rng, vtype, case):
+    """Deltas where most values share the two leading bytes that vary at all
+    (a few random outliers make those bytes vary), so the windows of the
+    prefix sort cannot order them and the full sort must."""
+    outliers = gen.random_values(rng, vtype, 20)
+    if case == "one_prefix":  # 60,000 values behind one 2-byte prefix
+        n = 60_000
+        if vtype == "str16":
+            d = rng.integers(0x20, 0x7F, size=(n, 16), dtype=np.uint8)
+            d[:, 0], d[:, 1] = ord("a"), ord("b")
+        elif vtype == "u32":
+            d = (np.uint32(0x1234) << np.uint32(16)) | rng.integers(0, 1 << 16, n).astype(np.uint32)
+        else:
+            d = (np.uint64(0x1234) << np.uint64(48)) | rng.integers(0, 1 << 48, n, dtype=np.uint64)
+    elif case == "one_misplaced":  # 20,000 copies of x and one smaller value next to them
+        if vtype == "str16":
+            d = np.full((20_001, 16), ord("m"), np.uint8)
+            d[7_777, 5] = ord("a")
+        else:
+            dt = np.uint32 if vtype == "u32" else np.uint64
+            d = np.full(20_001, 0x7F7F7F7F if vtype == "u32" else 0x7F7F7F7F7F7F7F7F, dt)
+            d[7_777] -= dt(5)
+    else:
+        raise ValueError(case)
+    d = np.concatenate([d, outliers])
+    return d[rng.permutation(d.shape[0])]
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+@pytest.mark.parametrize("case", ["one_prefix", "one_misplaced"])
+def test_prefix_sort_fallback(vtype, case):
+    """Values sharing their leading bytes over more than half a window: the
+    emit's order check fails and the full LSD sort takes over."""
+    rng = np.random.default_rng(91)
+    base = gen.random_column(rng, vtype, 3000, 20_000, 0)
+    col = gen.Column(vtype, base.u_m, base.main_packed, base.n_main, base.w,
+                     _clustered_delta(rng, vtype, case))
+    say(f"case prefix-sort fallback {vtype} {case} nd={col.n_delta}")
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+def test_prefix_sort_fallback_hash_route():
+    """The same on the hashing route: 2^21 + 5 rows over 400,000 distinct
+    values, all but 50 of them sharing their two leading bytes."""
+    rng = np.random.default_rng(92)
+    base = gen.random_column(rng, "u64", 1000, 5000, 0)
+    pool = (np.uint64(0x00AB) << np.uint64(48)) | rng.integers(0, 1 << 48, 400_000, dtype=np.uint64)
+    pool[:50] = gen.random_values(rng, "u64", 50)  # make the two leading bytes vary
+    delta = pool[rng.integers(0, pool.shape[0], (1 << 21) + 5)]
+    col = gen.Column("u64", base.u_m, base.main_packed, base.n_main, base.w, delta)
+    say("case prefix-sort fallback, hashing route")
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
 def test_naive_step2_matches_oracle(vtype):
     """The unoptimized Step 2(b) (binary search in U', Section 5.2) gives
