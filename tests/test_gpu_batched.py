@@ -63,6 +63,40 @@ def test_batched_partitioned_merge():
         check_col(c, o.fetch())
 
 
+def test_batched_prefix_sort_fallback():
+    """Columns whose values share their leading bytes (the order check fails
+    and the persistent full sort runs for them) between ordinary columns, in
+    one batch; twice, through a graph, so the full sort's counters restart."""
+    rng = np.random.default_rng(8)
+    cols = []
+    for vt in ("u64", "u32", "str16"):
+        base = gen.random_column(rng, vt, 2000, 10_000, 0)
+        if vt == "str16":
+            d = rng.integers(0x20, 0x7F, size=(30_000, 16), dtype=np.uint8)
+            d[:, 0], d[:, 1] = ord("q"), ord("r")
+        elif vt == "u32":
+            d = (np.uint32(0x4321) << np.uint32(16)) | rng.integers(0, 1 << 16, 30_000).astype(np.uint32)
+        else:
+            d = (np.uint64(0x4321) << np.uint64(48)) | rng.integers(0, 1 << 48, 30_000, dtype=np.uint64)
+        d = np.concatenate([d, gen.random_values(rng, vt, 10)])
+        cols.append(gen.Column(vt, base.u_m, base.main_packed, base.n_main, base.w,
+                               d[rng.permutation(d.shape[0])]))
+        cols.append(gen.random_column(rng, vt, 5000, 20_000, 7_000, 0.5))
+    say(f"case batched prefix-sort fallback, {len(cols)} columns")
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, graph = cm.merge_columns_batched(dcols, graph=True)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    for o in outs:
+        o.new_codes.zero_()
+        o.new_dict.zero_()
+    graph.launch()
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+
+
 def test_batched_graph_replays():
     cols = small_batch(24, 0.001)
     say(f"case batched graph, {len(cols)} columns")
