@@ -85,6 +85,12 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
     rows = sum(c.n_main + c.n_delta for c in cols)
     b_alg_in = sum(c.n_main * c.w / 8 + c.u_m.shape[0] * c.value_len + c.n_delta * c.value_len
                    for c in cols)
+    # launch shapes picked by the autotuner on this batch (untimed), used by
+    # both the batched and the per-column runs below
+    ctx = cm.Context(torch.cuda.current_device())
+    tune, tune_ms, touts = cm.autotune_batched(dcols, stream=stream, ctx=ctx)
+    del touts
+    log(f"autotuned shapes {tune} (candidate ms {[round(x, 3) for x in tune_ms]})")
     outs, graph = cm.merge_columns_batched(dcols, graph=True, stream=stream, ctx=ctx)
     torch.cuda.synchronize()
     scal = [o.scalars() for o in outs]
@@ -123,7 +129,8 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
             "batched_graph_ms": t_b * 1e3, "plain_ms": t_p * 1e3,
             "batched_tuples_s": rows / t_b, "plain_tuples_s": rows / t_p,
             "batched_gbs_alg": b_alg / t_b / 1e9, "plain_gbs_alg": b_alg / t_p / 1e9,
-            "speedup": t_p / t_b, "batched_equals_plain": bool(same)}
+            "speedup": t_p / t_b, "batched_equals_plain": bool(same),
+            "autotuned": tune, "autotune_candidate_ms": tune_ms}
 
 
 def bench_serve(args):

@@ -212,6 +212,42 @@ int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins,
 int mc_graph_launch(mc_graph *graph, struct ihipStream_t *stream);
 void mc_graph_destroy(mc_graph *graph);
 
+/* ---- tuning ------------------------------------------------------------ */
+
+/* Launch shapes a context uses for every later merge (single column and
+ * batched; a captured graph keeps the shapes it was captured with).
+ *   repack_codes: rows per Step 2(b) workgroup tile, 1024, 2048 (default)
+ *                 or 4096, i.e. 4, 8 or 16 codes per thread;
+ *   prefix_run:   values per run of equal prefix that Step 1(a) aims for
+ *                 when it picks how many leading digits to sort globally
+ *                 (4 .. 1024, default 32; more runs -> more radix passes,
+ *                 longer runs -> more work in the LDS windows).
+ * The results do not depend on them. */
+typedef struct mc_tuning {
+    uint32_t repack_codes;
+    uint32_t prefix_run;
+    uint32_t reserved[2]; /* zero */
+} mc_tuning;
+
+/* MC_E_ARG if a value is outside the ranges above (the context keeps its
+ * previous shapes). */
+int mc_ctx_set_tuning(mc_ctx *ctx, const mc_tuning *tuning);
+int mc_ctx_get_tuning(const mc_ctx *ctx, mc_tuning *tuning);
+
+/* Autotuner for the batched merge: runs the given batch (same arguments as
+ * mc_merge_columns_batched, no graph) with each candidate shape -- first
+ * repack_codes in {1024, 2048, 4096}, then, with the best of those,
+ * prefix_run in {16, 32, 64} -- timing each with HIP events on `stream`
+ * (best of two runs after one warm-up run), stores the fastest in the
+ * context and returns it in *chosen.  times_ms (nullable) receives the 6
+ * candidate times in that order.  It synchronizes the stream; the outputs
+ * hold the batch's merge result afterwards. */
+int mc_autotune_batched(mc_ctx *ctx, const mc_column_in *ins,
+                        const mc_column_out *outs, uint32_t ncols,
+                        void *scratch, uint64_t scratch_bytes,
+                        struct ihipStream_t *stream, mc_tuning *chosen,
+                        float *times_ms);
+
 /* ---- step timing (for measurement) ------------------------------------ */
 
 /* Enabling (or re-enabling) timing starts a new measurement: from then on

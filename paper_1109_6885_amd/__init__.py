@@ -19,8 +19,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (ColmergeError, McColumnIn, McColumnOut, McResult, TYPE_CODES, VALUE_LEN,
-                   check, load)
+from ._lib import (ColmergeError, McColumnIn, McColumnOut, McResult, McTuning, TYPE_CODES,
+                   VALUE_LEN, check, load)
 
 __all__ = [
     "Context", "context", "to_device", "value_tensor_empty", "merge_bounds", "merge_column",
@@ -49,6 +49,16 @@ class Context:
         arr = (ctypes.c_float * 5)()
         check(load().mc_ctx_step_times(self.handle, arr), "mc_ctx_step_times")
         return list(arr)
+
+    def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32):
+        """mc_ctx_set_tuning: launch shapes for every later merge on this context."""
+        t = McTuning(repack_codes, prefix_run)
+        check(load().mc_ctx_set_tuning(self.handle, ctypes.byref(t)), "mc_ctx_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = McTuning()
+        check(load().mc_ctx_get_tuning(self.handle, ctypes.byref(t)), "mc_ctx_get_tuning")
+        return {"repack_codes": t.repack_codes, "prefix_run": t.prefix_run}
 
     def __del__(self):
         try:
@@ -373,6 +383,30 @@ def batched_bounds(cols) -> int:
     check(load().mc_merge_batched_bounds(arr, len(cols), ctypes.byref(sb)),
           "mc_merge_batched_bounds")
     return int(sb.value)
+
+
+# candidates of mc_autotune_batched, in the order of its times
+AUTOTUNE_CANDIDATES = ([{"repack_codes": c, "prefix_run": 32} for c in (1024, 2048, 4096)]
+                       + [{"repack_codes": None, "prefix_run": r} for r in (16, 32, 64)])
+
+
+def autotune_batched(cols, outs=None, scratch=None, stream=None, ctx=None):
+    """mc_autotune_batched: time the candidate launch shapes on this batch,
+    keep the fastest in the context.  Returns (chosen dict, candidate ms list,
+    outs); the outputs hold the batch's merge result."""
+    ctx = ctx or context()
+    if outs is None:
+        outs = [alloc_output(c) for c in cols]
+    if scratch is None:
+        scratch = alloc_scratch(batched_bounds(cols))
+    ins = (McColumnIn * len(cols))(*[c.descriptor() for c in cols])
+    os_ = (McColumnOut * len(cols))(*[o.descriptor() for o in outs])
+    t = McTuning()
+    times = (ctypes.c_float * 6)()
+    check(load().mc_autotune_batched(ctx.handle, ins, os_, len(cols), _ptr(scratch),
+                                     scratch.numel(), _stream(stream), ctypes.byref(t), times),
+          "mc_autotune_batched")
+    return {"repack_codes": t.repack_codes, "prefix_run": t.prefix_run}, list(times), outs
 
 
 def merge_columns_batched(cols, outs=None, scratch=None, graph: bool = False, stream=None,

@@ -29,6 +29,7 @@ EXPORTS = [
     "mc_merge_dictionaries_scratch", "mc_reencode", "mc_merge_batched_bounds",
     "mc_merge_columns_batched", "mc_graph_launch", "mc_graph_destroy", "mc_ctx_set_timing",
     "mc_ctx_step_times", "mc_copy_bytes", "mc_gather_ref", "mc_merge_column_naive",
+    "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched",
 ]
 
 
@@ -50,6 +51,11 @@ class McColumnOut(ctypes.Structure):
                 ("new_codes", ctypes.c_void_p), ("new_codes_cap_words", ctypes.c_uint64),
                 ("x_main", ctypes.c_void_p), ("x_delta", ctypes.c_void_p),
                 ("result", ctypes.c_void_p)]
+
+
+class McTuning(ctypes.Structure):
+    _fields_ = [("repack_codes", ctypes.c_uint32), ("prefix_run", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class ColmergeError(RuntimeError):
@@ -95,6 +101,11 @@ def load():
         "mc_ctx_step_times": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_float)]),
         "mc_copy_bytes": (ctypes.c_int, [p, p, p, u64, p]),
         "mc_gather_ref": (ctypes.c_int, [p, p, u64, p, u32, u32, p, p]),
+        "mc_ctx_set_tuning": (ctypes.c_int, [p, ctypes.POINTER(McTuning)]),
+        "mc_ctx_get_tuning": (ctypes.c_int, [p, ctypes.POINTER(McTuning)]),
+        "mc_autotune_batched": (ctypes.c_int, [p, pin, pout, u32, p, u64, p,
+                                               ctypes.POINTER(McTuning),
+                                               ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

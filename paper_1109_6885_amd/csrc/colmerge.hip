@@ -31,6 +31,8 @@ struct mc_ctx {
     void *meta_host = nullptr;
     uint64_t meta_cap = 0;
     hipEvent_t meta_event = nullptr;
+    // launch shapes (mc_ctx_set_tuning / mc_autotune_batched)
+    mc_tuning tune = {2048u, 32u, {0u, 0u}};
 };
 
 struct mc_graph {
@@ -124,6 +126,7 @@ struct ColLayout {
              b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
+    uint32_t repack_codes = mc::kRepackCodes, prefix_run = 0;  // launch shapes
     bool partitioned = false;  // merge tile boundaries come from merge_partition
     bool hashed = false;       // Step 1(a) deduplicates by hashing first
     uint64_t hmask = 0;
@@ -144,9 +147,13 @@ constexpr uint64_t kMergePartMinTiles = 512;
 // Workgroups of merge_partition: one wave per tile boundary (tiles + 1).
 uint64_t merge_part_blocks(uint64_t merge_tiles) { return ceil_div(merge_tiles + 1, mc::kWaves); }
 
+const mc_tuning kDefaultTuning = {2048u, 32u, {0u, 0u}};
+
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
-                     bool allow_hash = true) {
+                     bool allow_hash = true, const mc_tuning &tune = kDefaultTuning) {
     ColLayout L;
+    L.repack_codes = tune.repack_codes;
+    L.prefix_run = tune.prefix_run;
     const uint32_t E = value_len(type);
     L.hashed = allow_hash && nd >= kHashMinRows;
     if (L.hashed) {
@@ -160,7 +167,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.emit_tiles = (uint32_t)ceil_div(nd, mc::kEmitTile);
     L.hist_tiles = (uint32_t)ceil_div(nd, mc::kHistChunk);
     L.merge_tiles = ceil_div(n_um + nd, merge_tile_of(type));
-    L.repack_tiles = ceil_div(n_main + nd, mc::kRepackCodes);
+    L.repack_tiles = ceil_div(n_main + nd, L.repack_codes);
     L.xc_tiles = n_main ? ceil_div(n_um, mc::kXCompactTile) : 0;
     Carver z;
     L.counters = z.take(16 * 4);
@@ -265,6 +272,7 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.emit_status2 = reinterpret_cast<uint64_t *>(za + L.emit_status2);
     C.merge_status = reinterpret_cast<uint64_t *>(za + L.merge_status);
     C.mbound = L.partitioned ? reinterpret_cast<uint64_t *>(za + L.mbound) : nullptr;
+    C.prefix_run = L.prefix_run;
     C.n_ud = reinterpret_cast<uint64_t *>(za + L.n_ud);
     C.n_ud_in = C.n_ud;
     C.nd_max = in->delta_rows;
@@ -400,9 +408,10 @@ __global__ __launch_bounds__(256) void k1_naive(mc::ColDesc C) {
 __global__ __launch_bounds__(256) void k1_xcompact(mc::ColDesc C) {
     mc::xcompact_tile(C, blockIdx.x);
 }
+template <int CODES>
 __global__ __launch_bounds__(256) void k1_repack(mc::ColDesc C) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
-    mc::repack_tile(C, blockIdx.x, smem);
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmemT<CODES>)];
+    mc::repack_tile<CODES>(C, blockIdx.x, smem);
 }
 
 // ---- batched ----
@@ -506,10 +515,11 @@ __global__ __launch_bounds__(256) void kn_xcompact(Batch B) {
     const uint32_t j = find_col(B, blockIdx.x);
     mc::xcompact_tile(B.cols[j], blockIdx.x - B.map[j]);
 }
+template <int CODES>
 __global__ __launch_bounds__(256) void kn_repack(Batch B) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmem)];
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmemT<CODES>)];
     const uint32_t j = find_col(B, blockIdx.x);
-    mc::repack_tile(B.cols[j], blockIdx.x - B.map[j], smem);
+    mc::repack_tile<CODES>(B.cols[j], blockIdx.x - B.map[j], smem);
 }
 
 // Random-gather reference: out[i] = table[idx[i] % n_table] for 4- or
@@ -628,15 +638,19 @@ int launch_merge(const mc::ColDesc &C, uint64_t merge_tiles, hipStream_t s) {
     return MC_OK;
 }
 
-int launch_repack(const mc::ColDesc &C, hipStream_t s) {
+int launch_repack(const mc::ColDesc &C, uint32_t codes, hipStream_t s) {
     if (C.xdev && C.n_um) {
         hipLaunchKernelGGL(k1_xcompact, dim3((uint32_t)ceil_div(C.n_um, mc::kXCompactTile)),
                            dim3(mc::kBlock), 0, s, C);
         MC_LAUNCHED("k1_xcompact");
     }
-    const uint64_t grid = ceil_div(C.n_main + C.nd, mc::kRepackCodes);
+    const uint64_t grid = ceil_div(C.n_main + C.nd, codes);
     if (grid == 0) return MC_OK;
-    hipLaunchKernelGGL(k1_repack, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C);
+    switch (codes) {
+        case 1024: hipLaunchKernelGGL(k1_repack<1024>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C); break;
+        case 4096: hipLaunchKernelGGL(k1_repack<4096>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C); break;
+        default: hipLaunchKernelGGL(k1_repack<2048>, dim3((uint32_t)grid), dim3(mc::kBlock), 0, s, C); break;
+    }
     MC_LAUNCHED("k1_repack");
     return MC_OK;
 }
@@ -718,7 +732,7 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
     rc = launch_merge<T>(C, L.merge_tiles, s);
     if (rc) return rc;
     if (ev) MC_HIP(hipEventRecord(ev[3], s));
-    rc = naive ? launch_naive<T>(C, s) : launch_repack(C, s);
+    rc = naive ? launch_naive<T>(C, s) : launch_repack(C, L.repack_codes, s);
     if (rc) return rc;
     if (ev) {
         MC_HIP(hipEventRecord(ev[4], s));
@@ -734,7 +748,8 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
     if (rc) return rc;
     rc = check_out(in, out);
     if (rc) return rc;
-    const ColLayout L = col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows);
+    const ColLayout L =
+        col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows, true, ctx->tune);
     if (!scratch || scratch_bytes < single_scratch(L))
         return fail(MC_E_CAP, "scratch below mc_merge_bounds");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
@@ -764,9 +779,16 @@ struct BatchPlan {
     std::vector<ColLayout> L;
     std::vector<uint32_t> maps;  // kNumMaps x (ncols + 1)
     uint32_t max_passes = 0;
+    uint32_t repack_codes = mc::kRepackCodes;
 };
 
-int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P) {
+int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs, uint32_t ncols,
+                void *scratch, uint64_t scratch_bytes, hipStream_t stream, const mc_tuning &tune,
+                mc_graph **graph);
+
+int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
+               const mc_tuning &tune = kDefaultTuning) {
+    P.repack_codes = tune.repack_codes;
     P.z_off.resize(ncols);
     P.b_off.resize(ncols);
     P.L.resize(ncols);
@@ -776,7 +798,7 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P) {
         int rc = check_in(&ins[i]);
         if (rc) return rc;
         P.L[i] = col_layout(ins[i].type, ins[i].main_dict_len, ins[i].delta_rows,
-                            ins[i].main_rows, /*allow_hash=*/false);
+                            ins[i].main_rows, /*allow_hash=*/false, tune);
         P.z_off[i] = z;
         z += P.L[i].z_size;
         P.b_off[i] = b;
@@ -893,8 +915,12 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
         MC_LAUNCHED("kn_xcompact");
     }
     if (tiles(kMapRepack)) {
-        hipLaunchKernelGGL(kn_repack, dim3(tiles(kMapRepack)), dim3(mc::kBlock), 0, s,
-                           batch(kMapRepack));
+        const dim3 g(tiles(kMapRepack)), b(mc::kBlock);
+        switch (P.repack_codes) {
+            case 1024: hipLaunchKernelGGL(kn_repack<1024>, g, b, 0, s, batch(kMapRepack)); break;
+            case 4096: hipLaunchKernelGGL(kn_repack<4096>, g, b, 0, s, batch(kMapRepack)); break;
+            default: hipLaunchKernelGGL(kn_repack<2048>, g, b, 0, s, batch(kMapRepack)); break;
+        }
         MC_LAUNCHED("kn_repack");
     }
     return MC_OK;
@@ -977,7 +1003,7 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     if (!aligned16(delta_values) || !aligned16(u_d) || !aligned4(drank) ||
         (reinterpret_cast<uintptr_t>(d_count) & 7u))
         return fail(MC_E_ARG, "misaligned buffer");
-    const ColLayout L = col_layout(type, 0, delta_rows, 0);
+    const ColLayout L = col_layout(type, 0, delta_rows, 0, true, ctx->tune);
     if (!scratch || scratch_bytes < single_scratch(L)) return fail(MC_E_CAP, "scratch too small");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
     char *za = static_cast<char *>(scratch), *zb = za + L.z_size;
@@ -1002,6 +1028,7 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     C.emit_status2 = reinterpret_cast<uint64_t *>(za + L.emit_status2);
     C.n_ud = d_count;
     C.nd_max = delta_rows;
+    C.prefix_run = L.prefix_run;
     C.u_d = u_d;
     C.drank = drank;
     set_hash_fields(C, za, zb, L);
@@ -1098,7 +1125,7 @@ int mc_reencode(mc_ctx *ctx, const uint64_t *main_codes, uint64_t n_main, uint32
     C.err = &result->error;
     C.out = out;
     C.out_cap = out_cap_words;
-    return launch_repack(C, s);
+    return launch_repack(C, ctx->tune.repack_codes, s);
 }
 
 int mc_ctx_set_timing(mc_ctx *ctx, int enable) {
@@ -1176,10 +1203,99 @@ int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_colu
                              uint32_t ncols, void *scratch, uint64_t scratch_bytes,
                              hipStream_t stream, mc_graph **graph) {
     if (!ctx) return fail(MC_E_ARG, "null context");
+    return batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, ctx->tune, graph);
+}
+
+int mc_ctx_set_tuning(mc_ctx *ctx, const mc_tuning *t) {
+    if (!ctx || !t) return fail(MC_E_ARG, "null argument");
+    if (t->repack_codes != 1024 && t->repack_codes != 2048 && t->repack_codes != 4096)
+        return fail(MC_E_ARG, "repack_codes must be 1024, 2048 or 4096");
+    if (t->prefix_run < 4 || t->prefix_run > 1024)
+        return fail(MC_E_ARG, "prefix_run must be in [4, 1024]");
+    if (t->reserved[0] || t->reserved[1]) return fail(MC_E_ARG, "reserved fields must be zero");
+    ctx->tune = *t;
+    return MC_OK;
+}
+
+int mc_ctx_get_tuning(const mc_ctx *ctx, mc_tuning *t) {
+    if (!ctx || !t) return fail(MC_E_ARG, "null argument");
+    *t = ctx->tune;
+    return MC_OK;
+}
+
+int mc_autotune_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
+                        uint32_t ncols, void *scratch, uint64_t scratch_bytes, hipStream_t stream,
+                        mc_tuning *chosen, float *times_ms) {
+    if (!ctx || !chosen) return fail(MC_E_ARG, "null argument");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MC_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    // one warm-up run, then the best of two timed runs
+    auto time_one = [&](const mc_tuning &t, float *ms) -> int {
+        int rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, t, nullptr);
+        if (rc) return rc;
+        float best = 0.0f;
+        for (int r = 0; r < 2; r++) {
+            MC_HIP(hipEventRecord(e0, stream));
+            rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, t, nullptr);
+            if (rc) return rc;
+            MC_HIP(hipEventRecord(e1, stream));
+            MC_HIP(hipEventSynchronize(e1));
+            float x = 0.0f;
+            MC_HIP(hipEventElapsedTime(&x, e0, e1));
+            best = r == 0 ? x : std::min(best, x);
+        }
+        *ms = best;
+        return MC_OK;
+    };
+    int rc = MC_OK;
+    float times[6] = {0};
+    mc_tuning best = kDefaultTuning;
+    float best_ms = 0.0f;
+    const uint32_t codes[3] = {1024u, 2048u, 4096u}, runs[3] = {16u, 32u, 64u};
+    for (int i = 0; i < 3 && rc == MC_OK; i++) {
+        mc_tuning t = kDefaultTuning;
+        t.repack_codes = codes[i];
+        rc = time_one(t, &times[i]);
+        if (rc == MC_OK && (i == 0 || times[i] < best_ms)) {
+            best = t;
+            best_ms = times[i];
+        }
+    }
+    const mc_tuning by_codes = best;
+    for (int i = 0; i < 3 && rc == MC_OK; i++) {
+        mc_tuning t = by_codes;
+        t.prefix_run = runs[i];
+        rc = time_one(t, &times[3 + i]);
+        if (rc == MC_OK && times[3 + i] < best_ms) {
+            best = t;
+            best_ms = times[3 + i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    ctx->tune = best;
+    *chosen = best;
+    if (times_ms) memcpy(times_ms, times, sizeof(times));
+    return MC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs, uint32_t ncols,
+                void *scratch, uint64_t scratch_bytes, hipStream_t stream, const mc_tuning &tune,
+                mc_graph **graph) {
     if (ncols == 0) return MC_OK;
     if (!ins || !outs) return fail(MC_E_ARG, "null descriptors");
     BatchPlan P;
-    int rc = plan_batch(ins, ncols, P);
+    int rc = plan_batch(ins, ncols, P, tune);
     if (rc) return rc;
     for (uint32_t i = 0; i < ncols; i++) {
         rc = check_out(&ins[i], &outs[i]);
@@ -1246,6 +1362,10 @@ int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_colu
     *graph = g;
     return MC_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int mc_graph_launch(mc_graph *graph, hipStream_t stream) {
     if (!graph || !graph->exec) return fail(MC_E_ARG, "null graph");

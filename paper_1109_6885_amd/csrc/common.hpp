@@ -16,7 +16,7 @@ constexpr int kWaves = kBlock / 64;
 // prefix passes, the flag "the prefix sort left the values out of order",
 // and the tile tickets of the two emits.
 constexpr int kPrefixSlots = 3;     // at most this many prefix passes
-constexpr double kPrefixRun = 32.0;  // wanted values per run of equal prefix
+constexpr double kPrefixRun = 32.0;  // default wanted values per run of equal prefix
 constexpr int kSfPrefix = 0, kSfUnsorted = kPrefixSlots, kSfEmitTicket = kPrefixSlots + 1,
               kSfEmitTicket2 = kPrefixSlots + 2, kSfSlots = 8;
 
@@ -243,6 +243,7 @@ struct ColDesc {
     uint64_t *emit_status2;    // prefix words of the emit after the full LSD sort (zeroed)
     uint64_t *merge_status;    // merge prefix words (zeroed)
     uint64_t *mbound;          // U_M entries before each merge tile's start, or null
+    uint32_t prefix_run;       // Step 1(a): wanted values per run of equal prefix (0: default)
     uint64_t *n_ud;            // |U_D| as written by Step 1(a) (zeroed)
     const uint64_t *n_ud_in;   // |U_D| as read by Step 1(b)
     uint64_t nd_max;           // capacity of u_d, drank, x_d

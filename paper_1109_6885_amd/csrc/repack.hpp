@@ -3,11 +3,12 @@
 // is unpacked at the old width w, translated through X_M and repacked at
 // the new width w'; the delta rows follow, translated through X_D.
 //
-// A workgroup owns 2048 consecutive output rows.  Because 64 codes of width
-// w fill exactly w 64-bit words, a tile of 2048 rows starts on an even word
-// boundary both in the input (32*w words) and in the output (32*w' words),
-// so tiles never share a word and need no atomics.  The tile's input words
-// are staged in LDS with 128-bit loads, each thread decodes 8 codes and
+// A workgroup owns CODES consecutive output rows (1024, 2048 or 4096; the
+// default 2048, or what the batched autotuner picked).  Because 64 codes of
+// width w fill exactly w 64-bit words, a tile of CODES rows starts on an even
+// word boundary both in the input (CODES/64*w words) and in the output, so
+// tiles never share a word and need no atomics.  The tile's input words are
+// staged in LDS with 128-bit loads, each thread decodes CODES/256 codes and
 // gathers their new codes from X_M (X_D for delta rows) into an LDS code
 // array, and then each thread assembles whole output words from the codes
 // that overlap them and writes them with coalesced 128-bit stores.
@@ -17,15 +18,17 @@
 
 namespace mc {
 
-constexpr int kRepackCodes = 2048;               // rows per tile (32 groups of 64)
-constexpr int kRepackPer = kRepackCodes / kBlock;  // codes per thread
+constexpr int kRepackCodes = 2048;  // default rows per tile (32 groups of 64)
+constexpr int kRepackPer = kRepackCodes / kBlock;  // codes per thread at the default
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
-struct RepackSmem {
-    uint64_t in[kRepackCodes / 64 * 32 + 2];
-    uint32_t code[kRepackCodes];
+template <int CODES>
+struct RepackSmemT {
+    uint64_t in[CODES / 64 * 32 + 2];
+    uint32_t code[CODES];
 };
+typedef RepackSmemT<kRepackCodes> RepackSmem;
 
 // ---------------------------------------------------------------------------
 // Compact X_M.  The gathers X_M[c] dominate Step 2(b), and their cost grows
@@ -71,12 +74,13 @@ __device__ inline void xcompact_tile(const ColDesc &C, uint64_t t) {
 
 // Stage the packed main words of the tile starting at row c0 into LDS with
 // 128-bit loads (streamed once: non-temporal, so the tables keep the cache).
+template <int CODES = kRepackCodes>
 __device__ inline void stage_main_words(const ColDesc &C, uint64_t c0, uint64_t *s_in) {
     if (c0 >= C.n_main) return;
     const uint32_t w = C.w;
     const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
     const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 32
-    const uint32_t nw = (uint32_t)min<uint64_t>(kRepackCodes / 64 * (uint64_t)w, win - wbase);
+    const uint32_t nw = (uint32_t)min<uint64_t>(CODES / 64 * (uint64_t)w, win - wbase);
     const uint32_t npair = nw / 2;
     const u64x2 *src2 = reinterpret_cast<const u64x2 *>(C.main_codes + wbase);
     u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
@@ -97,15 +101,17 @@ __device__ __forceinline__ uint32_t decode_code(const uint64_t *s_in, uint32_t i
 
 // Assemble the tile's output words from its new codes (s_code, zero past the
 // last row) and store them with 128-bit writes.
+template <int CODES = kRepackCodes>
 __device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint32_t *s_code,
                                        uint32_t wn, uint64_t n_out) {
     // local word k covers tile bits [64k, 64k + 64)
-    const uint64_t obase = t * (uint64_t)(kRepackCodes / 64) * wn;
+    const uint64_t obase = t * (uint64_t)(CODES / 64) * wn;
     const uint64_t wres = (n_out * wn + 63) / 64;
     const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
-    const uint32_t nwo = (kRepackCodes / 64) * wn;  // words of a full tile (even)
-    // floor(x / wn) for x < 2^17 as a multiply-high by ceil(2^32 / wn): the
-    // rounding error of the reciprocal times x stays below 2^32, so it is exact
+    const uint32_t nwo = (CODES / 64) * wn;  // words of a full tile (even)
+    // floor(x / wn) for x < CODES * 32 <= 2^17 as a multiply-high by
+    // ceil(2^32 / wn): the reciprocal's rounding error adds less than
+    // x / 2^32 <= 2^-15 < 1 / wn to the quotient, so the floor is exact
     const uint32_t rcp = (uint32_t)((0x100000000ull + wn - 1) / wn);
     for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
         uint64_t word[2];
@@ -114,7 +120,7 @@ __device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint3
             const uint32_t k = 2 * k2 + h;
             const uint32_t b0 = 64u * k;
             uint32_t q = __umulhi(b0, rcp);
-            const uint32_t qe = min<uint32_t>(__umulhi(b0 + 63, rcp), kRepackCodes - 1);
+            const uint32_t qe = min<uint32_t>(__umulhi(b0 + 63, rcp), CODES - 1);
             uint64_t acc = 0;
             for (; q <= qe; q++) {
                 const uint64_t c = s_code[q];
@@ -135,8 +141,10 @@ __device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint3
     }
 }
 
+template <int CODES = kRepackCodes>
 __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
-    RepackSmem &S = *reinterpret_cast<RepackSmem *>(smem);
+    constexpr int PER = CODES / kBlock;  // codes per thread
+    RepackSmemT<CODES> &S = *reinterpret_cast<RepackSmemT<CODES> *>(smem);
     uint64_t *s_in = S.in;
     uint32_t *s_code = S.code;
 
@@ -144,22 +152,22 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     const uint32_t wn = C.result->new_bitwidth;
     const uint64_t n_ud = C.result->delta_dict_len;
     const uint64_t n_out = C.n_main + C.nd;
-    const uint64_t c0 = t * kRepackCodes;
+    const uint64_t c0 = t * CODES;
     if (c0 >= n_out) return;
-    const uint32_t tn = (uint32_t)min<uint64_t>(kRepackCodes, n_out - c0);
+    const uint32_t tn = (uint32_t)min<uint64_t>(CODES, n_out - c0);
 
-    stage_main_words(C, c0, s_in);
+    stage_main_words<CODES>(C, c0, s_in);
     __syncthreads();
 
     // decode every code of this thread first, then issue all gathers together
     const uint64_t mask = (1ull << w) - 1ull;
     const bool compact = C.xdev != nullptr && *C.xflag == 0;
     const uint64_t A = compact ? xm_line_slope(C) : 0;
-    const uint32_t *tab[kRepackPer];
-    uint32_t idx[kRepackPer];
+    const uint32_t *tab[PER];
+    uint32_t idx[PER];
     uint32_t bad = 0;
 #pragma unroll
-    for (int j = 0; j < kRepackPer; j++) {
+    for (int j = 0; j < PER; j++) {
         const uint32_t i = j * kBlock + threadIdx.x;
         const uint64_t g = c0 + i;
         tab[j] = nullptr;
@@ -184,11 +192,11 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
             }
         }
     }
-    uint32_t nc[kRepackPer];
+    uint32_t nc[PER];
     if (compact) {
         // main rows: X_M[c] = c + a(c) + d(c); delta rows gather X_D
 #pragma unroll
-        for (int j = 0; j < kRepackPer; j++) {
+        for (int j = 0; j < PER; j++) {
             if (tab[j] == C.x_m)
                 nc[j] = idx[j] + (uint32_t)xm_line(idx[j], A) + (uint32_t)(int32_t)C.xdev[idx[j]];
             else
@@ -196,14 +204,14 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < kRepackPer; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+        for (int j = 0; j < PER; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kRepackPer; j++) s_code[j * kBlock + threadIdx.x] = nc[j];
+    for (int j = 0; j < PER; j++) s_code[j * kBlock + threadIdx.x] = nc[j];
     if (bad) flag_error(C.err, bad);
     __syncthreads();
 
-    pack_store_tile(C, t, s_code, wn, n_out);
+    pack_store_tile<CODES>(C, t, s_code, wn, n_out);
 }
 
 }  // namespace mc

@@ -159,15 +159,16 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
     if (threadIdx.x == 0) {
         // prefix digits: the most significant varying positions, as many as
         // it takes (at most kPrefixSlots) for n / (product of their numbers
-        // of distinct digits) <= kPrefixRun
+        // of distinct digits) <= the wanted run length
         int pos[kPrefixSlots];
         int k = 0;
         double combos = 1.0;
+        const double run = C.prefix_run ? (double)C.prefix_run : kPrefixRun;
         for (int p = P - 1; p >= 0 && k < kPrefixSlots; p--) {
             if (C.trivial[p]) continue;
             pos[k++] = p;
             combos *= (double)ndig[p];
-            if ((double)n <= combos * kPrefixRun) break;
+            if ((double)n <= combos * run) break;
         }
         for (int s = 0; s < kPrefixSlots; s++) {
             const int from_top = kPrefixSlots - 1 - s;  // the last slot takes the top digit

@@ -45,6 +45,7 @@ def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(_lib.McResult) == 32
     assert ctypes.sizeof(_lib.McColumnIn) == 56
     assert ctypes.sizeof(_lib.McColumnOut) == 56
+    assert ctypes.sizeof(_lib.McTuning) == 16
 
 
 def _in(type_=1, w=20, n_um=1_048_000, n_main=100_000_000, nd=1_000_000, ptr=256):
@@ -111,3 +112,10 @@ def test_batched_bounds(lib):
     assert sb.value >= per
     bad = (_lib.McColumnIn * 1)(_in(w=0))
     assert lib.mc_merge_batched_bounds(bad, 1, ctypes.byref(sb)) == -1
+
+
+def test_tuning_calls_reject_null_context(lib):
+    t = _lib.McTuning(2048, 32)
+    assert lib.mc_ctx_set_tuning(None, ctypes.byref(t)) == -1
+    assert lib.mc_ctx_get_tuning(None, ctypes.byref(t)) == -1
+    assert lib.mc_autotune_batched(None, None, None, 0, None, 0, None, ctypes.byref(t), None) == -1

@@ -97,6 +97,27 @@ def test_batched_prefix_sort_fallback():
         check_col(c, o.fetch())
 
 
+def test_autotune_batched():
+    """The autotuner picks one of its candidates, leaves the batch's result
+    in the outputs, and later batched merges with the chosen shapes agree
+    with the oracle."""
+    cols = small_batch(20, 0.002)
+    say(f"case autotune, {len(cols)} columns")
+    ctx = cm.Context(torch.cuda.current_device())
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    chosen, times, outs = cm.autotune_batched(dcols, ctx=ctx)
+    assert chosen["repack_codes"] in (1024, 2048, 4096)
+    assert chosen["prefix_run"] in (16, 32, 64)
+    assert len(times) == 6 and all(t > 0 for t in times)
+    assert ctx.get_tuning() == chosen
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    outs2, _ = cm.merge_columns_batched(dcols, ctx=ctx)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs2):
+        check_col(c, o.fetch())
+
+
 def test_batched_graph_replays():
     cols = small_batch(24, 0.001)
     say(f"case batched graph, {len(cols)} columns")

@@ -340,6 +340,31 @@ def test_prefix_sort_fallback_hash_route():
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+@pytest.mark.parametrize("codes,run", [(1024, 4), (4096, 1024), (1024, 64)])
+def test_launch_shapes_do_not_change_results(codes, run):
+    """Every re-encode tile size and prefix-run target gives the same bytes."""
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(repack_codes=codes, prefix_run=run)
+    assert ctx.get_tuning() == {"repack_codes": codes, "prefix_run": run}
+    rng = np.random.default_rng(codes + run)
+    for vtype, shape in (("u32", (3000, 9_001, 4_097, 0.5)), ("u64", (70_000, 123_457, 50_001, 0.9)),
+                         ("str16", (20_000, 40_000, 30_011, 0.3))):
+        col = gen.random_column(rng, vtype, *shape)
+        say(f"case tuning codes={codes} run={run} {vtype} {shape}")
+        out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=True, ctx=ctx)
+        torch.cuda.synchronize()
+        assert_same(out.fetch(), ora_merge(col))
+
+
+def test_set_tuning_rejects_bad_shapes():
+    ctx = cm.Context(torch.cuda.current_device())
+    for kw in ({"repack_codes": 3000}, {"repack_codes": 512}, {"prefix_run": 3},
+               {"prefix_run": 2048}):
+        with pytest.raises(cm.ColmergeError):
+            ctx.set_tuning(**kw)
+    assert ctx.get_tuning() == {"repack_codes": 2048, "prefix_run": 32}
+
+
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
 def test_naive_step2_matches_oracle(vtype):
     """The unoptimized Step 2(b) (binary search in U', Section 5.2) gives
