@@ -78,6 +78,11 @@ typedef enum mc_status {
 #define MC_DEVERR_CODE_RANGE 1u  /* a main code >= |U_M| was read            */
 #define MC_DEVERR_DELTA_RANGE 2u /* a delta index >= |U_D| (internal)        */
 #define MC_DEVERR_SPIN 4u        /* a cross-workgroup wait hit its bound     */
+#define MC_DEVERR_ORDER 8u       /* a dictionary is not strictly increasing  */
+/* The device does not check the order of U_M (a full check would cost a
+ * pass over it); a U_M out of order gives an undefined result, and where a
+ * merge tile meets the inconsistency it stays empty and sets
+ * MC_DEVERR_ORDER instead of reading past its inputs. */
 
 /* Result scalars, written by the device (caller-allocated device memory). */
 typedef struct mc_result {

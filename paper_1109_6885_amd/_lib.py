@@ -22,6 +22,7 @@ STATUS = {0: "MC_OK", -1: "MC_E_ARG", -2: "MC_E_CAP", -3: "MC_E_NOMEM", -4: "MC_
 MC_DEVERR_CODE_RANGE = 1
 MC_DEVERR_DELTA_RANGE = 2
 MC_DEVERR_SPIN = 4
+MC_DEVERR_ORDER = 8
 
 EXPORTS = [
     "mc_ctx_create", "mc_ctx_destroy", "mc_last_error", "mc_merge_bounds", "mc_merge_column",

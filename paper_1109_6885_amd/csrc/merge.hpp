@@ -163,8 +163,14 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
         i0 = S.i0;
         i1 = S.i1;
     }
-    const uint64_t j0 = k0 - i0, j1 = k1 - i1;
-    const uint32_t na = (uint32_t)(i1 - i0), nb = (uint32_t)(j1 - j0);
+    // With both inputs strictly increasing the co-ranks grow with k and the
+    // tile holds i1 - i0 U_M and j1 - j0 U_D entries.  Out-of-order inputs
+    // can break that; then the tile is left empty (nothing is read or
+    // written past the inputs) and the error word says why.
+    const bool order_ok = i1 >= i0 && i1 - i0 <= k1 - k0;
+    if (!order_ok && threadIdx.x == 0) flag_error(C.err, MC_DEVERR_ORDER);
+    const uint64_t j0 = k0 - i0, j1 = order_ok ? k1 - i1 : j0;
+    const uint32_t na = order_ok ? (uint32_t)(i1 - i0) : 0u, nb = (uint32_t)(j1 - j0);
     for (uint32_t x = threadIdx.x; x <= na; x += kBlock) {
         if (x == 0) {
             if (i0 > 0) S.a[0] = gA(i0 - 1);
@@ -176,7 +182,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     __syncthreads();
 
     // this thread's slice of the tile's merged range
-    const uint32_t len = (uint32_t)(k1 - k0);
+    const uint32_t len = na + nb;
     const uint32_t d0 = min<uint32_t>(threadIdx.x * ITEMS, len);
     const uint32_t d1 = min<uint32_t>(d0 + ITEMS, len);
     auto lA = [&](uint64_t i) { return S.a[i + 1]; };
