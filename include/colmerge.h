@@ -136,6 +136,11 @@ const char *mc_last_error(void);
  * graph capture (outputs sized before the real |U'| is known). */
 int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap,
                     uint64_t *codes_words, uint64_t *scratch_bytes);
+/* The same for merges on `ctx` (its tuning can route a delta to the
+ * hashing route of Step 1(a), which needs more scratch; NULL: defaults). */
+int mc_merge_bounds_ctx(const mc_ctx *ctx, const mc_column_in *in,
+                        uint64_t *dict_cap, uint64_t *codes_words,
+                        uint64_t *scratch_bytes);
 
 /* ---- the merge of one column (Section 5, Steps 1(a) to 2(b)) --------- */
 
@@ -162,7 +167,8 @@ int mc_merge_column_naive(mc_ctx *ctx, const mc_column_in *in,
 /* Step 1(a), modified form (Sections 5.1 and 5.3): sorted unique delta
  * dictionary u_d (delta_rows capacity, same value type) and each delta
  * row's index in it (drank, delta_rows entries).  *d_count (device u64)
- * receives |U_D|.  Scratch: mc_delta_dictionary_scratch bytes. */
+ * receives |U_D|.  Scratch: mc_delta_dictionary_scratch bytes (enough
+ * for either route of Step 1(a), whatever the context's tuning). */
 int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values,
                         uint64_t delta_rows, void *u_d, uint32_t *drank,
                         uint64_t *d_count, void *scratch,
@@ -226,12 +232,15 @@ void mc_graph_destroy(mc_graph *graph);
  *   prefix_run:   values per run of equal prefix that Step 1(a) aims for
  *                 when it picks how many leading digits to sort globally
  *                 (4 .. 1024, default 32; more runs -> more radix passes,
- *                 longer runs -> more work in the LDS windows).
+ *                 longer runs -> more work in the LDS windows);
+ *   hash_min_rows: deltas of at least this many rows deduplicate by hashing
+ *                 before sorting (0: the default, 2^21; 1: always).
  * The results do not depend on them. */
 typedef struct mc_tuning {
     uint32_t repack_codes;
     uint32_t prefix_run;
-    uint32_t reserved[2]; /* zero */
+    uint32_t hash_min_rows;
+    uint32_t reserved; /* zero */
 } mc_tuning;
 
 /* MC_E_ARG if a value is outside the ranges above (the context keeps its

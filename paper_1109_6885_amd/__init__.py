@@ -50,15 +50,16 @@ class Context:
         check(load().mc_ctx_step_times(self.handle, arr), "mc_ctx_step_times")
         return list(arr)
 
-    def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32):
+    def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32, hash_min_rows: int = 0):
         """mc_ctx_set_tuning: launch shapes for every later merge on this context."""
-        t = McTuning(repack_codes, prefix_run)
+        t = McTuning(repack_codes, prefix_run, hash_min_rows)
         check(load().mc_ctx_set_tuning(self.handle, ctypes.byref(t)), "mc_ctx_set_tuning")
 
     def get_tuning(self) -> dict:
         t = McTuning()
         check(load().mc_ctx_get_tuning(self.handle, ctypes.byref(t)), "mc_ctx_get_tuning")
-        return {"repack_codes": t.repack_codes, "prefix_run": t.prefix_run}
+        return {"repack_codes": t.repack_codes, "prefix_run": t.prefix_run,
+                "hash_min_rows": t.hash_min_rows}
 
     def __del__(self):
         try:
@@ -227,12 +228,14 @@ def batched_bounds_of(descs) -> int:
     return int(sb.value)
 
 
-def merge_bounds(col: ColumnInput):
-    """(dict_cap, codes_words, scratch_bytes) for one column (host only)."""
+def merge_bounds(col: ColumnInput, ctx: Context | None = None):
+    """(dict_cap, codes_words, scratch_bytes) for one column (host only);
+    with ctx, for merges on that context (mc_merge_bounds_ctx)."""
     d = col.descriptor()
     a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-    check(load().mc_merge_bounds(ctypes.byref(d), ctypes.byref(a), ctypes.byref(b),
-                                 ctypes.byref(c)), "mc_merge_bounds")
+    check(load().mc_merge_bounds_ctx(ctx.handle if ctx is not None else None, ctypes.byref(d),
+                                     ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+          "mc_merge_bounds_ctx")
     return int(a.value), int(b.value), int(c.value)
 
 
@@ -262,7 +265,7 @@ def merge_column(col: ColumnInput, out: MergeOutput | None = None,
     if out is None:
         out = alloc_output(col, tables)
     if scratch is None:
-        scratch = alloc_scratch(merge_bounds(col)[2])
+        scratch = alloc_scratch(merge_bounds(col, ctx)[2])
     din, dout = col.descriptor(), out.descriptor()
     check(load().mc_merge_column(ctx.handle, ctypes.byref(din), ctypes.byref(dout),
                                  _ptr(scratch), scratch.numel(), _stream(stream)),
@@ -278,7 +281,7 @@ def merge_column_naive(col: ColumnInput, out: MergeOutput | None = None,
     if out is None:
         out = alloc_output(col, tables)
     if scratch is None:
-        scratch = alloc_scratch(merge_bounds(col)[2])
+        scratch = alloc_scratch(merge_bounds(col, ctx)[2])
     din, dout = col.descriptor(), out.descriptor()
     check(load().mc_merge_column_naive(ctx.handle, ctypes.byref(din), ctypes.byref(dout),
                                        _ptr(scratch), scratch.numel(), _stream(stream)),
@@ -406,7 +409,8 @@ def autotune_batched(cols, outs=None, scratch=None, stream=None, ctx=None):
     check(load().mc_autotune_batched(ctx.handle, ins, os_, len(cols), _ptr(scratch),
                                      scratch.numel(), _stream(stream), ctypes.byref(t), times),
           "mc_autotune_batched")
-    return {"repack_codes": t.repack_codes, "prefix_run": t.prefix_run}, list(times), outs
+    return ({"repack_codes": t.repack_codes, "prefix_run": t.prefix_run,
+             "hash_min_rows": t.hash_min_rows}, list(times), outs)
 
 
 def merge_columns_batched(cols, outs=None, scratch=None, graph: bool = False, stream=None,

@@ -30,7 +30,7 @@ EXPORTS = [
     "mc_merge_dictionaries_scratch", "mc_reencode", "mc_merge_batched_bounds",
     "mc_merge_columns_batched", "mc_graph_launch", "mc_graph_destroy", "mc_ctx_set_timing",
     "mc_ctx_step_times", "mc_copy_bytes", "mc_gather_ref", "mc_merge_column_naive",
-    "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched",
+    "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched", "mc_merge_bounds_ctx",
 ]
 
 
@@ -56,7 +56,7 @@ class McColumnOut(ctypes.Structure):
 
 class McTuning(ctypes.Structure):
     _fields_ = [("repack_codes", ctypes.c_uint32), ("prefix_run", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("hash_min_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ColmergeError(RuntimeError):
@@ -85,6 +85,7 @@ def load():
         "mc_ctx_destroy": (None, [p]),
         "mc_last_error": (ctypes.c_char_p, []),
         "mc_merge_bounds": (ctypes.c_int, [pin, pu64, pu64, pu64]),
+        "mc_merge_bounds_ctx": (ctypes.c_int, [p, pin, pu64, pu64, pu64]),
         "mc_merge_column": (ctypes.c_int, [p, pin, pout, p, u64, p]),
         "mc_merge_column_naive": (ctypes.c_int, [p, pin, pout, p, u64, p]),
         "mc_delta_dictionary": (ctypes.c_int, [p, i32, p, u64, p, p, p, p, u64, p]),

@@ -32,7 +32,7 @@ struct mc_ctx {
     uint64_t meta_cap = 0;
     hipEvent_t meta_event = nullptr;
     // launch shapes (mc_ctx_set_tuning / mc_autotune_batched)
-    mc_tuning tune = {2048u, 32u, {0u, 0u}};
+    mc_tuning tune = {2048u, 32u, 0u, 0u};
 };
 
 struct mc_graph {
@@ -147,7 +147,7 @@ constexpr uint64_t kMergePartMinTiles = 512;
 // Workgroups of merge_partition: one wave per tile boundary (tiles + 1).
 uint64_t merge_part_blocks(uint64_t merge_tiles) { return ceil_div(merge_tiles + 1, mc::kWaves); }
 
-const mc_tuning kDefaultTuning = {2048u, 32u, {0u, 0u}};
+const mc_tuning kDefaultTuning = {2048u, 32u, 0u, 0u};
 
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
                      bool allow_hash = true, const mc_tuning &tune = kDefaultTuning) {
@@ -155,7 +155,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.repack_codes = tune.repack_codes;
     L.prefix_run = tune.prefix_run;
     const uint32_t E = value_len(type);
-    L.hashed = allow_hash && nd >= kHashMinRows;
+    L.hashed = allow_hash && nd >= (tune.hash_min_rows ? tune.hash_min_rows : kHashMinRows);
     if (L.hashed) {
         uint64_t h = 1024;
         while (h < 2 * nd) h <<= 1;
@@ -961,8 +961,8 @@ void mc_ctx_destroy(mc_ctx *ctx) {
     delete ctx;
 }
 
-int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap, uint64_t *codes_words,
-                    uint64_t *scratch_bytes) {
+int mc_merge_bounds_ctx(const mc_ctx *ctx, const mc_column_in *in, uint64_t *dict_cap,
+                        uint64_t *codes_words, uint64_t *scratch_bytes) {
     int rc = check_in(in);
     if (rc) return rc;
     const uint64_t dc = in->main_dict_len + in->delta_rows;
@@ -970,9 +970,15 @@ int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap, uint64_t *codes_
     if (dict_cap) *dict_cap = dc;
     if (codes_words) *codes_words = codes_words_bound(rows, dc);
     if (scratch_bytes)
-        *scratch_bytes = single_scratch(
-            col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows));
+        *scratch_bytes = single_scratch(col_layout(in->type, in->main_dict_len, in->delta_rows,
+                                                   in->main_rows, true,
+                                                   ctx ? ctx->tune : kDefaultTuning));
     return MC_OK;
+}
+
+int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap, uint64_t *codes_words,
+                    uint64_t *scratch_bytes) {
+    return mc_merge_bounds_ctx(nullptr, in, dict_cap, codes_words, scratch_bytes);
 }
 
 int mc_merge_column(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out, void *scratch,
@@ -988,7 +994,12 @@ int mc_merge_column_naive(mc_ctx *ctx, const mc_column_in *in, const mc_column_o
 int mc_delta_dictionary_scratch(int32_t type, uint64_t delta_rows, uint64_t *scratch_bytes) {
     if (value_len(type) == 0) return fail(MC_E_ARG, "unknown value type");
     if (delta_rows >= (1ull << 30)) return fail(MC_E_ARG, "delta_rows must be < 2^30");
-    if (scratch_bytes) *scratch_bytes = single_scratch(col_layout(type, 0, delta_rows, 0));
+    // enough for either route of Step 1(a), whatever a context's tuning picks
+    mc_tuning always_hash = kDefaultTuning;
+    always_hash.hash_min_rows = 1;
+    const uint64_t a = single_scratch(col_layout(type, 0, delta_rows, 0, false));
+    const uint64_t b = single_scratch(col_layout(type, 0, delta_rows, 0, true, always_hash));
+    if (scratch_bytes) *scratch_bytes = std::max(a, b);
     return MC_OK;
 }
 
@@ -1212,7 +1223,7 @@ int mc_ctx_set_tuning(mc_ctx *ctx, const mc_tuning *t) {
         return fail(MC_E_ARG, "repack_codes must be 1024, 2048 or 4096");
     if (t->prefix_run < 4 || t->prefix_run > 1024)
         return fail(MC_E_ARG, "prefix_run must be in [4, 1024]");
-    if (t->reserved[0] || t->reserved[1]) return fail(MC_E_ARG, "reserved fields must be zero");
+    if (t->reserved) return fail(MC_E_ARG, "the reserved field must be zero");
     ctx->tune = *t;
     return MC_OK;
 }

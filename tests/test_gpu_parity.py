@@ -345,12 +345,32 @@ def test_launch_shapes_do_not_change_results(codes, run):
     """Every re-encode tile size and prefix-run target gives the same bytes."""
     ctx = cm.Context(torch.cuda.current_device())
     ctx.set_tuning(repack_codes=codes, prefix_run=run)
-    assert ctx.get_tuning() == {"repack_codes": codes, "prefix_run": run}
+    assert ctx.get_tuning() == {"repack_codes": codes, "prefix_run": run, "hash_min_rows": 0}
     rng = np.random.default_rng(codes + run)
     for vtype, shape in (("u32", (3000, 9_001, 4_097, 0.5)), ("u64", (70_000, 123_457, 50_001, 0.9)),
                          ("str16", (20_000, 40_000, 30_011, 0.3))):
         col = gen.random_column(rng, vtype, *shape)
         say(f"case tuning codes={codes} run={run} {vtype} {shape}")
+        out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=True, ctx=ctx)
+        torch.cuda.synchronize()
+        assert_same(out.fetch(), ora_merge(col))
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+def test_hash_route_on_every_shape(vtype):
+    """Step 1(a)'s hashing route, forced for every delta size, on the random
+    shapes (ragged tails, single rows, empty deltas) and the clustered deltas
+    that need the full sort after the prefix sort."""
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(hash_min_rows=1)
+    rng = np.random.default_rng({"u32": 51, "u64": 52, "str16": 53}[vtype])
+    cols = [gen.random_column(rng, vtype, *shape) for shape in SHAPES]
+    for case in ("one_prefix", "one_misplaced"):
+        base = gen.random_column(rng, vtype, 3000, 20_000, 0)
+        cols.append(gen.Column(vtype, base.u_m, base.main_packed, base.n_main, base.w,
+                               _clustered_delta(rng, vtype, case)))
+    for col in cols:
+        say(f"case hash route forced {vtype} n_um={col.u_m.shape[0]} nd={col.n_delta}")
         out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=True, ctx=ctx)
         torch.cuda.synchronize()
         assert_same(out.fetch(), ora_merge(col))
@@ -362,7 +382,7 @@ def test_set_tuning_rejects_bad_shapes():
                {"prefix_run": 2048}):
         with pytest.raises(cm.ColmergeError):
             ctx.set_tuning(**kw)
-    assert ctx.get_tuning() == {"repack_codes": 2048, "prefix_run": 32}
+    assert ctx.get_tuning() == {"repack_codes": 2048, "prefix_run": 32, "hash_min_rows": 0}
 
 
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
