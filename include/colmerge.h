@@ -203,6 +203,50 @@ int mc_reencode(mc_ctx *ctx, const uint64_t *main_codes, uint64_t n_main,
                 mc_result *result, uint64_t *out, uint64_t out_cap_words,
                 struct ihipStream_t *stream);
 
+/* ---- delta index: Step 1(a)'s hashing done as rows are appended ------- */
+
+/* The paper keeps a CSB+ tree beside each delta partition so that Step 1(a)
+ * is a walk over its leaves and the insert cost is paid per update (Section
+ * 4, Section 6.1; other delta structures are its stated future work).  A
+ * delta index does the same job with the hashing route of Step 1(a): each
+ * appended batch of rows is hashed into an open-addressing table of
+ * representative rows, and the batch's new distinct values are added to a
+ * distinct list, so that a merge (mc_merge_column_indexed) starts from the
+ * distinct values and skips the hashing; T_U of Eq. 1 then carries it.
+ *
+ * workspace:  device memory of mc_delta_index_bytes (16-byte aligned),
+ *             owned by the caller; reset it before the first append and
+ *             after each merge that consumed the delta;
+ * capacity:   delta rows it can index (< 2^30);
+ * type:       mc_type of the delta values. */
+typedef struct mc_delta_index {
+    void *workspace;
+    uint64_t workspace_bytes;
+    uint64_t capacity;
+    int32_t type;
+    uint32_t reserved; /* zero */
+} mc_delta_index;
+
+int mc_delta_index_bytes(int32_t type, uint64_t capacity, uint64_t *bytes);
+/* Empty the index (stream-ordered). */
+int mc_delta_index_reset(mc_ctx *ctx, const mc_delta_index *index,
+                         struct ihipStream_t *stream);
+/* Index rows [row0, row0 + rows) of the delta (device values, all rows
+ * before row0 already indexed, each row exactly once, in order;
+ * row0 + rows <= capacity).  Stream-ordered. */
+int mc_delta_index_append(mc_ctx *ctx, const mc_delta_index *index,
+                          const void *delta_values, uint64_t row0, uint64_t rows,
+                          struct ihipStream_t *stream);
+/* The merge of mc_merge_column with Step 1(a) starting from the index:
+ * in->delta_values / delta_rows are the indexed rows [0, delta_rows), in
+ * the same buffer that was indexed.  Same outputs and error word (plus the
+ * index's own error bits).  Scratch: mc_merge_indexed_bounds bytes. */
+int mc_merge_indexed_bounds(const mc_column_in *in, uint64_t *scratch_bytes);
+int mc_merge_column_indexed(mc_ctx *ctx, const mc_column_in *in,
+                            const mc_delta_index *index,
+                            const mc_column_out *out, void *scratch,
+                            uint64_t scratch_bytes, struct ihipStream_t *stream);
+
 /* ---- many columns at once (Section 6.2.1, scheme (i)) ----------------- */
 
 /* Worst-case scratch for merging ncols columns in one batched call. */

@@ -19,8 +19,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (ColmergeError, McColumnIn, McColumnOut, McResult, McTuning, TYPE_CODES,
-                   VALUE_LEN, check, load)
+from ._lib import (ColmergeError, McColumnIn, McColumnOut, McDeltaIndex, McResult, McTuning,
+                   TYPE_CODES, VALUE_LEN, check, load)
 
 __all__ = [
     "Context", "context", "to_device", "value_tensor_empty", "merge_bounds", "merge_column",
@@ -286,6 +286,65 @@ def merge_column_naive(col: ColumnInput, out: MergeOutput | None = None,
     check(load().mc_merge_column_naive(ctx.handle, ctypes.byref(din), ctypes.byref(dout),
                                        _ptr(scratch), scratch.numel(), _stream(stream)),
           "mc_merge_column_naive")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Delta index (Step 1(a)'s hashing done as rows are appended)
+# ---------------------------------------------------------------------------
+
+class DeltaIndex:
+    """An mc_delta_index for a delta buffer of up to `capacity` rows.  The
+    caller appends rows to its delta buffer and then calls append(delta, n)
+    for them; merge_column_indexed merges the indexed rows."""
+
+    def __init__(self, vtype: str, capacity: int, stream=None, ctx: Context | None = None):
+        self.ctx = ctx or context()
+        nb = ctypes.c_uint64()
+        check(load().mc_delta_index_bytes(TYPE_CODES[vtype], capacity, ctypes.byref(nb)),
+              "mc_delta_index_bytes")
+        self.workspace = alloc_scratch(nb.value)
+        self.desc = McDeltaIndex(_ptr(self.workspace), nb.value, capacity, TYPE_CODES[vtype], 0)
+        self.vtype = vtype
+        self.capacity = capacity
+        self.rows = 0
+        self.reset(stream)
+
+    def reset(self, stream=None):
+        check(load().mc_delta_index_reset(self.ctx.handle, ctypes.byref(self.desc),
+                                          _stream(stream)), "mc_delta_index_reset")
+        self.rows = 0
+
+    def append(self, delta: torch.Tensor, rows: int, stream=None):
+        """Index the next `rows` rows of `delta` (rows [self.rows, self.rows + rows))."""
+        check(load().mc_delta_index_append(self.ctx.handle, ctypes.byref(self.desc), _ptr(delta),
+                                           self.rows, rows, _stream(stream)),
+              "mc_delta_index_append")
+        self.rows += rows
+
+
+def merge_indexed_bounds(col: ColumnInput) -> int:
+    d = col.descriptor()
+    sb = ctypes.c_uint64()
+    check(load().mc_merge_indexed_bounds(ctypes.byref(d), ctypes.byref(sb)),
+          "mc_merge_indexed_bounds")
+    return int(sb.value)
+
+
+def merge_column_indexed(col: ColumnInput, index: DeltaIndex, out: MergeOutput | None = None,
+                         scratch: torch.Tensor | None = None, tables: bool = False,
+                         stream=None, ctx: Context | None = None) -> MergeOutput:
+    """mc_merge_column_indexed: the merge with Step 1(a) starting from the index
+    (col.delta holds the indexed rows)."""
+    ctx = ctx or context()
+    if out is None:
+        out = alloc_output(col, tables)
+    if scratch is None:
+        scratch = alloc_scratch(merge_indexed_bounds(col))
+    din, dout = col.descriptor(), out.descriptor()
+    check(load().mc_merge_column_indexed(ctx.handle, ctypes.byref(din), ctypes.byref(index.desc),
+                                         ctypes.byref(dout), _ptr(scratch), scratch.numel(),
+                                         _stream(stream)), "mc_merge_column_indexed")
     return out
 
 

@@ -31,6 +31,8 @@ EXPORTS = [
     "mc_merge_columns_batched", "mc_graph_launch", "mc_graph_destroy", "mc_ctx_set_timing",
     "mc_ctx_step_times", "mc_copy_bytes", "mc_gather_ref", "mc_merge_column_naive",
     "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched", "mc_merge_bounds_ctx",
+    "mc_delta_index_bytes", "mc_delta_index_reset", "mc_delta_index_append",
+    "mc_merge_indexed_bounds", "mc_merge_column_indexed",
 ]
 
 
@@ -57,6 +59,12 @@ class McColumnOut(ctypes.Structure):
 class McTuning(ctypes.Structure):
     _fields_ = [("repack_codes", ctypes.c_uint32), ("prefix_run", ctypes.c_uint32),
                 ("hash_min_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class McDeltaIndex(ctypes.Structure):
+    _fields_ = [("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("capacity", ctypes.c_uint64), ("type", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class ColmergeError(RuntimeError):
@@ -86,6 +94,12 @@ def load():
         "mc_last_error": (ctypes.c_char_p, []),
         "mc_merge_bounds": (ctypes.c_int, [pin, pu64, pu64, pu64]),
         "mc_merge_bounds_ctx": (ctypes.c_int, [p, pin, pu64, pu64, pu64]),
+        "mc_delta_index_bytes": (ctypes.c_int, [i32, u64, pu64]),
+        "mc_delta_index_reset": (ctypes.c_int, [p, ctypes.POINTER(McDeltaIndex), p]),
+        "mc_delta_index_append": (ctypes.c_int, [p, ctypes.POINTER(McDeltaIndex), p, u64, u64, p]),
+        "mc_merge_indexed_bounds": (ctypes.c_int, [pin, pu64]),
+        "mc_merge_column_indexed": (ctypes.c_int, [p, pin, ctypes.POINTER(McDeltaIndex), pout, p,
+                                                   u64, p]),
         "mc_merge_column": (ctypes.c_int, [p, pin, pout, p, u64, p]),
         "mc_merge_column_naive": (ctypes.c_int, [p, pin, pout, p, u64, p]),
         "mc_delta_dictionary": (ctypes.c_int, [p, i32, p, u64, p, p, p, p, u64, p]),

@@ -129,6 +129,7 @@ struct ColLayout {
     uint32_t repack_codes = mc::kRepackCodes, prefix_run = 0;  // launch shapes
     bool partitioned = false;  // merge tile boundaries come from merge_partition
     bool hashed = false;       // Step 1(a) deduplicates by hashing first
+    bool indexed = false;      // ... with the hashing done by a delta index (mc_delta_index)
     uint64_t hmask = 0;
     uint32_t hash_tiles = 0;
 };
@@ -150,17 +151,20 @@ uint64_t merge_part_blocks(uint64_t merge_tiles) { return ceil_div(merge_tiles +
 const mc_tuning kDefaultTuning = {2048u, 32u, 0u, 0u};
 
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
-                     bool allow_hash = true, const mc_tuning &tune = kDefaultTuning) {
+                     bool allow_hash = true, const mc_tuning &tune = kDefaultTuning,
+                     bool indexed = false) {
     ColLayout L;
     L.repack_codes = tune.repack_codes;
     L.prefix_run = tune.prefix_run;
     const uint32_t E = value_len(type);
-    L.hashed = allow_hash && nd >= (tune.hash_min_rows ? tune.hash_min_rows : kHashMinRows);
-    if (L.hashed) {
+    L.indexed = indexed;
+    L.hashed = indexed ||
+               (allow_hash && nd >= (tune.hash_min_rows ? tune.hash_min_rows : kHashMinRows));
+    if (L.hashed) L.hash_tiles = (uint32_t)ceil_div(nd, mc::kHashTile);  // also rank_rows' grid
+    if (L.hashed && !L.indexed) {
         uint64_t h = 1024;
         while (h < 2 * nd) h <<= 1;
         L.hmask = h - 1;
-        L.hash_tiles = (uint32_t)ceil_div(nd, mc::kHashTile);
     }
     L.passes = E;  // one 8-bit digit per value byte
     L.sort_tiles = (uint32_t)ceil_div(nd, sort_tile_of(type));
@@ -182,7 +186,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.merge_status = z.take(L.merge_tiles * 8);
     L.partitioned = L.merge_tiles >= kMergePartMinTiles;
     if (L.partitioned) L.mbound = z.take((L.merge_tiles + 1) * 8);
-    if (L.hashed) {
+    if (L.hashed && !L.indexed) {
         L.dcount = z.take(8);
         L.hstatus = z.take(ceil_div(nd, mc::kCompactTile) * 8);
         L.htab = z.take((L.hmask + 1) * 4);
@@ -200,12 +204,12 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.x_d = b.take(nd * 4);
     L.x_m = b.take(n_um * 4);
     L.xdev = b.take(n_um * 2);
-    if (L.hashed) {
+    if (L.hashed && !L.indexed) {
         L.rep = b.take(nd * 4);
         L.dindex = b.take(nd * 4);
         L.dkeys = b.take(nd * E);
-        L.drankd = b.take(nd * 4);
     }
+    if (L.hashed) L.drankd = b.take(nd * 4);
     L.b_size = b.size();
     return L;
 }
@@ -223,12 +227,13 @@ void set_hash_fields(mc::ColDesc &C, char *za, char *zb, const ColLayout &L) {
     C.sort_src = C.delta;
     C.sort_n = nullptr;
     if (!L.hashed) return;
+    C.drankd = reinterpret_cast<uint32_t *>(zb + L.drankd);
+    if (L.indexed) return;  // the index's own buffers are set by the caller
     C.htab = reinterpret_cast<uint32_t *>(za + L.htab);
     C.hmask = L.hmask;
     C.rep = reinterpret_cast<uint32_t *>(zb + L.rep);
     C.dindex = reinterpret_cast<uint32_t *>(zb + L.dindex);
     C.dkeys = zb + L.dkeys;
-    C.drankd = reinterpret_cast<uint32_t *>(zb + L.drankd);
     C.dcount = reinterpret_cast<uint64_t *>(za + L.dcount);
     C.hstatus = reinterpret_cast<uint64_t *>(za + L.hstatus);
     C.sort_src = C.dkeys;
@@ -285,6 +290,54 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
 }
 
 // ---------------------------------------------------------------------------
+// Delta index (mc_delta_index): the hashing route's table, representatives
+// and distinct list, kept up to date by appends instead of built in a merge.
+// Layout of its workspace:
+//   [0, 64)    u32 counters ([2]: compaction tile ticket of the batch)
+//   64: u64 distinct values listed; 72: u64 the same before this batch;
+//   80: u32 error word
+//   then the table (power of two >= 2 * capacity slots, >= 1024), the
+//   representative and distinct position of every row, the distinct values
+//   and the compaction's prefix words (one per tile of a batch).
+// ---------------------------------------------------------------------------
+
+struct IndexLayout {
+    uint64_t scal = 0, htab = 0, rep = 0, dindex = 0, dkeys = 0, hstatus = 0, size = 0;
+    uint64_t hmask = 0;
+};
+
+IndexLayout index_layout(int32_t type, uint64_t cap) {
+    IndexLayout X;
+    uint64_t h = 1024;
+    while (h < 2 * cap) h <<= 1;
+    X.hmask = h - 1;
+    Carver c;
+    X.scal = c.take(128);
+    X.htab = c.take(h * 4);
+    X.rep = c.take(cap * 4);
+    X.dindex = c.take(cap * 4);
+    X.dkeys = c.take(cap * value_len(type));
+    X.hstatus = c.take(ceil_div(cap, mc::kCompactTile) * 8);
+    X.size = c.size();
+    return X;
+}
+
+// The index's part of a column descriptor.
+void set_index_fields(mc::ColDesc &C, const mc_delta_index *ix) {
+    const IndexLayout X = index_layout(ix->type, ix->capacity);
+    char *w = static_cast<char *>(ix->workspace);
+    C.htab = reinterpret_cast<uint32_t *>(w + X.htab);
+    C.hmask = X.hmask;
+    C.rep = reinterpret_cast<uint32_t *>(w + X.rep);
+    C.dindex = reinterpret_cast<uint32_t *>(w + X.dindex);
+    C.dkeys = w + X.dkeys;
+    C.dcount = reinterpret_cast<uint64_t *>(w + X.scal + 64);
+    C.hstatus = reinterpret_cast<uint64_t *>(w + X.hstatus);
+    C.sort_src = C.dkeys;
+    C.sort_n = C.dcount;
+}
+
+// ---------------------------------------------------------------------------
 // Kernels.  k1_* serve one column (descriptor by value, grid = its tiles);
 // kn_* serve a batch: every workgroup finds its column in a per-phase prefix
 // of tile counts and runs the same tile function, dispatched on the value
@@ -314,6 +367,24 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, ui
 
 // Plain 128-bit copy: the achievable streaming bandwidth on this GPU, and
 // the kernel of known traffic that calibrates hardware byte counters.
+// Before an index batch: clear the batch's compaction prefix words and tile
+// ticket, and remember how many distinct values are listed already.
+__global__ __launch_bounds__(256) void k_index_prepare(uint64_t *hstatus, uint64_t ntiles,
+                                                       uint32_t *counters, const uint64_t *dcount,
+                                                       uint64_t *dbase) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntiles;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        hstatus[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counters[2] = 0;
+        *dbase = *dcount;
+    }
+}
+// err |= *src (an index's error word into a merge's result)
+__global__ void k_or_word(uint32_t *err, const uint32_t *src) {
+    if (threadIdx.x == 0 && *src) atomicOr(err, *src);
+}
+
 __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
                                                 uint4 *__restrict__ dst, uint64_t n16) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -583,7 +654,7 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
         if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
         return MC_OK;
     }
-    if (L.hashed) {
+    if (L.hashed && !L.indexed) {
         hipLaunchKernelGGL(k1_hash_insert<T>, dim3(L.hash_tiles), dim3(mc::kBlock), 0, s, C);
         MC_LAUNCHED("k1_hash_insert");
         hipLaunchKernelGGL(k1_compact<T>, dim3((uint32_t)ceil_div(C.nd, mc::kCompactTile)),
@@ -684,6 +755,17 @@ int check_in(const mc_column_in *in) {
     return MC_OK;
 }
 
+int check_index(const mc_delta_index *ix) {
+    if (!ix) return fail(MC_E_ARG, "null index");
+    if (value_len(ix->type) == 0) return fail(MC_E_ARG, "unknown index value type");
+    if (ix->capacity >= (1ull << 30)) return fail(MC_E_ARG, "index capacity must be < 2^30");
+    if (ix->reserved) return fail(MC_E_ARG, "the index's reserved field must be zero");
+    if (!ix->workspace || !aligned16(ix->workspace)) return fail(MC_E_ARG, "bad index workspace");
+    if (ix->workspace_bytes < index_layout(ix->type, ix->capacity).size)
+        return fail(MC_E_CAP, "index workspace below mc_delta_index_bytes");
+    return MC_OK;
+}
+
 int check_out(const mc_column_in *in, const mc_column_out *out) {
     if (!out) return fail(MC_E_ARG, "null output descriptor");
     if (!out->result) return fail(MC_E_ARG, "null result pointer");
@@ -712,8 +794,10 @@ int launch_naive(const mc::ColDesc &C, hipStream_t s) {
 
 template <class T>
 int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out, char *ws,
-                   const ColLayout &L, hipStream_t s, bool naive = false) {
-    const mc::ColDesc C = make_desc(in, out, ws, ws + L.z_size, L);
+                   const ColLayout &L, hipStream_t s, bool naive = false,
+                   const mc_delta_index *ix = nullptr) {
+    mc::ColDesc C = make_desc(in, out, ws, ws + L.z_size, L);
+    if (ix) set_index_fields(C, ix);
     hipEvent_t *ev = nullptr;
     if (ctx->timing) {
         if (ctx->used == ctx->ev.size()) {
@@ -726,6 +810,13 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
     }
     int rc = launch_fill(ws, L.z_size, out->result, sizeof(mc_result), s);
     if (rc) return rc;
+    if (ix) {
+        const IndexLayout X = index_layout(ix->type, ix->capacity);
+        hipLaunchKernelGGL(k_or_word, dim3(1), dim3(64), 0, s, C.err,
+                           reinterpret_cast<const uint32_t *>(
+                               static_cast<char *>(ix->workspace) + X.scal + 80));
+        MC_LAUNCHED("k_or_word");
+    }
     rc = launch_delta_dictionary<T>(C, L, s, ev ? ev[1] : nullptr);
     if (rc) return rc;
     if (ev) MC_HIP(hipEventRecord(ev[2], s));
@@ -1200,6 +1291,102 @@ int mc_gather_ref(mc_ctx *ctx, const uint32_t *idx, uint64_t n, const void *tabl
 }
 
 // ---- batched ---------------------------------------------------------------
+
+int mc_delta_index_bytes(int32_t type, uint64_t capacity, uint64_t *bytes) {
+    if (value_len(type) == 0) return fail(MC_E_ARG, "unknown value type");
+    if (capacity >= (1ull << 30)) return fail(MC_E_ARG, "capacity must be < 2^30");
+    if (bytes) *bytes = index_layout(type, capacity).size;
+    return MC_OK;
+}
+
+int mc_delta_index_reset(mc_ctx *ctx, const mc_delta_index *ix, hipStream_t s) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    int rc = check_index(ix);
+    if (rc) return rc;
+    const IndexLayout X = index_layout(ix->type, ix->capacity);
+    // counters, scalars and the table; the rest is written before it is read
+    return launch_fill(ix->workspace, X.rep, nullptr, 0, s);
+}
+
+int mc_delta_index_append(mc_ctx *ctx, const mc_delta_index *ix, const void *delta_values,
+                          uint64_t row0, uint64_t rows, hipStream_t s) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    int rc = check_index(ix);
+    if (rc) return rc;
+    if (row0 > ix->capacity || rows > ix->capacity - row0)
+        return fail(MC_E_CAP, "rows past the index capacity");
+    if (rows == 0) return MC_OK;
+    if (!delta_values || !aligned16(delta_values)) return fail(MC_E_ARG, "bad delta buffer");
+    const IndexLayout X = index_layout(ix->type, ix->capacity);
+    char *w = static_cast<char *>(ix->workspace);
+    mc::ColDesc C;
+    memset(&C, 0, sizeof(C));
+    C.type = ix->type;
+    C.delta = delta_values;
+    C.nd = (uint32_t)(row0 + rows);
+    C.nd_max = ix->capacity;
+    C.hrow0 = row0;
+    set_index_fields(C, ix);
+    C.counters = reinterpret_cast<uint32_t *>(w + X.scal);
+    C.dbase = reinterpret_cast<const uint64_t *>(w + X.scal + 72);
+    C.err = reinterpret_cast<uint32_t *>(w + X.scal + 80);
+    const uint64_t ntiles = ceil_div(rows, mc::kCompactTile);
+    hipLaunchKernelGGL(k_index_prepare, dim3((uint32_t)std::min<uint64_t>(ceil_div(ntiles, 256), 1024)),
+                       dim3(256), 0, s, C.hstatus, ntiles, C.counters, C.dcount,
+                       reinterpret_cast<uint64_t *>(w + X.scal + 72));
+    MC_LAUNCHED("k_index_prepare");
+    const dim3 gh((uint32_t)ceil_div(rows, mc::kHashTile)), gc((uint32_t)ntiles), b(mc::kBlock);
+    switch (ix->type) {
+        case MC_U32:
+            hipLaunchKernelGGL(k1_hash_insert<mc::TU32>, gh, b, 0, s, C);
+            hipLaunchKernelGGL(k1_compact<mc::TU32>, gc, b, 0, s, C);
+            break;
+        case MC_U64:
+            hipLaunchKernelGGL(k1_hash_insert<mc::TU64>, gh, b, 0, s, C);
+            hipLaunchKernelGGL(k1_compact<mc::TU64>, gc, b, 0, s, C);
+            break;
+        default:
+            hipLaunchKernelGGL(k1_hash_insert<mc::TS16>, gh, b, 0, s, C);
+            hipLaunchKernelGGL(k1_compact<mc::TS16>, gc, b, 0, s, C);
+            break;
+    }
+    MC_LAUNCHED("k1_hash_insert / k1_compact (index)");
+    return MC_OK;
+}
+
+int mc_merge_indexed_bounds(const mc_column_in *in, uint64_t *scratch_bytes) {
+    int rc = check_in(in);
+    if (rc) return rc;
+    if (scratch_bytes)
+        *scratch_bytes = single_scratch(col_layout(in->type, in->main_dict_len, in->delta_rows,
+                                                   in->main_rows, true, kDefaultTuning, true));
+    return MC_OK;
+}
+
+int mc_merge_column_indexed(mc_ctx *ctx, const mc_column_in *in, const mc_delta_index *ix,
+                            const mc_column_out *out, void *scratch, uint64_t scratch_bytes,
+                            hipStream_t s) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    int rc = check_in(in);
+    if (rc) return rc;
+    rc = check_out(in, out);
+    if (rc) return rc;
+    rc = check_index(ix);
+    if (rc) return rc;
+    if (ix->type != in->type) return fail(MC_E_ARG, "index and column value types differ");
+    if (in->delta_rows > ix->capacity) return fail(MC_E_ARG, "delta_rows past the index capacity");
+    const ColLayout L = col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows,
+                                   true, ctx->tune, true);
+    if (!scratch || scratch_bytes < single_scratch(L))
+        return fail(MC_E_CAP, "scratch below mc_merge_indexed_bounds");
+    if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
+    char *ws = static_cast<char *>(scratch);
+    switch (in->type) {
+        case MC_U32: return merge_column_t<mc::TU32>(ctx, in, out, ws, L, s, false, ix);
+        case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, s, false, ix);
+        default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, s, false, ix);
+    }
+}
 
 int mc_merge_batched_bounds(const mc_column_in *ins, uint32_t ncols, uint64_t *scratch_bytes) {
     if (!ins && ncols) return fail(MC_E_ARG, "null descriptors");

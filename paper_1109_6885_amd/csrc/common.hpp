@@ -262,6 +262,8 @@ struct ColDesc {
     uint32_t *drankd;          // rank in U_D of every distinct value (by distinct position)
     uint64_t *dcount;          // number of distinct values (zeroed)
     uint64_t *hstatus;         // prefix words of the compaction (zeroed)
+    uint64_t hrow0;            // first delta row of this hashing launch (0 in a merge)
+    const uint64_t *dbase;     // distinct values listed before this batch, or null (0)
 };
 
 // The same prefix with the whole workgroup looking back: each round the 256

@@ -15,6 +15,12 @@
 //                      drankd[distinct position] = i
 //   rank_rows_tile     drank[row] = drankd[dindex[rep[row]]]
 //
+// The same two kernels keep a delta index up to date as rows are appended
+// (rows [hrow0, nd) of the delta, a batch at a time: the table, the
+// representatives and the distinct list persist between batches, and the
+// batch's new distinct values go after the *dbase ones already listed), so
+// that a merge can start from the distinct list.
+//
 // A slot holds (representative row + 1) and is written once, by one
 // compare-and-swap from zero.  Slots are read with device-coherent loads:
 // the compare-and-swap takes effect beyond the per-XCD L2, so a plain load
@@ -80,7 +86,8 @@ template <class T>
 __device__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
     typedef typename T::K K;
     HashSmem<T> &S = *reinterpret_cast<HashSmem<T> *>(smem);
-    const uint64_t r0 = t * kHashTile;
+    const uint64_t r0 = C.hrow0 + t * kHashTile;
+    if (r0 >= C.nd) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(kHashTile, C.nd - r0);
     for (uint32_t i = threadIdx.x; i < (uint32_t)kLocalSlots; i += kBlock) S.slot[i] = 0;
     for (uint32_t i = threadIdx.x; i < tn; i += kBlock) S.keys[i] = T::load(C.delta, r0 + i);
@@ -128,7 +135,8 @@ __device__ void compact_tile(const ColDesc &C, char *smem) {
     if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[2], 1u);
     __syncthreads();
     const uint32_t t = S.tile;
-    const uint64_t r0 = (uint64_t)t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+    const uint64_t base = C.dbase ? *C.dbase : 0;  // distinct values listed before this batch
+    const uint64_t r0 = C.hrow0 + (uint64_t)t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
     uint32_t flags = 0;
 #pragma unroll
     for (int j = 0; j < kCompactItems; j++) {
@@ -138,18 +146,24 @@ __device__ void compact_tile(const ColDesc &C, char *smem) {
     uint32_t tot;
     const uint32_t ex = block_excl_scan((uint32_t)__popc(flags), S.tmp, &tot);
     const uint64_t pre = lookback_block(C.hstatus, t, tot, C.err, S.lb64, S.lb32);
-    uint64_t pos = pre + ex;
+    uint64_t pos = base + pre + ex;
+    bool full = false;
 #pragma unroll
     for (int j = 0; j < kCompactItems; j++) {
         if ((flags >> j) & 1u) {
             const uint64_t row = r0 + j;
-            T::store(C.dkeys, pos, T::load(C.delta, row));
-            C.dindex[row] = (uint32_t)pos;
+            if (pos < C.nd_max) {  // the distinct list's capacity
+                T::store(C.dkeys, pos, T::load(C.delta, row));
+                C.dindex[row] = (uint32_t)pos;
+            } else {
+                full = true;
+            }
             pos++;
         }
     }
-    const uint64_t tb = (uint64_t)t * kCompactTile;
-    if (threadIdx.x == 0 && tb < C.nd && tb + kCompactTile >= C.nd) *C.dcount = pre + tot;
+    if (full) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+    const uint64_t tb = C.hrow0 + (uint64_t)t * kCompactTile;
+    if (threadIdx.x == 0 && tb < C.nd && tb + kCompactTile >= C.nd) *C.dcount = base + pre + tot;
 }
 
 // After the radix passes over the distinct values: every sorted position

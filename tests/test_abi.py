@@ -46,6 +46,7 @@ def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(_lib.McColumnIn) == 56
     assert ctypes.sizeof(_lib.McColumnOut) == 56
     assert ctypes.sizeof(_lib.McTuning) == 16
+    assert ctypes.sizeof(_lib.McDeltaIndex) == 32
 
 
 def _in(type_=1, w=20, n_um=1_048_000, n_main=100_000_000, nd=1_000_000, ptr=256):
@@ -119,3 +120,15 @@ def test_tuning_calls_reject_null_context(lib):
     assert lib.mc_ctx_set_tuning(None, ctypes.byref(t)) == -1
     assert lib.mc_ctx_get_tuning(None, ctypes.byref(t)) == -1
     assert lib.mc_autotune_batched(None, None, None, 0, None, 0, None, ctypes.byref(t), None) == -1
+
+
+def test_delta_index_bytes_and_argument_checks(lib):
+    b = ctypes.c_uint64()
+    assert lib.mc_delta_index_bytes(1, 1000, ctypes.byref(b)) == 0
+    # table of 2048 slots, representatives, positions, values, prefix words
+    assert b.value >= 2048 * 4 + 1000 * (4 + 4 + 8)
+    assert lib.mc_delta_index_bytes(7, 10, ctypes.byref(b)) == -1
+    assert lib.mc_delta_index_bytes(1, 1 << 30, ctypes.byref(b)) == -1
+    ix = _lib.McDeltaIndex(None, 0, 10, 1, 0)
+    assert lib.mc_delta_index_reset(None, ctypes.byref(ix), None) == -1
+    assert lib.mc_delta_index_append(None, ctypes.byref(ix), None, 0, 1, None) == -1
