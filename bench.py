@@ -151,7 +151,7 @@ def bench_serve(args):
     shapes = gpu_gen.served_shapes(64, scale)
     ex = serve.GpuExecutor(n_streams=4)
     budget = int(args.serve_budget_gb * 1e9)
-    srv = serve.Server(ex, budget_bytes=budget, max_inflight=4)
+    srv = serve.Server(ex, budget_bytes=budget, max_inflight=4, merge_trigger=args.serve_trigger)
     tick = 0.01
     pools = {}
     host_rng = np.random.default_rng(gpu_gen.BASE_SEED + 5)
@@ -193,10 +193,11 @@ def bench_serve(args):
         f"{resident0 / 1e9:.1f} GB resident, budget {budget / 1e9:.0f} GB")
 
     # Poisson arrivals at 5/s over warmup + window, each naming a random table
+    # (none with --serve-trigger: the server requests merges itself)
     arr_rng = np.random.default_rng(gpu_gen.BASE_SEED + 55)
     horizon = args.serve_warmup + args.serve_seconds
     arrivals, tt = [], 0.0
-    while True:
+    while args.serve_trigger is None:
         tt += arr_rng.exponential(1.0 / args.serve_rate)
         if tt >= horizon:
             break
@@ -233,6 +234,8 @@ def bench_serve(args):
         f"draining: {len(v.queue)} queued, {len(v.running)} running, "
         f"{v.in_use() / 1e9:.1f} GB in use"))
     torch.cuda.synchronize()
+    if args.serve_trigger is not None:
+        reqs = list(srv.done)
     counted = [r for r in reqs if r.arrival - t0 >= args.serve_warmup and r.committed is not None]
     lat = np.array([r.latency for r in counted]) if counted else np.zeros(0)
     window = t_end - (t0 + args.serve_warmup)
@@ -241,7 +244,10 @@ def bench_serve(args):
         "metric": "served merge stream: p50/p99 merge latency and merged tuples/s",
         "workload": f"64 tables, {ncols_total} columns (10-200 per table, batched column shapes "
                     f"x{scale}), appends {sum(r for _, _, r in shapes):.3g} rows/s total in 10 ms "
-                    f"ticks, merges Poisson {args.serve_rate}/s on random tables",
+                    f"ticks, " + (f"merges Poisson {args.serve_rate}/s on random tables"
+                                   if args.serve_trigger is None else
+                                   f"a table merged once its delta exceeds "
+                                   f"{args.serve_trigger:g} x its main rows"),
         "scale": scale, "budget_bytes": budget, "resident_bytes_start": resident0,
         "window_s": window, "requests": len(reqs), "committed_in_window": len(counted),
         "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
@@ -250,7 +256,7 @@ def bench_serve(args):
         "merged_tuples_s": sum(r.rows for r in counted) / window if window > 0 else None,
         "appended_rows_s": st["appended_rows"] / (t_end - t0),
         "admission_waits": st["admission_waits"], "backpressure": st["backpressure"],
-        "rejected": st["rejected"],
+        "rejected": st["rejected"], "auto_requests": st["auto_requests"],
         "late_ticks": late_ticks, "ticks": ticks,
         "peak_in_use_bytes": st["peak_in_use_bytes"],
     }
@@ -439,6 +445,78 @@ def bench_sweep_fig9(args):
                         "delta 1% of the main", "rows": rows}
 
 
+def bench_index(args):
+    """Update path with and without the delta index (Eq. 1): the delta of
+    configurations 2 and 3 arrives in batches of 65,536 rows that are copied
+    into the delta buffer (T_U) -- and, with the index, hashed into it as they
+    arrive -- then the column is merged (T_M).  Reports T_U, T_M, their step
+    split and the update rate N_D / (T_U + T_M) of one column."""
+    import torch
+
+    import paper_1109_6885_amd as cm
+    from workloads import gen
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rows_out = []
+    batch = 65_536
+    for k in (2, 3):
+        t = time.time()
+        col = gen.config_column(k)
+        log(f"config {k} generated in {time.time() - t:.1f}s")
+        dcol = cm.ColumnInput.from_numpy(col)
+        nd = col.n_delta
+        src = dcol.delta.clone()  # the arriving values
+        buf = torch.empty_like(src)  # the delta partition
+        esz = src.element_size() * (src.shape[1] if src.dim() == 2 else 1)
+        ix = cm.DeltaIndex(col.vtype, nd)
+        col_buf = cm.ColumnInput(col.vtype, dcol.u_m, dcol.main_codes, dcol.n_main, dcol.w, buf)
+        out = cm.alloc_output(col_buf)
+        scr = cm.alloc_scratch(max(cm.merge_bounds(col_buf)[2], cm.merge_indexed_bounds(col_buf)))
+        res = {}
+        for mode in ("plain", "indexed"):
+            ctx = cm.Context(torch.cuda.current_device())
+            t_u, t_m, steps = [], [], None
+            for rep in range(4):  # one warm-up round, then three timed
+                if mode == "indexed":
+                    ix.reset(stream)
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record(stream)
+                for r0 in range(0, nd, batch):
+                    r = min(batch, nd - r0)
+                    cm.copy_bytes(src[r0:r0 + r], buf[r0:r0 + r], r * esz, stream=stream)
+                    if mode == "indexed":
+                        ix.append(buf, r, stream=stream)
+                e1.record(stream)
+                if rep == 3:
+                    ctx.set_timing(True)
+                if mode == "indexed":
+                    cm.merge_column_indexed(col_buf, ix, out=out, scratch=scr, stream=stream, ctx=ctx)
+                else:
+                    cm.merge_column(col_buf, out=out, scratch=scr, stream=stream, ctx=ctx)
+                e2.record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    t_u.append(e0.elapsed_time(e1))
+                    t_m.append(e1.elapsed_time(e2))
+            steps = ctx.step_times()
+            sc = out.scalars()
+            assert sc["error"] == 0, sc
+            tu, tm = min(t_u), min(t_m)
+            res[mode] = {"append_ms": tu, "merge_ms": tm,
+                         "merge_steps_ms": {"clear+sort": steps[0], "emit": steps[1],
+                                            "merge_dict": steps[2], "reencode": steps[3]},
+                         "update_rate_per_s": nd / ((tu + tm) / 1e3)}
+            log(f"config {k} {mode}: T_U {tu:.3f} ms, T_M {tm:.3f} ms")
+            del ctx
+        rows_out.append({"config": gen.CONFIG_NAMES[k], "delta_rows": nd, "batch_rows": batch,
+                         **res})
+        del dcol, src, buf, ix, out, scr, col_buf
+        torch.cuda.empty_cache()
+    return {"metric": "update path: append (T_U) and merge (T_M) with and without the delta index",
+            "rows": rows_out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -458,10 +536,12 @@ def main():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="row and append-rate scale of the served tables")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-trigger", type=float, default=None,
+                    help="merge a table once N_D > f * N_M (Section 4) instead of Poisson requests")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-rate", type=float, default=5.0, help="merge requests per second")
-    ap.add_argument("--sweep", choices=["fig7", "fig8", "fig9"],
+    ap.add_argument("--sweep", choices=["fig7", "fig8", "fig9", "index"],
                     help="run a sweep instead and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -473,7 +553,8 @@ def main():
         print(json.dumps(bench_serve(args)), flush=True)
         return
     if args.sweep:
-        fn = {"fig7": bench_sweep_fig7, "fig8": bench_sweep_fig8, "fig9": bench_sweep_fig9}
+        fn = {"fig7": bench_sweep_fig7, "fig8": bench_sweep_fig8, "fig9": bench_sweep_fig9,
+              "index": bench_index}
         print(json.dumps(fn[args.sweep](args)), flush=True)
         return
 

@@ -21,7 +21,10 @@ keeps that protocol for many tables at once on one GPU:
 * commit swaps the table's main for the merge result, frees the old main and
   clears the snapshot buffer, which becomes the next second delta;
 * latency = commit time - arrival time; p50/p99 and merged tuples/s are
-  reported.
+  reported;
+* optionally the paper's merge trigger (Section 4) submits the requests
+  itself: a table is merged once its delta holds more than a given fraction
+  of the main's rows.
 
 The Server logic talks to an executor (GpuExecutor here; the tests also use
 a CPU executor), so admission, snapshot and commit rules are checked without
@@ -66,8 +69,11 @@ class TableState:
 class Server:
     """Admission, snapshot and commit for merges of resident tables."""
 
-    def __init__(self, executor, budget_bytes: int, max_inflight: int = 4, clock=None):
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 4, clock=None,
+                 merge_trigger: float | None = None):
         self.ex = executor
+        self.merge_trigger = merge_trigger  # f: merge once N_D > f * N_M (None: requests only)
+        self.auto_requests = 0
         self.budget = int(budget_bytes)
         self.max_inflight = max_inflight
         self.clock = clock or time.perf_counter
@@ -125,7 +131,21 @@ class Server:
             self._refresh_need(t)
         self.appended_rows += n
         self._note_use()
+        self._maybe_trigger(tid, t)
         return True
+
+    def _maybe_trigger(self, tid: int, t: TableState):
+        """Merge trigger of Section 4: request a merge of the table once its
+        active delta holds more than merge_trigger times the main's rows (one
+        request per table at a time)."""
+        if self.merge_trigger is None or t.merging is not None:
+            return
+        if any(r.table == tid for r in self.queue):
+            return
+        n_main = self.ex.main_rows(t.main) / max(1, self.ex.columns(t.main))
+        if self.ex.delta_rows(t.active) > self.merge_trigger * n_main:
+            self.submit_merge(tid)
+            self.auto_requests += 1
 
     # ---- requests -----------------------------------------------------------
 
@@ -261,6 +281,7 @@ class Server:
             "admission_waits": self.admission_waits,
             "backpressure": self.backpressure,
             "rejected": self.rejected,
+            "auto_requests": self.auto_requests,
             "peak_in_use_bytes": self.peak_in_use,
             "budget_bytes": self.budget,
             "wall_s": wall,

@@ -318,3 +318,44 @@ def test_growth_keeps_room_for_the_largest_merge():
     reqs = [s.submit_merge(t) for t in range(3)]
     s.drain()
     assert all(r.status == "committed" for r in reqs) and s.rejected == 0
+
+
+def test_merge_trigger_fraction_of_main():
+    """Section 4's trigger: a merge is requested once the delta holds more
+    than f * N_M rows, once per table at a time, and the merged table holds
+    every appended row in order."""
+    rng = np.random.default_rng(21)
+    ex = CpuExecutor(polls_to_finish=2)
+    s = Server(ex, budget_bytes=10 ** 12, clock=FakeClock(), merge_trigger=0.1)
+    m = make_table(rng, 2, 200)       # N_M = 200 rows: trigger above 20 delta rows
+    expected = [decode(c) for c in m.cols]
+    shape = CpuMain([dict(c) for c in m.cols])  # batches keep the column types after commits
+    s.add_table(0, m, delta_capacity=1000)
+    batches = []
+    for n in (10, 10):                 # 20 rows: not above 20
+        batches.append(batch(rng, shape, n))
+        assert s.append(0, batches[-1])
+    assert not s.queue and s.auto_requests == 0
+    batches.append(batch(rng, shape, 1))   # 21 rows: requested
+    assert s.append(0, batches[-1])
+    assert len(s.queue) == 1 and s.auto_requests == 1
+    batches.append(batch(rng, shape, 5))   # still queued: no second request
+    assert s.append(0, batches[-1])
+    assert len(s.queue) == 1 and s.auto_requests == 1
+    s.poll()                           # admitted: the active delta is the empty second one
+    assert s.running and s.tables[0].merging is not None
+    batches.append(batch(rng, shape, 30))  # above 0.1 * 200, but the table is merging
+    assert s.append(0, batches[-1])
+    assert s.auto_requests == 1
+    s.drain()
+    batches.append(batch(rng, shape, 1))   # N_M is now 226: 31 rows > 22.6 -> requested again
+    assert s.append(0, batches[-1])
+    assert s.auto_requests == 2
+    s.drain()
+    final = s.tables[0].main
+    for j, c in enumerate(final.cols):
+        vt = c["vtype"]
+        add = [(bytes(np.asarray(v, np.uint8)) if vt == "str16" else int(v))
+               for b in batches for v in b["cols"][j]]
+        assert decode(c) == expected[j] + add
+    assert s.stats()["auto_requests"] == 2
