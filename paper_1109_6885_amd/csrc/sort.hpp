@@ -20,10 +20,11 @@
 // window_sort_tile then sorts windows of one tile in LDS by the whole value,
 // first windows aligned to tiles, then windows shifted by half a tile: a run
 // of equal prefix no longer than half a tile lies inside one window of one of
-// the two rounds, so the array ends up sorted.  emit_tile checks every
-// adjacent pair; if a long run (heavy duplicates, clustered values) left the
-// order wrong, the full LSD sort over every digit runs after it (its launches
-// return at once otherwise) and emit runs again.
+// the two rounds, so the array ends up sorted.  A window that meets a long
+// run out of order flags it at once, and emit_tile checks every adjacent
+// pair; either way (heavy duplicates, clustered values) the full LSD sort
+// over every digit runs after the emit (its launches return at once
+// otherwise) and emit runs again.
 //
 // emit_tile marks run heads of the sorted values, numbers them with a
 // cross-tile prefix, writes U_D and scatters each row's index (the paper's
@@ -360,8 +361,10 @@ __device__ void sort_down_tile(const ColDesc &C, const PassIO &io, uint32_t t, c
 // equal prefix need ordering: a value's place in its run is the number of
 // run members that are smaller (or equal and before it).  Runs longer than
 // kRunLimit keep their place if already ordered (runs of one repeated value);
-// a long run out of order makes the whole window take LDS radix passes over
-// every varying digit.
+// a long run out of order (heavy duplicates among other values, clustered
+// values) means the prefix sort cannot finish the job: the window sets the
+// "out of order" flag at once and leaves its values, and the full LSD sort
+// after the emit starts over from the unsorted values.
 
 constexpr uint32_t kRunLimit = 256;
 
@@ -373,39 +376,6 @@ __device__ __forceinline__ uint32_t prefix_of(const typename T::K &k, const int 
     for (int s = 0; s < kPrefixSlots; s++)
         if (pp[s] >= 0) v = (v << 8) | T::digit(k, pp[s]);
     return v;
-}
-
-template <class T>
-__device__ void window_radix(const ColDesc &C, DownSmem<T> &S, uint32_t tn) {
-    typedef typename T::K K;
-    constexpr int P = T::kBytes;
-    constexpr int ITEMS = SortCfg<T>::kItems;
-    constexpr int WCHUNK = 64 * ITEMS;
-    const int lane = lane_id(), wv = wave_id();
-    for (int p = 0; p < P; p++) {
-        if (C.trivial[p]) continue;  // the same for the whole block
-        K key[ITEMS];
-        uint32_t val[ITEMS], dig[ITEMS], slot[ITEMS];
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            const uint32_t li = wv * WCHUNK + j * 64 + lane;
-            dig[j] = 0;
-            if (li < tn) {
-                key[j] = S.keys[li];
-                val[j] = S.vals[li];
-                dig[j] = T::digit(key[j], p);
-            }
-        }
-        rank_digits<ITEMS>(dig, tn, S.wcnt, S.dex, S.tmp, slot);  // ends with a barrier
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            if ((uint32_t)(wv * WCHUNK + j * 64 + lane) < tn) {
-                S.keys[slot[j]] = key[j];
-                S.vals[slot[j]] = val[j];
-            }
-        }
-        __syncthreads();
-    }
 }
 
 template <class T>
@@ -477,22 +447,17 @@ __device__ void window_sort_tile(const ColDesc &C, int round, uint32_t t, char *
     }
     if (disorder) S.tmp[0] = 1u;
     __syncthreads();
-    if (S.tmp[0] == 0) {
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            const uint32_t i = j * kBlock + wv * 64 + lane;
-            if (i < tn && npos[j] != i) {
-                T::store(C.keys1, b0 + npos[j], S.keys[i]);
-                C.vals1[b0 + npos[j]] = S.vals[i];
-            }
-        }
+    if (S.tmp[0] != 0) {
+        if (threadIdx.x == 0) C.sflags[kSfUnsorted] = 1u;  // the full sort takes over
         return;
     }
-    __syncthreads();  // every thread has read S.tmp[0] and the mask before the radix passes
-    window_radix<T>(C, S, tn);
-    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
-        T::store(C.keys1, b0 + i, S.keys[i]);
-        C.vals1[b0 + i] = S.vals[i];
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t i = j * kBlock + wv * 64 + lane;
+        if (i < tn && npos[j] != i) {
+            T::store(C.keys1, b0 + npos[j], S.keys[i]);
+            C.vals1[b0 + npos[j]] = S.vals[i];
+        }
     }
 }
 
