@@ -67,21 +67,35 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
 
 
-def merge_column(vtype: str, u_m, main_packed, n_main: int, w: int, delta, threads: int) -> dict:
+def alloc_outputs(vtype: str, n_um: int, n_main: int, nd: int) -> dict:
+    """Output buffers for a merge of these sizes (reusable across calls, so a
+    timed call does not pay for fresh pages)."""
+    shape = (n_um + nd, 16) if vtype == "str16" else (n_um + nd,)
+    rows = n_main + nd
+    return {"u_new": np.zeros(shape, dtype=np.uint8 if vtype == "str16" else DTYPES[vtype]),
+            "out": np.zeros(max(1, (rows * 32 + 63) // 64), dtype=np.uint64),
+            "x_m": np.zeros(max(1, n_um), dtype=np.uint32),
+            "x_d": np.zeros(max(1, nd), dtype=np.uint32),
+            "sizes": (vtype, n_um, n_main, nd)}
+
+
+def merge_column(vtype: str, u_m, main_packed, n_main: int, w: int, delta, threads: int,
+                 outputs: dict | None = None) -> dict:
     """The merged column: dict with u_new, codes (uint64 words), w_new, n_new,
-    n_words, x_m, x_d (|U_D| entries)."""
+    n_words, x_m, x_d (|U_D| entries), views into `outputs` (from
+    alloc_outputs with the same sizes) when given."""
     lib = _load()
     n_um = int(len(u_m))
     nd = int(len(delta))
     u_m = _arr(vtype, u_m, n_um)
     delta = _arr(vtype, delta, nd)
     codes = np.ascontiguousarray(main_packed, dtype=np.uint64)
-    shape = (n_um + nd, 16) if vtype == "str16" else (n_um + nd,)
-    u_new = np.zeros(shape, dtype=np.uint8 if vtype == "str16" else DTYPES[vtype])
+    if outputs is None:
+        outputs = alloc_outputs(vtype, n_um, n_main, nd)
+    elif outputs["sizes"] != (vtype, n_um, n_main, nd):
+        raise CpuMergeError(f"outputs sized for {outputs['sizes']}, not {(vtype, n_um, n_main, nd)}")
+    u_new, out, x_m, x_d = outputs["u_new"], outputs["out"], outputs["x_m"], outputs["x_d"]
     rows = n_main + nd
-    out = np.zeros(max(1, (rows * 32 + 63) // 64), dtype=np.uint64)
-    x_m = np.zeros(max(1, n_um), dtype=np.uint32)
-    x_d = np.zeros(max(1, nd), dtype=np.uint32)
     n_new, w_new, n_ud = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
     rc = lib.cmp_merge_column(TYPES[vtype], _ptr(u_m), n_um, _ptr(codes), n_main, w,
                               _ptr(delta), nd, threads, _ptr(u_new), _ptr(out), _ptr(x_m),

@@ -49,3 +49,22 @@ def test_bad_code_is_reported():
     packed = gen.pack_codes(np.array([0, 3, 2], np.uint32), 2)  # code 3 >= |U_M|
     with pytest.raises(cpu_parallel.CpuMergeError):
         cpu_parallel.merge_column("u64", u_m, packed, 3, 2, np.array([4], np.uint64), 2)
+
+
+def test_reused_outputs():
+    """Output buffers reused across calls give the same result as fresh ones;
+    buffers sized for another merge are refused."""
+    rng = np.random.default_rng(23)
+    col = gen.random_column(rng, "u64", 500, 20_000, 7_000, 0.5)
+    o = cpu_parallel.alloc_outputs("u64", len(col.u_m), col.n_main, len(col.delta))
+    o["out"][:] = ~np.uint64(0)  # stale contents must not leak into the result
+    ref = oracle.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w, col.delta)
+    for threads in (4, 2):
+        got = cpu_parallel.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w,
+                                        col.delta, threads, outputs=o)
+        assert np.array_equal(got["codes"], ref["codes"])
+        assert np.array_equal(got["x_d"], ref["x_d"])
+    small = cpu_parallel.alloc_outputs("u64", 10, 10, 10)
+    with pytest.raises(cpu_parallel.CpuMergeError):
+        cpu_parallel.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w,
+                                  col.delta, 2, outputs=small)
