@@ -249,9 +249,16 @@ int mc_merge_column_indexed(mc_ctx *ctx, const mc_column_in *in,
 
 /* ---- many columns at once (Section 6.2.1, scheme (i)) ----------------- */
 
-/* Worst-case scratch for merging ncols columns in one batched call. */
+/* Worst-case scratch for merging ncols columns in one batched call on a
+ * context with the default tuning.  Every column takes the Step 1(a) route
+ * it would take alone (deltas of 2^21 rows or more hash first), so columns
+ * on the hashing route need its table and distinct-value buffers too. */
 int mc_merge_batched_bounds(const mc_column_in *ins, uint32_t ncols,
                             uint64_t *scratch_bytes);
+/* The same for batched merges on `ctx`, whose hash_min_rows can send more
+ * deltas to the hashing route (NULL: defaults). */
+int mc_merge_batched_bounds_ctx(const mc_ctx *ctx, const mc_column_in *ins,
+                                uint32_t ncols, uint64_t *scratch_bytes);
 
 /* Enqueue the merge of ncols independent columns (uneven sizes and value
  * types) as one batched launch sequence: every kernel covers the tiles of

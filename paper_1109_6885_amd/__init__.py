@@ -219,12 +219,13 @@ def bounds_of(desc: McColumnIn):
     return int(a.value), int(b.value), int(c.value)
 
 
-def batched_bounds_of(descs) -> int:
-    """mc_merge_batched_bounds on raw descriptors."""
+def batched_bounds_of(descs, ctx: "Context | None" = None) -> int:
+    """mc_merge_batched_bounds_ctx on raw descriptors (ctx None: default tuning)."""
     arr = (McColumnIn * len(descs))(*descs)
     sb = ctypes.c_uint64()
-    check(load().mc_merge_batched_bounds(arr, len(descs), ctypes.byref(sb)),
-          "mc_merge_batched_bounds")
+    check(load().mc_merge_batched_bounds_ctx(ctx.handle if ctx is not None else None, arr,
+                                             len(descs), ctypes.byref(sb)),
+          "mc_merge_batched_bounds_ctx")
     return int(sb.value)
 
 
@@ -439,12 +440,10 @@ class Graph:
             pass
 
 
-def batched_bounds(cols) -> int:
-    arr = (McColumnIn * len(cols))(*[c.descriptor() for c in cols])
-    sb = ctypes.c_uint64()
-    check(load().mc_merge_batched_bounds(arr, len(cols), ctypes.byref(sb)),
-          "mc_merge_batched_bounds")
-    return int(sb.value)
+def batched_bounds(cols, ctx: "Context | None" = None) -> int:
+    """Scratch bytes for one batched merge of these columns on ctx (None:
+    default tuning)."""
+    return batched_bounds_of([c.descriptor() for c in cols], ctx)
 
 
 # candidates of mc_autotune_batched, in the order of its times
@@ -460,7 +459,7 @@ def autotune_batched(cols, outs=None, scratch=None, stream=None, ctx=None):
     if outs is None:
         outs = [alloc_output(c) for c in cols]
     if scratch is None:
-        scratch = alloc_scratch(batched_bounds(cols))
+        scratch = alloc_scratch(batched_bounds(cols, ctx))
     ins = (McColumnIn * len(cols))(*[c.descriptor() for c in cols])
     os_ = (McColumnOut * len(cols))(*[o.descriptor() for o in outs])
     t = McTuning()
@@ -479,7 +478,7 @@ def merge_columns_batched(cols, outs=None, scratch=None, graph: bool = False, st
     if outs is None:
         outs = [alloc_output(c) for c in cols]
     if scratch is None:
-        scratch = alloc_scratch(batched_bounds(cols))
+        scratch = alloc_scratch(batched_bounds(cols, ctx))
     ins = (McColumnIn * len(cols))(*[c.descriptor() for c in cols])
     os_ = (McColumnOut * len(cols))(*[o.descriptor() for o in outs])
     g = ctypes.c_void_p() if graph else None

@@ -32,7 +32,7 @@ EXPORTS = [
     "mc_ctx_step_times", "mc_copy_bytes", "mc_gather_ref", "mc_merge_column_naive",
     "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched", "mc_merge_bounds_ctx",
     "mc_delta_index_bytes", "mc_delta_index_reset", "mc_delta_index_append",
-    "mc_merge_indexed_bounds", "mc_merge_column_indexed",
+    "mc_merge_indexed_bounds", "mc_merge_column_indexed", "mc_merge_batched_bounds_ctx",
 ]
 
 
@@ -109,6 +109,7 @@ def load():
         "mc_merge_dictionaries_scratch": (ctypes.c_int, [u64, u64, pu64]),
         "mc_reencode": (ctypes.c_int, [p, p, u64, u32, p, u64, p, u64, p, p, p, u64, p]),
         "mc_merge_batched_bounds": (ctypes.c_int, [pin, u32, pu64]),
+        "mc_merge_batched_bounds_ctx": (ctypes.c_int, [p, pin, u32, pu64]),
         "mc_merge_columns_batched": (ctypes.c_int, [p, pin, pout, u32, p, u64, p,
                                                     ctypes.POINTER(p)]),
         "mc_graph_launch": (ctypes.c_int, [p, p]),

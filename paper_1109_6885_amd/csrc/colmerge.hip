@@ -354,6 +354,8 @@ constexpr size_t kSmemMerge = max3(sizeof(mc::MergeSmem<mc::TU32>),
                                    sizeof(mc::MergeSmem<mc::TU64>),
                                    sizeof(mc::MergeSmem<mc::TS16>));
 constexpr size_t kSmemSmall = 1024;
+constexpr size_t kSmemHash = max3(sizeof(mc::HashSmem<mc::TU32>), sizeof(mc::HashSmem<mc::TU64>),
+                                  sizeof(mc::HashSmem<mc::TS16>));
 constexpr size_t kSmemHistScan = (mc::kWaves + 16) * 4;  // scan scratch + digits per position
 
 __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, uint32_t *p1,
@@ -569,7 +571,28 @@ __global__ __launch_bounds__(256) void kn_emit(Batch B, int again) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::emit_tile, C, smem, again != 0);
+    if (C.drankd) {  // hashing route: the sorted values are distinct
+        MC_DISPATCH(C, mc::emit_distinct_tile, C, blockIdx.x - B.map[j], again != 0);
+    } else {
+        MC_DISPATCH(C, mc::emit_tile, C, smem, again != 0);
+    }
+}
+// Step 1(a)'s hashing route for the columns whose deltas take it
+__global__ __launch_bounds__(256) void kn_hash_insert(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemHash];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::hash_insert_tile, C, blockIdx.x - B.map[j], smem);
+}
+__global__ __launch_bounds__(256) void kn_compact(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::CompactSmem)];
+    const uint32_t j = find_col(B, blockIdx.x);
+    const mc::ColDesc &C = B.cols[j];
+    MC_DISPATCH(C, mc::compact_tile, C, smem);
+}
+__global__ __launch_bounds__(256) void kn_rank_rows(Batch B) {
+    const uint32_t j = find_col(B, blockIdx.x);
+    mc::rank_rows_tile(B.cols[j], blockIdx.x - B.map[j]);
 }
 __global__ __launch_bounds__(256) void kn_merge_part(Batch B) {
     const uint32_t j = find_col(B, blockIdx.x);
@@ -859,10 +882,12 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 
 constexpr int kMaxPasses = 16;
 // map slots: 0 hist, 1 hist_scan, 2..17 pass up/down, 18..33 pass scan,
-// 34 emit, 35 merge, 36 repack, 37 X_M compaction, 38 merge tile boundaries
+// 34 emit, 35 merge, 36 repack, 37 X_M compaction, 38 merge tile boundaries,
+// 39 hash insert, 40 compaction of the distinct values, 41 row ranks
 constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 2 + kMaxPasses,
               kMapEmit = 2 + 2 * kMaxPasses, kMapMerge = kMapEmit + 1, kMapRepack = kMapEmit + 2,
-              kMapXc = kMapEmit + 3, kMapMergePart = kMapEmit + 4, kNumMaps = kMapEmit + 5;
+              kMapXc = kMapEmit + 3, kMapMergePart = kMapEmit + 4, kMapHash = kMapEmit + 5,
+              kMapCompact = kMapEmit + 6, kMapRank = kMapEmit + 7, kNumMaps = kMapEmit + 8;
 
 struct BatchPlan {
     uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, total = 0;
@@ -888,8 +913,9 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
     for (uint32_t i = 0; i < ncols; i++) {
         int rc = check_in(&ins[i]);
         if (rc) return rc;
+        // each column takes the Step 1(a) route it would take alone
         P.L[i] = col_layout(ins[i].type, ins[i].main_dict_len, ins[i].delta_rows,
-                            ins[i].main_rows, /*allow_hash=*/false, tune);
+                            ins[i].main_rows, /*allow_hash=*/true, tune);
         P.z_off[i] = z;
         z += P.L[i].z_size;
         P.b_off[i] = b;
@@ -920,6 +946,9 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
             else if (m == kMapRepack) n = L.repack_tiles;
             else if (m == kMapXc) n = L.xc_tiles;
             else if (m == kMapMergePart) n = L.partitioned ? merge_part_blocks(L.merge_tiles) : 0;
+            else if (m == kMapHash || m == kMapRank) n = L.hashed ? L.hash_tiles : 0;
+            else if (m == kMapCompact)
+                n = L.hashed ? ceil_div(ins[j].delta_rows, mc::kCompactTile) : 0;
             at(m, j) = (uint32_t)acc;
             acc += n;
             if (acc >= (1ull << 31)) return fail(MC_E_ARG, "batch has too many tiles for one launch");
@@ -945,6 +974,15 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
     if (rc) return rc;
     hipLaunchKernelGGL(kn_zero_results, dim3((ncols + 255) / 256), dim3(256), 0, s, batch(0));
     MC_LAUNCHED("kn_zero_results");
+    if (tiles(kMapHash)) {
+        // hashing route: distinct values first, then the sort phases see only them
+        hipLaunchKernelGGL(kn_hash_insert, dim3(tiles(kMapHash)), dim3(mc::kBlock), 0, s,
+                           batch(kMapHash));
+        MC_LAUNCHED("kn_hash_insert");
+        hipLaunchKernelGGL(kn_compact, dim3(tiles(kMapCompact)), dim3(mc::kBlock), 0, s,
+                           batch(kMapCompact));
+        MC_LAUNCHED("kn_compact");
+    }
     if (tiles(kMapHist)) {
         hipLaunchKernelGGL(kn_hist, dim3(tiles(kMapHist)), dim3(mc::kBlock), 0, s, batch(kMapHist));
         MC_LAUNCHED("kn_hist");
@@ -990,6 +1028,11 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
                                batch(kMapEmit), again);
             MC_LAUNCHED("kn_emit");
         }
+    }
+    if (tiles(kMapRank)) {
+        hipLaunchKernelGGL(kn_rank_rows, dim3(tiles(kMapRank)), dim3(mc::kBlock), 0, s,
+                           batch(kMapRank));
+        MC_LAUNCHED("kn_rank_rows");
     }
     if (tiles(kMapMergePart)) {
         hipLaunchKernelGGL(kn_merge_part, dim3(tiles(kMapMergePart)), dim3(mc::kBlock), 0, s,
@@ -1388,13 +1431,18 @@ int mc_merge_column_indexed(mc_ctx *ctx, const mc_column_in *in, const mc_delta_
     }
 }
 
-int mc_merge_batched_bounds(const mc_column_in *ins, uint32_t ncols, uint64_t *scratch_bytes) {
+int mc_merge_batched_bounds_ctx(const mc_ctx *ctx, const mc_column_in *ins, uint32_t ncols,
+                                uint64_t *scratch_bytes) {
     if (!ins && ncols) return fail(MC_E_ARG, "null descriptors");
     BatchPlan P;
-    int rc = plan_batch(ins, ncols, P);
+    int rc = plan_batch(ins, ncols, P, ctx ? ctx->tune : kDefaultTuning);
     if (rc) return rc;
     if (scratch_bytes) *scratch_bytes = P.total;
     return MC_OK;
+}
+
+int mc_merge_batched_bounds(const mc_column_in *ins, uint32_t ncols, uint64_t *scratch_bytes) {
+    return mc_merge_batched_bounds_ctx(nullptr, ins, ncols, scratch_bytes);
 }
 
 int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,

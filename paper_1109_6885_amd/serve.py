@@ -437,7 +437,7 @@ class GpuExecutor:
             ins.append(d)
             dc, words, _ = cm.bounds_of(d)
             total += dc * cm.VALUE_LEN[c.vtype] + max(words, 2) * 8 + cm.RESULT_BYTES
-        total += cm.batched_bounds_of(ins)
+        total += cm.batched_bounds_of(ins, self.ctx)
         if len(cache) > 64:
             cache.clear()
         cache[key] = total
@@ -461,7 +461,7 @@ class GpuExecutor:
                     torch.empty(max(words, 2), dtype=torch.int64, device=f"cuda:{self.device}"),
                     None, None, res[j * cm.RESULT_BYTES:(j + 1) * cm.RESULT_BYTES],
                     col.n_main + int(col.delta.shape[0])))
-            scratch = cm.alloc_scratch(cm.batched_bounds(cols))
+            scratch = cm.alloc_scratch(cm.batched_bounds(cols, self.ctx))
             cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s, ctx=self.ctx)
             done = torch.cuda.Event()
             done.record(s)

@@ -115,6 +115,22 @@ def test_batched_bounds(lib):
     assert lib.mc_merge_batched_bounds(bad, 1, ctypes.byref(sb)) == -1
 
 
+def test_batched_bounds_cover_the_hashing_route(lib):
+    """A delta of 2^21 rows or more hashes first in a batch as it does alone:
+    the batched bound covers that column's single-call bound (which includes
+    the hash table and distinct-value buffers); the _ctx form with no context
+    equals the plain one."""
+    big = _in(type_=1, w=20, n_um=1000, n_main=5000, nd=3_000_000)
+    ins = (_lib.McColumnIn * 2)(big, _in(type_=0, w=12, n_um=4000, n_main=10_000, nd=500))
+    sb, sc = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.mc_merge_batched_bounds(ins, 2, ctypes.byref(sb)) == 0
+    assert lib.mc_merge_batched_bounds_ctx(None, ins, 2, ctypes.byref(sc)) == 0
+    assert sb.value == sc.value
+    assert sb.value >= _bounds(lib, ins[0])[3] + _bounds(lib, ins[1])[3]
+    # the hash table alone (a power of two of at least twice the rows, 4 bytes a slot)
+    assert sb.value >= (1 << 23) * 4
+
+
 def test_tuning_calls_reject_null_context(lib):
     t = _lib.McTuning(2048, 32)
     assert lib.mc_ctx_set_tuning(None, ctypes.byref(t)) == -1

@@ -156,3 +156,67 @@ def test_batched_equals_plain():
         assert np.array_equal(ga["codes"], gb["codes"])
         assert np.array_equal(ga["u_new"], gb["u_new"])
         assert ga["w_new"] == gb["w_new"]
+
+
+def _replay_and_check(outs, graph, first, reps=3):
+    for rep in range(reps):
+        for o in outs:
+            o.new_codes.zero_()
+            o.new_dict.zero_()
+        x = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        for g0, o in zip(first, outs):
+            g = o.fetch()
+            assert g["error"] == 0
+            assert np.array_equal(g["codes"], g0["codes"]), f"replay {rep}"
+            assert np.array_equal(g["u_new"], g0["u_new"]), f"replay {rep}"
+        del x
+
+
+def test_batched_hash_route():
+    """Columns whose deltas reach 2^21 rows hash first inside the batch, as
+    they do alone (all distinct, heavy duplicates), beside radix-route and
+    empty-delta columns; directly, then from a graph replayed three times
+    with eager work between the replays."""
+    rng = np.random.default_rng(11)
+    n = (1 << 21) + 777
+    cols = [gen.random_column(rng, "u64", 50_000, 200_000, n, 0.5),
+            gen.random_column(rng, "u32", 300, 2000, 100, 0.5),
+            gen.random_column(rng, "str16", 20_000, 100_000, n + 5, 0.3, zipf_s=1.1,
+                              new_pool=5000),
+            gen.random_column(rng, "u32", 1000, 10_000, 0)]
+    say(f"case batched hash route, {len(cols)} columns, delta rows {[c.n_delta for c in cols]}")
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, _ = cm.merge_columns_batched(dcols)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    say("case batched hash route, graph")
+    gouts, graph = cm.merge_columns_batched(dcols, graph=True)
+    torch.cuda.synchronize()
+    first = [o.fetch() for o in gouts]
+    for c, g in zip(cols, first):
+        check_col(c, g)
+    _replay_and_check(gouts, graph, first)
+
+
+def test_batched_forced_hash_route():
+    """Every column with a delta through the hashing route (hash_min_rows = 1
+    on the context, scratch from the context's bound): the whole small batch
+    against the oracle, and the same as the plain calls on that context."""
+    cols = small_batch(24, 0.002)
+    say(f"case batched forced hash route, {len(cols)} columns")
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(hash_min_rows=1)
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    assert cm.batched_bounds(dcols, ctx) > cm.batched_bounds(dcols)
+    outs, _ = cm.merge_columns_batched(dcols, ctx=ctx)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    plain = [cm.merge_column(d, ctx=ctx) for d in dcols]
+    torch.cuda.synchronize()
+    for a, b in zip(outs, plain):
+        assert np.array_equal(a.fetch()["codes"], b.fetch()["codes"])
