@@ -437,10 +437,14 @@ __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int kind, int
     mc::PassIO io;
     if (pass_io(C, kind, p, &io)) mc::sort_down_tile<T>(C, io, blockIdx.x, smem);
 }
+// round 0: every tile sorted in LDS; round 1: the runs crossing tile seams
 template <class T>
 __global__ __launch_bounds__(256) void k1_window(mc::ColDesc C, int round) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
-    mc::window_sort_tile<T>(C, round, blockIdx.x, smem);
+    if (round == 0)
+        mc::window_sort_tile<T>(C, blockIdx.x, smem);
+    else
+        mc::window_seam_tile<T>(C, blockIdx.x, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C, int again) {
@@ -565,7 +569,11 @@ __global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::window_sort_tile, C, round, blockIdx.x - B.map[j], smem);
+    if (round == 0) {
+        MC_DISPATCH(C, mc::window_sort_tile, C, blockIdx.x - B.map[j], smem);
+    } else {
+        MC_DISPATCH(C, mc::window_seam_tile, C, blockIdx.x - B.map[j], smem);
+    }
 }
 __global__ __launch_bounds__(256) void kn_emit(Batch B, int again) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];

@@ -17,14 +17,15 @@
 // many as it takes for runs of about 32 values on average, judged from the
 // histograms) leave the values ordered by their leading bytes ("prefix"), in
 // runs of equal prefix.
-// window_sort_tile then sorts windows of one tile in LDS by the whole value,
-// first windows aligned to tiles, then windows shifted by half a tile: a run
-// of equal prefix no longer than half a tile lies inside one window of one of
-// the two rounds, so the array ends up sorted.  A window that meets a long
-// run out of order flags it at once, and emit_tile checks every adjacent
-// pair; either way (heavy duplicates, clustered values) the full LSD sort
-// over every digit runs after the emit (its launches return at once
-// otherwise) and emit runs again.
+// window_sort_tile then sorts every tile in LDS by the whole value: each run
+// of equal prefix inside the tile is ordered.  window_seam_tile finishes the
+// runs that cross a tile seam: such a run, if it is short, is ranked as a
+// whole; if it is long, both of its sides are already ordered and only the
+// pair across the seam needs checking.  A tile or seam that meets a long run
+// out of order flags it at once, and emit_tile checks every adjacent pair;
+// either way (heavy duplicates, clustered values) the full LSD sort over
+// every digit runs after the emit (its launches return at once otherwise)
+// and emit runs again.
 //
 // emit_tile marks run heads of the sorted values, numbers them with a
 // cross-tile prefix, writes U_D and scatters each row's index (the paper's
@@ -356,15 +357,16 @@ __device__ void sort_down_tile(const ColDesc &C, const PassIO &io, uint32_t t, c
 }
 
 // ---- windows sorted in LDS after the prefix passes --------------------------
-// Round 0 sorts [t*TILE, (t+1)*TILE), round 1 [t*TILE + TILE/2, ...), in place
-// in keys1 / vals1.  The window is already ordered by prefix, so only runs of
-// equal prefix need ordering: a value's place in its run is the number of
-// run members that are smaller (or equal and before it).  Runs longer than
-// kRunLimit keep their place if already ordered (runs of one repeated value);
-// a long run out of order (heavy duplicates among other values, clustered
-// values) means the prefix sort cannot finish the job: the window sets the
-// "out of order" flag at once and leaves its values, and the full LSD sort
-// after the emit starts over from the unsorted values.
+// window_sort_tile sorts [t*TILE, (t+1)*TILE) in place in keys1 / vals1.  The
+// tile is already ordered by prefix, so only runs of equal prefix need
+// ordering: a value's place in its run is the number of run members that
+// are smaller (or equal and before it).  Runs longer than kRunLimit keep
+// their place if already ordered (runs of one repeated value); a long run
+// out of order (heavy duplicates among other values, clustered values)
+// means the prefix sort cannot finish the job: the tile sets the "out of
+// order" flag at once and leaves its values, and the full LSD sort after
+// the emit starts over from the unsorted values.  window_seam_tile then
+// handles the run crossing seam (t+1)*TILE, if any.
 
 constexpr uint32_t kRunLimit = 256;
 
@@ -379,7 +381,7 @@ __device__ __forceinline__ uint32_t prefix_of(const typename T::K &k, const int 
 }
 
 template <class T>
-__device__ void window_sort_tile(const ColDesc &C, int round, uint32_t t, char *smem) {
+__device__ void window_sort_tile(const ColDesc &C, uint32_t t, char *smem) {
     typedef typename T::K K;
     constexpr int ITEMS = SortCfg<T>::kItems;
     constexpr int TILE = sort_tile<T>();
@@ -387,7 +389,7 @@ __device__ void window_sort_tile(const ColDesc &C, int round, uint32_t t, char *
     DownSmem<T> &S = *reinterpret_cast<DownSmem<T> *>(smem);
     uint64_t *heads = reinterpret_cast<uint64_t *>(&S.wcnt[0][0]);  // NW words, counting path only
     const uint64_t n = sort_n(C);
-    const uint64_t b0 = (uint64_t)t * TILE + (round ? TILE / 2 : 0);
+    const uint64_t b0 = (uint64_t)t * TILE;
     if (b0 >= n) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - b0);
     int pp[kPrefixSlots];
@@ -457,6 +459,71 @@ __device__ void window_sort_tile(const ColDesc &C, int round, uint32_t t, char *
         if (i < tn && npos[j] != i) {
             T::store(C.keys1, b0 + npos[j], S.keys[i]);
             C.vals1[b0 + npos[j]] = S.vals[i];
+        }
+    }
+}
+
+// The run of equal prefix crossing seam B = (t+1)*TILE, after every tile is
+// sorted.  Values [B - kRunLimit - 1, B + kRunLimit + 1) are read: a run no
+// longer than kRunLimit lies inside them and is ranked as a whole (its two
+// sides were sorted separately); a longer run (it may leave the range,
+// which then holds more than kRunLimit + 1 of its values) is in order iff
+// the pair across the seam is, since each side is ordered or already
+// flagged.  Seams are at least 1536 values apart, so the ranges of two
+// seams never overlap.
+template <class T>
+__device__ void window_seam_tile(const ColDesc &C, uint32_t t, char *smem) {
+    typedef typename T::K K;
+    constexpr int TILE = sort_tile<T>();
+    static_assert(TILE >= 2 * (int)(kRunLimit + 1), "seam ranges must not overlap");
+    DownSmem<T> &S = *reinterpret_cast<DownSmem<T> *>(smem);
+    const uint64_t n = sort_n(C);
+    const uint64_t B = (uint64_t)(t + 1) * TILE;
+    if (B >= n) return;  // no seam inside the values
+    int pp[kPrefixSlots];
+#pragma unroll
+    for (int s = 0; s < kPrefixSlots; s++) pp[s] = (int)C.sflags[kSfPrefix + s] - 1;
+    if (pp[kPrefixSlots - 1] < 0) return;  // no digit varies: every value is the same
+    const uint64_t lo = B - (kRunLimit + 1);  // B >= TILE > kRunLimit + 1
+    const uint32_t m = (uint32_t)(min<uint64_t>(n, B + kRunLimit + 1) - lo);
+    const uint32_t sb = kRunLimit + 1;  // index of B in the range
+    if (threadIdx.x == 0) {
+        S.tmp[0] = 0;  // run start: one past the last differing value before the seam
+        S.tmp[1] = m;  // run end: the first differing value after it
+    }
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+        S.keys[i] = T::load(C.keys1, lo + i);
+        S.vals[i] = C.vals1[lo + i];
+    }
+    __syncthreads();
+    const uint32_t pre = prefix_of<T>(S.keys[sb - 1], pp);
+    if (prefix_of<T>(S.keys[sb], pp) != pre) return;  // no run crosses the seam (uniform)
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+        if (prefix_of<T>(S.keys[i], pp) != pre) {
+            if (i < sb)
+                atomicMax(&S.tmp[0], i + 1);
+            else
+                atomicMin(&S.tmp[1], i);
+        }
+    }
+    __syncthreads();
+    const uint32_t s = S.tmp[0], e = S.tmp[1];
+    if (e - s - 1 > kRunLimit) {
+        // long run: its sides are ordered; check the pair across the seam
+        if (threadIdx.x == 0 && T::lt(T::norm(S.keys[sb]), T::norm(S.keys[sb - 1])))
+            C.sflags[kSfUnsorted] = 1u;
+        return;
+    }
+    for (uint32_t i = s + threadIdx.x; i < e; i += kBlock) {
+        const K k = S.keys[i];
+        const typename T::N kn = T::norm(k);
+        uint32_t rank = 0;
+        for (uint32_t q = s; q < i; q++) rank += T::le(T::norm(S.keys[q]), kn) ? 1u : 0u;
+        for (uint32_t q = i + 1; q < e; q++) rank += T::lt(T::norm(S.keys[q]), kn) ? 1u : 0u;
+        const uint32_t np = s + rank;
+        if (np != i) {
+            T::store(C.keys1, lo + np, k);
+            C.vals1[lo + np] = S.vals[i];
         }
     }
 }

@@ -340,6 +340,51 @@ def test_prefix_sort_fallback_hash_route():
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+def _seam_delta(rng, vtype, long_runs):
+    """256 runs of values sharing their leading byte (the run number), the
+    rest random, shuffled: with a prefix-run target of 1024 the prefix sort
+    takes the leading byte alone, so after it the runs lie end to end and
+    many cross a tile seam.  Runs hold 200-256 values (short enough to be
+    ranked whole), or, with long_runs, every other run is one value repeated
+    300-700 times (long, and in order however it lands)."""
+    parts = []
+    for r in range(256):
+        if long_runs and r % 2 == 0:
+            one = gen.random_values(rng, vtype, 1)
+            ln = int(rng.integers(300, 701))
+            v = np.repeat(one, ln, axis=0)
+        else:
+            v = gen.random_values(rng, vtype, int(rng.integers(200, 257)))
+        if vtype == "str16":
+            v = v.copy()
+            v[:, 0] = r
+        elif vtype == "u32":
+            v = (v & np.uint32(0x00FFFFFF)) | (np.uint32(r) << np.uint32(24))
+        else:
+            v = (v & np.uint64(0x00FFFFFFFFFFFFFF)) | (np.uint64(r) << np.uint64(56))
+        parts.append(v)
+    d = np.concatenate(parts)
+    return d[rng.permutation(d.shape[0])]
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+@pytest.mark.parametrize("long_runs", [False, True])
+def test_runs_across_tile_seams(vtype, long_runs):
+    """Runs of equal prefix that cross tile seams after the prefix sort: the
+    seam round ranks the short ones whole and checks the long ones across
+    the seam."""
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(prefix_run=1024)
+    rng = np.random.default_rng(600 + 2 * ("u32", "u64", "str16").index(vtype) + long_runs)
+    base = gen.random_column(rng, vtype, 4000, 30_000, 0)
+    col = gen.Column(vtype, base.u_m, base.main_packed, base.n_main, base.w,
+                     _seam_delta(rng, vtype, long_runs))
+    say(f"case seams {vtype} long_runs={long_runs} nd={col.n_delta}")
+    out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=True, ctx=ctx)
+    torch.cuda.synchronize()
+    assert_same(out.fetch(), ora_merge(col))
+
+
 @pytest.mark.parametrize("codes,run", [(1024, 4), (4096, 1024), (1024, 64)])
 def test_launch_shapes_do_not_change_results(codes, run):
     """Every re-encode tile size and prefix-run target gives the same bytes."""
