@@ -328,6 +328,27 @@ __device__ inline uint64_t lookback_block(uint64_t *status, uint32_t tile, uint6
     return lookback_resolve(status, tile, agg, err, s_u64, s_i32);
 }
 
+// Move n (<= SLOTS * kBlock) elements: element x = load(x) goes to
+// store(x, value).  Every load of a thread is issued before its first
+// store, so the loads are in flight together; a strided load-then-store
+// loop would wait for each load in turn (the compiler keeps the order
+// because the store may alias the next load).
+template <int SLOTS, class LoadF, class StoreF>
+__device__ __forceinline__ void stage_all(uint32_t n, LoadF load, StoreF store) {
+    typedef decltype(load(0u)) V;
+    V r[SLOTS];
+#pragma unroll
+    for (int j = 0; j < SLOTS; j++) {
+        const uint32_t x = j * kBlock + threadIdx.x;
+        if (x < n) r[j] = load(x);
+    }
+#pragma unroll
+    for (int j = 0; j < SLOTS; j++) {
+        const uint32_t x = j * kBlock + threadIdx.x;
+        if (x < n) store(x, r[j]);
+    }
+}
+
 // Code width for a dictionary of n entries: ceil(log2 n), at least 1.
 __device__ __host__ inline uint32_t code_width(uint64_t n) {
     uint32_t w = 1;

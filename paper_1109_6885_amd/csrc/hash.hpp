@@ -90,7 +90,9 @@ __device__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
     if (r0 >= C.nd) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(kHashTile, C.nd - r0);
     for (uint32_t i = threadIdx.x; i < (uint32_t)kLocalSlots; i += kBlock) S.slot[i] = 0;
-    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) S.keys[i] = T::load(C.delta, r0 + i);
+    stage_all<kHashItems>(
+        tn, [&](uint32_t x) { return T::load(C.delta, r0 + x); },
+        [&](uint32_t x, const K &k) { S.keys[x] = k; });
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
         const K key = S.keys[i];
@@ -148,12 +150,16 @@ __device__ void compact_tile(const ColDesc &C, char *smem) {
     const uint64_t pre = lookback_block(C.hstatus, t, tot, C.err, S.lb64, S.lb32);
     uint64_t pos = base + pre + ex;
     bool full = false;
+    typename T::K kv[kCompactItems];
+#pragma unroll
+    for (int j = 0; j < kCompactItems; j++)  // the representatives' values, all loads first
+        if ((flags >> j) & 1u) kv[j] = T::load(C.delta, r0 + j);
 #pragma unroll
     for (int j = 0; j < kCompactItems; j++) {
         if ((flags >> j) & 1u) {
             const uint64_t row = r0 + j;
             if (pos < C.nd_max) {  // the distinct list's capacity
-                T::store(C.dkeys, pos, T::load(C.delta, row));
+                T::store(C.dkeys, pos, kv[j]);
                 C.dindex[row] = (uint32_t)pos;
             } else {
                 full = true;
@@ -176,16 +182,27 @@ __device__ void emit_distinct_tile(const ColDesc &C, uint64_t t, bool again) {
     const uint32_t *rows = C.vals1;
     const uint64_t n = sort_n(C);
     bool bad = false, unsorted = false;
-    for (uint32_t x = threadIdx.x; x < (uint32_t)kEmitTile; x += kBlock) {
-        const uint64_t i = t * kEmitTile + x;
+    typedef typename T::K K;
+    K k[kEmitItems], kp[kEmitItems];
+    uint32_t d[kEmitItems];
+#pragma unroll
+    for (int j = 0; j < kEmitItems; j++) {  // every load first
+        const uint64_t i = t * kEmitTile + (uint64_t)j * kBlock + threadIdx.x;
+        if (i < n) {
+            k[j] = T::load(keys, i);
+            kp[j] = i > 0 ? T::load(keys, i - 1) : K{};
+            d[j] = rows[i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kEmitItems; j++) {
+        const uint64_t i = t * kEmitTile + (uint64_t)j * kBlock + threadIdx.x;
         if (i >= n) break;
-        const typename T::K k = T::load(keys, i);
         // distinct values: strictly increasing
-        if (i > 0 && !T::lt(T::norm(T::load(keys, i - 1)), T::norm(k))) unsorted = true;
-        T::store(C.u_d, i, k);
-        const uint32_t d = rows[i];
-        if (d < n)
-            C.drankd[d] = (uint32_t)i;
+        if (i > 0 && !T::lt(T::norm(kp[j]), T::norm(k[j]))) unsorted = true;
+        T::store(C.u_d, i, k[j]);
+        if (d[j] < n)
+            C.drankd[d[j]] = (uint32_t)i;
         else
             bad = true;
     }
@@ -197,17 +214,26 @@ __device__ void emit_distinct_tile(const ColDesc &C, uint64_t t, bool again) {
 __device__ inline void rank_rows_tile(const ColDesc &C, uint64_t t) {
     const uint64_t n = sort_n(C);
     bool bad = false;
+    // three rounds of gathers (representative, its distinct position, that
+    // position's rank), each with all of the thread's loads in flight
+    uint32_t v[kHashItems];
+#pragma unroll
     for (int j = 0; j < kHashItems; j++) {
         const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
-        if (row >= C.nd) break;
-        const uint32_t r = C.rep[row];
-        const uint32_t d = r < C.nd ? C.dindex[r] : 0xffffffffu;
-        if (d < n) {
-            C.drank[row] = C.drankd[d];
-        } else {
-            C.drank[row] = 0;
-            bad = true;
-        }
+        v[j] = row < C.nd ? C.rep[row] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) v[j] = v[j] < C.nd ? C.dindex[v[j]] : 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) {
+        const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+        if (row < C.nd && v[j] >= n) bad = true;
+        v[j] = v[j] < n ? C.drankd[v[j]] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) {
+        const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+        if (row < C.nd) C.drank[row] = v[j];
     }
     if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
 }

@@ -171,14 +171,22 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     if (!order_ok && threadIdx.x == 0) flag_error(C.err, MC_DEVERR_ORDER);
     const uint64_t j0 = k0 - i0, j1 = order_ok ? k1 - i1 : j0;
     const uint32_t na = order_ok ? (uint32_t)(i1 - i0) : 0u, nb = (uint32_t)(j1 - j0);
-    for (uint32_t x = threadIdx.x; x <= na; x += kBlock) {
-        if (x == 0) {
-            if (i0 > 0) S.a[0] = gA(i0 - 1);
-        } else {
-            S.a[x] = gA(i0 + x - 1);
-        }
-    }
-    for (uint32_t x = threadIdx.x; x < nb; x += kBlock) S.b[x] = gB(j0 + x);
+    // stage S.a[0] = U_M[i0 - 1] (if any), S.a[1 + x] = U_M[i0 + x] and
+    // S.b[x] = U_D[j0 + x] as one range of na + 1 + nb loads
+    typedef typename T::N N;
+    constexpr int kStageSlots = (merge_tile<T>() + 1 + kBlock - 1) / kBlock;
+    stage_all<kStageSlots>(
+        na + 1 + nb,
+        [&](uint32_t q) -> N {
+            if (q <= na) return (q > 0 || i0 > 0) ? gA(i0 + q - 1) : N{};
+            return gB(j0 + (q - na - 1));
+        },
+        [&](uint32_t q, const N &v) {
+            if (q <= na)
+                S.a[q] = v;
+            else
+                S.b[q - na - 1] = v;
+        });
     __syncthreads();
 
     // this thread's slice of the tile's merged range

@@ -128,12 +128,23 @@ __device__ void hist_tile(const ColDesc &C, uint32_t blk, char *smem) {
     __syncthreads();
     const uint64_t b0 = (uint64_t)blk * kHistChunk;
     const uint64_t n = sort_n(C);
-    for (uint32_t j = threadIdx.x; j < kHistChunk; j += kBlock) {
-        const uint64_t i = b0 + j;
-        if (i < n) {
-            typename T::K k = T::load(C.sort_src, i);
+    // eight loads in flight per thread, then their counts
+    constexpr int kBatch = 8;
+    static_assert(kHistChunk % (kBatch * kBlock) == 0, "whole batches");
+    for (int h = 0; h < kHistChunk / kBlock; h += kBatch) {
+        typename T::K k[kBatch];
 #pragma unroll
-            for (int p = 0; p < P; p++) atomicAdd(&S.h[p * 256 + T::digit(k, p)], 1u);
+        for (int q = 0; q < kBatch; q++) {
+            const uint64_t i = b0 + (uint64_t)(h + q) * kBlock + threadIdx.x;
+            if (i < n) k[q] = T::load(C.sort_src, i);
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; q++) {
+            const uint64_t i = b0 + (uint64_t)(h + q) * kBlock + threadIdx.x;
+            if (i < n) {
+#pragma unroll
+                for (int p = 0; p < P; p++) atomicAdd(&S.h[p * 256 + T::digit(k[q], p)], 1u);
+            }
         }
     }
     __syncthreads();
@@ -193,10 +204,16 @@ __device__ void sort_up_tile(const ColDesc &C, const PassIO &io, uint32_t t, cha
     const uint64_t b0 = (uint64_t)t * TILE;
     const void *src = io.src;
     const uint64_t n = sort_n(C);
-#pragma unroll 4
+    uint32_t dg[SortCfg<T>::kItems];
+#pragma unroll
+    for (int j = 0; j < SortCfg<T>::kItems; j++) {  // every load first
+        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
+        dg[j] = i < n ? T::digit(T::load(src, i), p) : 0u;
+    }
+#pragma unroll
     for (int j = 0; j < SortCfg<T>::kItems; j++) {
         const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[T::digit(T::load(src, i), p)], 1u);
+        if (i < n) atomicAdd(&h[dg[j]], 1u);
     }
     __syncthreads();
     C.tcount[(uint64_t)threadIdx.x * C.sort_tiles + t] = h[threadIdx.x];
@@ -397,10 +414,16 @@ __device__ void window_sort_tile(const ColDesc &C, uint32_t t, char *smem) {
     for (int s = 0; s < kPrefixSlots; s++) pp[s] = (int)C.sflags[kSfPrefix + s] - 1;
     if (pp[kPrefixSlots - 1] < 0) return;  // no digit varies: every value is the same
     if (threadIdx.x == 0) S.tmp[0] = 0;  // "a long run is out of order"
-    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
-        S.keys[i] = T::load(C.keys1, b0 + i);
-        S.vals[i] = C.vals1[b0 + i];
-    }
+    struct KV {
+        K k;
+        uint32_t v;
+    };
+    stage_all<ITEMS>(
+        tn, [&](uint32_t x) { return KV{T::load(C.keys1, b0 + x), C.vals1[b0 + x]}; },
+        [&](uint32_t x, const KV &e) {
+            S.keys[x] = e.k;
+            S.vals[x] = e.v;
+        });
     __syncthreads();
     // run heads: bit i set where a run of equal prefix starts (positions past
     // the window count as heads, so every run ends inside the mask)
@@ -491,10 +514,17 @@ __device__ void window_seam_tile(const ColDesc &C, uint32_t t, char *smem) {
         S.tmp[0] = 0;  // run start: one past the last differing value before the seam
         S.tmp[1] = m;  // run end: the first differing value after it
     }
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
-        S.keys[i] = T::load(C.keys1, lo + i);
-        S.vals[i] = C.vals1[lo + i];
-    }
+    struct KV {
+        K k;
+        uint32_t v;
+    };
+    constexpr int kSeamSlots = (2 * (kRunLimit + 1) + kBlock - 1) / kBlock;
+    stage_all<kSeamSlots>(
+        m, [&](uint32_t x) { return KV{T::load(C.keys1, lo + x), C.vals1[lo + x]}; },
+        [&](uint32_t x, const KV &e) {
+            S.keys[x] = e.k;
+            S.vals[x] = e.v;
+        });
     __syncthreads();
     const uint32_t pre = prefix_of<T>(S.keys[sb - 1], pp);
     if (prefix_of<T>(S.keys[sb], pp) != pre) return;  // no run crosses the seam (uniform)
@@ -558,11 +588,17 @@ __device__ void emit_tile(const ColDesc &C, char *smem, bool again) {
     __syncthreads();
     const uint32_t t = S.tile;
     const uint64_t tb = (uint64_t)t * kEmitTile;
-    // coalesced staging of the tile (and its predecessor value) in LDS
-    for (uint32_t x = threadIdx.x; x <= (uint32_t)kEmitTile; x += kBlock) {
-        const uint64_t i = tb + x;  // LDS slot x holds sorted position i - 1
-        if (i >= 1 && i - 1 < C.nd) S.keys[x] = T::load(keys, i - 1);
-    }
+    // coalesced staging of the tile (and its predecessor value) in LDS: slot
+    // x holds sorted position tb + x - 1 (zero where there is none; such
+    // slots are never compared)
+    constexpr int kStageSlots = (kEmitTile + 1 + kBlock - 1) / kBlock;
+    stage_all<kStageSlots>(
+        kEmitTile + 1,
+        [&](uint32_t x) {
+            const uint64_t i = tb + x;
+            return (i >= 1 && i - 1 < C.nd) ? T::load(keys, i - 1) : K{};
+        },
+        [&](uint32_t x, const K &k) { S.keys[x] = k; });
     __syncthreads();
     const uint64_t i0 = tb + (uint64_t)threadIdx.x * kEmitItems;
     const uint32_t l0 = threadIdx.x * kEmitItems;
@@ -598,12 +634,15 @@ __device__ void emit_tile(const ColDesc &C, char *smem, bool again) {
     }
     uint64_t idx = tile_prefix + ex;  // heads seen so far, over the whole array
     bool bad = false;
+    uint32_t rowv[kEmitItems];
+#pragma unroll
+    for (int j = 0; j < kEmitItems; j++) rowv[j] = i0 + j < C.nd ? rows[i0 + j] : 0u;
 #pragma unroll
     for (int j = 0; j < kEmitItems; j++) {
         const uint64_t i = i0 + j;
         if (i < C.nd) {
             if ((head >> j) & 1u) idx++;
-            const uint32_t row = rows[i];
+            const uint32_t row = rowv[j];
             if (row < C.nd && idx - 1 < C.nd)
                 C.drank[row] = (uint32_t)(idx - 1);
             else
