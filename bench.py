@@ -724,7 +724,14 @@ def main():
         "roofline": {"kernel": "k_repack (Step 2(b))", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.config == 2 else None,
-                     "bytes_per_launch": b_re},
+                     "bytes_per_launch": b_re,
+                     # the kernel's real limit: one random translation-table
+                     # read per row; the plain gather reference does the same
+                     # number of reads from a table of the same size
+                     "gather_ceiling": {"reference_lookups": col.n_main,
+                                        "reference_us": gather_us[2],
+                                        "kernel_us": re_ms * 1000.0,
+                                        "frac": gather_us[2] / (re_ms * 1000.0)}},
         "copy_kernel_gbs": copy_gbs,
         "gather_ref_us": {"rows": col.n_main, "table_entries": int(col.u_m.shape[0]),
                           "u32_table": gather_us[4], "u16_table": gather_us[2],

@@ -158,15 +158,26 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
     uint32_t *ndig = tmp + kWaves;  // distinct digits per position
     const uint64_t n = sort_n(C);
-    for (int p = 0; p < P; p++) {
-        const uint32_t v = C.gh[p * 256 + threadIdx.x];
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, tmp, &tot);
-        C.base[p * 256 + threadIdx.x] = ex;
-        if (v == n) C.trivial[p] = 1u;
-        uint32_t nz;
-        block_excl_scan(v ? 1u : 0u, tmp, &nz);
-        if (threadIdx.x == 0) ndig[p] = nz;
+    // one wave per digit position at a time, lane l holding digits 4l..4l+3:
+    // a wave scan and no block barrier per position
+    const int lane = lane_id();
+    for (int p = wave_id(); p < P; p += kWaves) {
+        uint32_t v[4], run = 0, nz = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            v[q] = C.gh[p * 256 + 4 * lane + q];
+            run += v[q];
+            nz += v[q] ? 1u : 0u;
+            if (v[q] == n) C.trivial[p] = 1u;
+        }
+        uint32_t ex = wave_incl_scan(run) - run;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            C.base[p * 256 + 4 * lane + q] = ex;
+            ex += v[q];
+        }
+        nz = wave_sum(nz);
+        if (lane == 0) ndig[p] = nz;
     }
     __syncthreads();  // the flags above, written by other threads of the block
     if (threadIdx.x == 0) {
