@@ -53,6 +53,20 @@ def measured_traffic():
     return nbytes if src == reencode_source_hash() else None
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host the CPU legs run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -613,6 +627,18 @@ def main():
     ctx.set_timing(False)
     torch.cuda.synchronize()
 
+    # and once more with an event pair around every merge: the spread
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in evs)
+    dist = {"median": per[len(per) // 2], "min": per[0],
+            "p90": per[min(len(per) - 1, int(0.9 * len(per)))], "n": len(per)}
+
     # achievable streaming bandwidth: the library's plain 128-bit copy of
     # 1 GiB (2 GiB moved per copy), timed with events on the same stream
     copy_bytes = 1 << 30
@@ -673,7 +699,7 @@ def main():
         assert ref["n_new"] == sc["n_new"]
         cpu = {"value": n_out / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
                "sample": "the whole 101M-tuple column, one serial run of the C oracle "
-                         f"({dt:.1f} s)"}
+                         f"({dt:.1f} s)", "host": host_cpu()}
 
     cpu_par = None
     if not args.no_cpu:
@@ -696,7 +722,8 @@ def main():
         cpu_par = {"value": n_out / dt, "unit": "tuples/s", "threads": threads,
                    "kind": "multi-threaded C++ (Section 6.2 scheme)", "ms": dt * 1000.0,
                    "gpu_speedup": (dt * 1000.0) / ms_per_step,
-                   "sample": "the whole column, best of two calls after a warm-up call"}
+                   "sample": "the whole column, best of two calls after a warm-up call",
+                   "host": host_cpu()}
         del o, r
 
     line = {
@@ -719,6 +746,7 @@ def main():
         "hbm_gbs_alg": b_alg / (ms_per_step / 1000.0) / 1e9,
         "hbm_frac_alg": b_alg / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS,
         "bytes_alg": b_alg,
+        "merge_ms_dist": dist,
         "step_ms": {"clear+sort": steps_ms[0], "emit": steps_ms[1], "merge_dict": steps_ms[2],
                     "reencode": steps_ms[3], "whole": steps_ms[4]},
         "roofline": {"kernel": "k_repack (Step 2(b))", "bound": "hbm", "achieved": achieved,

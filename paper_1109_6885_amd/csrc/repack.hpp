@@ -109,18 +109,20 @@ __device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint3
     const uint64_t wres = (n_out * wn + 63) / 64;
     const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
     const uint32_t nwo = (CODES / 64) * wn;  // words of a full tile (even)
-    // floor(x / wn) for x < CODES * 32 <= 2^17 as a multiply-high by
-    // ceil(2^32 / wn): the reciprocal's rounding error adds less than
-    // x / 2^32 <= 2^-15 < 1 / wn to the quotient, so the floor is exact
-    const uint32_t rcp = (uint32_t)((0x100000000ull + wn - 1) / wn);
+    // floor(x / wn) for x < CODES * 32 <= 2^17 as (x * ceil(2^32 / wn)) >> 32:
+    // the reciprocal's rounding error adds less than x / 2^32 <= 2^-15 < 1 / wn
+    // to the quotient, so the floor is exact.  The reciprocal is 64-bit: for
+    // wn = 1 it is 2^32 itself.
+    const uint64_t rcp = (0x100000000ull + wn - 1) / wn;
     for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
         uint64_t word[2];
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const uint32_t k = 2 * k2 + h;
             const uint32_t b0 = 64u * k;
-            uint32_t q = __umulhi(b0, rcp);
-            const uint32_t qe = min<uint32_t>(__umulhi(b0 + 63, rcp), CODES - 1);
+            uint32_t q = (uint32_t)(((uint64_t)b0 * rcp) >> 32);
+            const uint32_t qe =
+                min<uint32_t>((uint32_t)(((uint64_t)(b0 + 63) * rcp) >> 32), CODES - 1);
             uint64_t acc = 0;
             for (; q <= qe; q++) {
                 const uint64_t c = s_code[q];

@@ -3,9 +3,12 @@ byte for byte: random shapes and value types, 1 to 8 threads (more threads
 than rows included), empty main / delta, heavy duplicates, a bad code."""
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 
 import cpu_parallel
 import oracle
+from test_oracle import tiny_columns
 from workloads import gen
 
 
@@ -68,3 +71,11 @@ def test_reused_outputs():
     with pytest.raises(cpu_parallel.CpuMergeError):
         cpu_parallel.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w,
                                   col.delta, 2, outputs=small)
+
+
+@settings(max_examples=200, deadline=None, suppress_health_check=list(HealthCheck))
+@given(tiny_columns(), st.integers(1, 9))
+def test_hypothesis_tiny_columns(col, threads):
+    """The oracle's brute-force strategy at 1 to 9 threads (often more threads
+    than rows or dictionary entries)."""
+    check(col, threads)

@@ -10,8 +10,11 @@ import numpy as np
 import pytest
 import torch
 
+from hypothesis import HealthCheck, Phase, given, settings
+
 import oracle
 import paper_1109_6885_amd as cm
+from test_oracle import tiny_columns
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
@@ -53,6 +56,74 @@ SHAPES = [
     (3, 100_000, 0, 0.0), (20_000, 9_000, 100_000, 0.1), (100_000, 1, 1, 1.0),
     (60_000, 250_000, 33_333, 0.95),
 ]
+
+
+@settings(max_examples=150, deadline=None, derandomize=True, database=None,
+          phases=[Phase.explicit, Phase.generate],
+          suppress_health_check=list(HealthCheck))
+@given(tiny_columns())
+def test_hypothesis_tiny_columns(col):
+    """The oracle's brute-force strategy (tiny dictionaries, many collisions,
+    empty parts, codes stored wider than needed, u64 values with the top bit
+    set) through the GPU: generated deterministically and never shrunk, so a
+    failing case runs once."""
+    say(f"case hypothesis {col.vtype} n_um={col.u_m.shape[0]} n_main={col.n_main} "
+        f"nd={col.n_delta} w={col.w}")
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
+def _two_entry_columns(rng, vtype):
+    """Columns whose merged dictionary has exactly two entries (w' = 1, codes
+    0 and 1 mixed): two main entries and no delta; one main entry and one new
+    delta value; no main and two delta values; a wide stored main width."""
+    vals = np.sort(gen.random_values(rng, vtype, 2), axis=0)
+    if vtype == "str16":
+        vals = np.unique(vals, axis=0)
+    a, b = vals[:1], vals[1:2]
+    n = 5_000
+    cols = []
+    codes = rng.integers(0, 2, n)
+    cols.append(gen.Column(vtype, vals, gen.pack_codes(codes, 1), n, 1, vals[:0]))
+    pick = rng.integers(0, 2, 3_001)
+    delta = np.where(pick[:, None] == 0, a, b) if vtype == "str16" else np.where(pick == 0, a[0], b[0])
+    cols.append(gen.Column(vtype, a, gen.pack_codes(np.zeros(n, np.uint64), 1), n, 1, delta))
+    cols.append(gen.Column(vtype, vals[:0], gen.pack_codes(np.zeros(0), 3), 0, 3, delta))
+    cols.append(gen.Column(vtype, vals, gen.pack_codes(codes, 9), n, 9, delta[:70]))
+    return cols
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+def test_two_entry_dictionary(vtype):
+    """|U'| = 2 gives one-bit output codes: every output word holds 64
+    codes, both values occur (the plain, naive and batched re-encodes)."""
+    rng = np.random.default_rng(77 + ("u32", "u64", "str16").index(vtype))
+    cols = _two_entry_columns(rng, vtype)
+    for i, col in enumerate(cols):
+        say(f"case two-entry dictionary {vtype} #{i} n_um={col.u_m.shape[0]} nd={col.n_delta}")
+        ref = ora_merge(col)
+        assert ref["w_new"] == 1 and ref["n_new"] == 2
+        assert_same(gpu_merge(col), ref)
+        out = cm.merge_column_naive(cm.ColumnInput.from_numpy(col))
+        torch.cuda.synchronize()
+        got = out.fetch()
+        assert np.array_equal(got["codes"], ref["codes"])
+    say(f"case two-entry dictionary {vtype}, batched")
+    outs, _ = cm.merge_columns_batched([cm.ColumnInput.from_numpy(c) for c in cols])
+    torch.cuda.synchronize()
+    for col, o in zip(cols, outs):
+        assert_same(o.fetch(), ora_merge(col))
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+def test_everything_empty(vtype):
+    """No dictionary, no main rows, no delta rows: U' is empty, w' = 1, no
+    result words."""
+    rng = np.random.default_rng(3)
+    col = gen.random_column(rng, vtype, 0, 0, 0, 0.0)
+    say(f"case everything empty {vtype}")
+    got, ref = gpu_merge(col), ora_merge(col)
+    assert_same(got, ref)
+    assert got["n_new"] == 0 and got["w_new"] == 1 and got["words"] == 0
 
 
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
