@@ -7,8 +7,12 @@ import numpy as np
 import pytest
 import torch
 
+from hypothesis import HealthCheck, Phase, given, settings
+from hypothesis import strategies as st
+
 import oracle
 import paper_1109_6885_amd as cm
+from test_oracle import tiny_columns
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
@@ -220,3 +224,19 @@ def test_batched_forced_hash_route():
     torch.cuda.synchronize()
     for a, b in zip(outs, plain):
         assert np.array_equal(a.fetch()["codes"], b.fetch()["codes"])
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          phases=[Phase.explicit, Phase.generate], suppress_health_check=list(HealthCheck))
+@given(st.lists(tiny_columns(), min_size=1, max_size=10))
+def test_hypothesis_batches(cols):
+    """Batches of 1 to 10 columns from the oracle's hypothesis strategy
+    (columns with nothing to sort, merge or re-encode give zero tiles in
+    some phases), generated deterministically and never shrunk."""
+    say(f"case hypothesis batch of {len(cols)}: "
+        + ", ".join(f"{c.vtype}/{c.u_m.shape[0]}/{c.n_main}/{c.n_delta}" for c in cols))
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, _ = cm.merge_columns_batched(dcols)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())

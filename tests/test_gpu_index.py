@@ -7,8 +7,12 @@ import numpy as np
 import pytest
 import torch
 
+from hypothesis import HealthCheck, Phase, given, settings
+from hypothesis import strategies as st
+
 import oracle
 import paper_1109_6885_amd as cm
+from test_oracle import tiny_columns
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
@@ -81,3 +85,28 @@ def test_index_append_rejects_overflow():
     ix.append(delta, 60)
     with pytest.raises(cm.ColmergeError):
         ix.append(delta, 41)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          phases=[Phase.explicit, Phase.generate], suppress_health_check=list(HealthCheck))
+@given(tiny_columns(), st.lists(st.integers(1, 25), min_size=1, max_size=8))
+def test_hypothesis_indexed(col, cuts):
+    """Tiny columns from the oracle's hypothesis strategy with the delta
+    appended to an index in batches of 1 to 25 rows (the last batch takes
+    the rest), generated deterministically and never shrunk."""
+    dcol = cm.ColumnInput.from_numpy(col)
+    ix = cm.DeltaIndex(col.vtype, max(col.n_delta, 1))
+    done = 0
+    for b in cuts:
+        b = min(b, col.n_delta - done)
+        if b <= 0:
+            break
+        ix.append(dcol.delta, b)
+        done += b
+    if done < col.n_delta:
+        ix.append(dcol.delta, col.n_delta - done)
+    say(f"case hypothesis indexed {col.vtype} n_um={col.u_m.shape[0]} nd={col.n_delta} "
+        f"batches={cuts}")
+    out = cm.merge_column_indexed(dcol, ix, tables=True)
+    torch.cuda.synchronize()
+    same(out.fetch(), ora(col))

@@ -69,7 +69,12 @@ def test_hypothesis_tiny_columns(col):
     failing case runs once."""
     say(f"case hypothesis {col.vtype} n_um={col.u_m.shape[0]} n_main={col.n_main} "
         f"nd={col.n_delta} w={col.w}")
-    assert_same(gpu_merge(col), ora_merge(col))
+    ref = ora_merge(col)
+    assert_same(gpu_merge(col), ref)
+    out = cm.merge_column_naive(cm.ColumnInput.from_numpy(col))
+    torch.cuda.synchronize()
+    got = out.fetch()
+    assert got["error"] == 0 and np.array_equal(got["codes"], ref["codes"])
 
 
 def _two_entry_columns(rng, vtype):
