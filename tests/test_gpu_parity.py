@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from hypothesis import HealthCheck, Phase, given, settings
+from hypothesis import strategies as st
 
 import oracle
 import paper_1109_6885_amd as cm
@@ -95,6 +96,56 @@ def _two_entry_columns(rng, vtype):
     cols.append(gen.Column(vtype, vals[:0], gen.pack_codes(np.zeros(0), 3), 0, 3, delta))
     cols.append(gen.Column(vtype, vals, gen.pack_codes(codes, 9), n, 9, delta[:70]))
     return cols
+
+
+@st.composite
+def structured_columns(draw):
+    """Deltas whose values share their leading byte in 1 to 256 groups, with
+    1 to 1000 copies of each distinct value, U_M holding some of them, a
+    prefix-run target from 4 to 1024 (how many prefix digits the sort takes)
+    and the hashing route on or off: runs of equal prefix of every length,
+    across tile seams, ordered or not."""
+    vtype = draw(st.sampled_from(["u32", "u64", "str16"]))
+    rng = np.random.default_rng(draw(st.integers(0, 2 ** 32 - 1)))
+    nd = draw(st.integers(1, 20_000))
+    groups = draw(st.integers(1, 256))
+    copies = draw(st.sampled_from([1, 2, 50, 1000]))
+    run = draw(st.sampled_from([4, 16, 32, 256, 1024]))
+    hashed = draw(st.booleans())
+    ndist = max(1, nd // copies)
+    vals = gen.random_values(rng, vtype, ndist)
+    lead = rng.integers(0, groups, ndist)
+    if vtype == "str16":
+        vals = vals.copy()
+        vals[:, 0] = lead
+    elif vtype == "u32":
+        vals = (vals & np.uint32(0x00FFFFFF)) | (lead.astype(np.uint32) << np.uint32(24))
+    else:
+        vals = (vals & np.uint64((1 << 56) - 1)) | (lead.astype(np.uint64) << np.uint64(56))
+    delta = vals[rng.integers(0, ndist, nd)]
+    k_old = draw(st.integers(0, min(ndist, 2000)))
+    um = np.concatenate([vals[rng.integers(0, ndist, k_old)],
+                         gen.random_values(rng, vtype, draw(st.integers(0, 2000)))])
+    um = np.unique(um, axis=0) if vtype == "str16" else np.unique(um)
+    n_main = draw(st.integers(0, 30_000)) if um.shape[0] else 0
+    w = gen.code_width(max(um.shape[0], 1))
+    codes = rng.integers(0, max(um.shape[0], 1), n_main)
+    col = gen.Column(vtype, um, gen.pack_codes(codes, w), n_main, w, delta)
+    return col, run, hashed
+
+
+@settings(max_examples=60, deadline=None, derandomize=True, database=None,
+          phases=[Phase.explicit, Phase.generate], suppress_health_check=list(HealthCheck))
+@given(structured_columns())
+def test_hypothesis_structured_deltas(case):
+    col, run, hashed = case
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(prefix_run=run, hash_min_rows=1 if hashed else 0)
+    say(f"case structured {col.vtype} n_um={col.u_m.shape[0]} nd={col.n_delta} run={run} "
+        f"hashed={hashed}")
+    out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=True, ctx=ctx)
+    torch.cuda.synchronize()
+    assert_same(out.fetch(), ora_merge(col))
 
 
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
