@@ -119,7 +119,7 @@ struct ColLayout {
     // part Z
     uint64_t counters = 0, sflags = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0,
              emit_status = 0, emit_status2 = 0,
-             merge_status = 0, mbound = 0, dcount = 0, hstatus = 0, htab = 0, z_size = 0;
+             merge_status = 0, mbound = 0, dcount = 0, htab = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
              drank = 0, x_d = 0, x_m = 0, xdev = 0, rep = 0, dindex = 0, dkeys = 0, drankd = 0,
@@ -188,7 +188,6 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     if (L.partitioned) L.mbound = z.take((L.merge_tiles + 1) * 8);
     if (L.hashed && !L.indexed) {
         L.dcount = z.take(8);
-        L.hstatus = z.take(ceil_div(nd, mc::kCompactTile) * 8);
         L.htab = z.take((L.hmask + 1) * 4);
     }
     L.z_size = z.size();
@@ -235,7 +234,6 @@ void set_hash_fields(mc::ColDesc &C, char *za, char *zb, const ColLayout &L) {
     C.dindex = reinterpret_cast<uint32_t *>(zb + L.dindex);
     C.dkeys = zb + L.dkeys;
     C.dcount = reinterpret_cast<uint64_t *>(za + L.dcount);
-    C.hstatus = reinterpret_cast<uint64_t *>(za + L.hstatus);
     C.sort_src = C.dkeys;
     C.sort_n = C.dcount;
 }
@@ -293,16 +291,15 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
 // Delta index (mc_delta_index): the hashing route's table, representatives
 // and distinct list, kept up to date by appends instead of built in a merge.
 // Layout of its workspace:
-//   [0, 64)    u32 counters ([2]: compaction tile ticket of the batch)
-//   64: u64 distinct values listed; 72: u64 the same before this batch;
-//   80: u32 error word
+//   64: u64 distinct values listed; 80: u32 error word (the rest of the
+//   first 128 bytes is unused)
 //   then the table (power of two >= 2 * capacity slots, >= 1024), the
-//   representative and distinct position of every row, the distinct values
-//   and the compaction's prefix words (one per tile of a batch).
+//   representative and distinct position of every row, and the distinct
+//   values.
 // ---------------------------------------------------------------------------
 
 struct IndexLayout {
-    uint64_t scal = 0, htab = 0, rep = 0, dindex = 0, dkeys = 0, hstatus = 0, size = 0;
+    uint64_t scal = 0, htab = 0, rep = 0, dindex = 0, dkeys = 0, size = 0;
     uint64_t hmask = 0;
 };
 
@@ -317,7 +314,6 @@ IndexLayout index_layout(int32_t type, uint64_t cap) {
     X.rep = c.take(cap * 4);
     X.dindex = c.take(cap * 4);
     X.dkeys = c.take(cap * value_len(type));
-    X.hstatus = c.take(ceil_div(cap, mc::kCompactTile) * 8);
     X.size = c.size();
     return X;
 }
@@ -332,7 +328,6 @@ void set_index_fields(mc::ColDesc &C, const mc_delta_index *ix) {
     C.dindex = reinterpret_cast<uint32_t *>(w + X.dindex);
     C.dkeys = w + X.dkeys;
     C.dcount = reinterpret_cast<uint64_t *>(w + X.scal + 64);
-    C.hstatus = reinterpret_cast<uint64_t *>(w + X.hstatus);
     C.sort_src = C.dkeys;
     C.sort_n = C.dcount;
 }
@@ -369,19 +364,6 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, ui
 
 // Plain 128-bit copy: the achievable streaming bandwidth on this GPU, and
 // the kernel of known traffic that calibrates hardware byte counters.
-// Before an index batch: clear the batch's compaction prefix words and tile
-// ticket, and remember how many distinct values are listed already.
-__global__ __launch_bounds__(256) void k_index_prepare(uint64_t *hstatus, uint64_t ntiles,
-                                                       uint32_t *counters, const uint64_t *dcount,
-                                                       uint64_t *dbase) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntiles;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        hstatus[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counters[2] = 0;
-        *dbase = *dcount;
-    }
-}
 // err |= *src (an index's error word into a merge's result)
 __global__ void k_or_word(uint32_t *err, const uint32_t *src) {
     if (threadIdx.x == 0 && *src) atomicOr(err, *src);
@@ -459,7 +441,7 @@ __global__ __launch_bounds__(256) void k1_hash_insert(mc::ColDesc C) {
 template <class T>
 __global__ __launch_bounds__(256) void k1_compact(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::CompactSmem)];
-    mc::compact_tile<T>(C, smem);
+    mc::compact_tile<T>(C, blockIdx.x, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_emit_distinct(mc::ColDesc C, int again) {
@@ -596,7 +578,7 @@ __global__ __launch_bounds__(256) void kn_compact(Batch B) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::CompactSmem)];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::compact_tile, C, smem);
+    MC_DISPATCH(C, mc::compact_tile, C, blockIdx.x - B.map[j], smem);
 }
 __global__ __launch_bounds__(256) void kn_rank_rows(Batch B) {
     const uint32_t j = find_col(B, blockIdx.x);
@@ -1378,14 +1360,8 @@ int mc_delta_index_append(mc_ctx *ctx, const mc_delta_index *ix, const void *del
     C.nd_max = ix->capacity;
     C.hrow0 = row0;
     set_index_fields(C, ix);
-    C.counters = reinterpret_cast<uint32_t *>(w + X.scal);
-    C.dbase = reinterpret_cast<const uint64_t *>(w + X.scal + 72);
     C.err = reinterpret_cast<uint32_t *>(w + X.scal + 80);
     const uint64_t ntiles = ceil_div(rows, mc::kCompactTile);
-    hipLaunchKernelGGL(k_index_prepare, dim3((uint32_t)std::min<uint64_t>(ceil_div(ntiles, 256), 1024)),
-                       dim3(256), 0, s, C.hstatus, ntiles, C.counters, C.dcount,
-                       reinterpret_cast<uint64_t *>(w + X.scal + 72));
-    MC_LAUNCHED("k_index_prepare");
     const dim3 gh((uint32_t)ceil_div(rows, mc::kHashTile)), gc((uint32_t)ntiles), b(mc::kBlock);
     switch (ix->type) {
         case MC_U32:

@@ -237,7 +237,7 @@ struct ColDesc {
     uint32_t *base;            // [passes][256] digit offsets
     uint32_t *trivial;         // [passes] single-digit flags (zeroed)
     uint32_t *tcount;          // [256][sort_tiles] tile counts / offsets
-    uint32_t *counters;        // [1] merge tile counter, [2] compaction tile counter (zeroed)
+    uint32_t *counters;        // [1] merge tile counter (zeroed)
     uint32_t *sflags;          // Step 1(a) words, slots kSf* below (zeroed)
     uint64_t *emit_status;     // emit prefix words (zeroed)
     uint64_t *emit_status2;    // prefix words of the emit after the full LSD sort (zeroed)
@@ -258,12 +258,10 @@ struct ColDesc {
     uint64_t hmask;            // table size - 1 (power of two >= 2 * nd)
     uint32_t *rep;             // representative row of every delta row
     uint32_t *dindex;          // position of a representative in the distinct list
-    void *dkeys;               // distinct values, in row order of their representatives
+    void *dkeys;               // distinct values (tiles of representatives in any order)
     uint32_t *drankd;          // rank in U_D of every distinct value (by distinct position)
-    uint64_t *dcount;          // number of distinct values (zeroed)
-    uint64_t *hstatus;         // prefix words of the compaction (zeroed)
+    uint64_t *dcount;          // number of distinct values listed (zeroed in a merge)
     uint64_t hrow0;            // first delta row of this hashing launch (0 in a merge)
-    const uint64_t *dbase;     // distinct values listed before this batch, or null (0)
 };
 
 // The same prefix with the whole workgroup looking back: each round the 256

@@ -7,9 +7,12 @@
 //                      open-addressing table; the claiming row is the
 //                      value's representative (rep[row] = representative);
 //                      rows first meet their tile's equal values in LDS
-//   compact_tile       representatives, in row order, become the distinct
-//                      list (dkeys) with a cross-tile prefix; dindex[rep] is a
-//                      representative's position in it; *dcount = its length
+//   compact_tile       representatives become the distinct list (dkeys):
+//                      each tile reserves a range of it with one atomic add
+//                      on *dcount (the list's length); dindex[rep] is a
+//                      representative's position in it.  The list's order
+//                      does not matter (it is sorted next), so tiles need no
+//                      prefix over each other
 //   (radix passes over dkeys, count read on the device)
 //   emit_distinct_tile sorted position i holds distinct value i of U_D;
 //                      drankd[distinct position] = i
@@ -18,8 +21,8 @@
 // The same two kernels keep a delta index up to date as rows are appended
 // (rows [hrow0, nd) of the delta, a batch at a time: the table, the
 // representatives and the distinct list persist between batches, and the
-// batch's new distinct values go after the *dbase ones already listed), so
-// that a merge can start from the distinct list.
+// batch's new distinct values are added to the list), so that a merge can
+// start from the distinct list.
 //
 // A slot holds (representative row + 1) and is written once, by one
 // compare-and-swap from zero.  Slots are read with device-coherent loads:
@@ -122,23 +125,17 @@ __device__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
 }
 
 struct CompactSmem {
-    uint32_t tile;
     uint32_t tmp[kWaves];
-    uint64_t lb64[kWaves + 1];
-    int lb32[kWaves];
+    uint64_t base;  // the tile's first position in the distinct list
 };
 
 constexpr int kCompactItems = 8;
 constexpr int kCompactTile = kBlock * kCompactItems;
 
 template <class T>
-__device__ void compact_tile(const ColDesc &C, char *smem) {
+__device__ void compact_tile(const ColDesc &C, uint64_t t, char *smem) {
     CompactSmem &S = *reinterpret_cast<CompactSmem *>(smem);
-    if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[2], 1u);
-    __syncthreads();
-    const uint32_t t = S.tile;
-    const uint64_t base = C.dbase ? *C.dbase : 0;  // distinct values listed before this batch
-    const uint64_t r0 = C.hrow0 + (uint64_t)t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+    const uint64_t r0 = C.hrow0 + t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
     uint32_t flags = 0;
 #pragma unroll
     for (int j = 0; j < kCompactItems; j++) {
@@ -147,8 +144,12 @@ __device__ void compact_tile(const ColDesc &C, char *smem) {
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan((uint32_t)__popc(flags), S.tmp, &tot);
-    const uint64_t pre = lookback_block(C.hstatus, t, tot, C.err, S.lb64, S.lb32);
-    uint64_t pos = base + pre + ex;
+    if (threadIdx.x == 0)
+        S.base = tot ? atomicAdd(reinterpret_cast<unsigned long long *>(C.dcount),
+                                 (unsigned long long)tot)
+                     : 0;
+    __syncthreads();
+    uint64_t pos = S.base + ex;
     bool full = false;
     typename T::K kv[kCompactItems];
 #pragma unroll
@@ -168,8 +169,6 @@ __device__ void compact_tile(const ColDesc &C, char *smem) {
         }
     }
     if (full) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
-    const uint64_t tb = C.hrow0 + (uint64_t)t * kCompactTile;
-    if (threadIdx.x == 0 && tb < C.nd && tb + kCompactTile >= C.nd) *C.dcount = base + pre + tot;
 }
 
 // After the radix passes over the distinct values: every sorted position

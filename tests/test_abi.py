@@ -141,7 +141,7 @@ def test_tuning_calls_reject_null_context(lib):
 def test_delta_index_bytes_and_argument_checks(lib):
     b = ctypes.c_uint64()
     assert lib.mc_delta_index_bytes(1, 1000, ctypes.byref(b)) == 0
-    # table of 2048 slots, representatives, positions, values, prefix words
+    # table of 2048 slots, representatives, positions, values
     assert b.value >= 2048 * 4 + 1000 * (4 + 4 + 8)
     assert lib.mc_delta_index_bytes(7, 10, ctypes.byref(b)) == -1
     assert lib.mc_delta_index_bytes(1, 1 << 30, ctypes.byref(b)) == -1
