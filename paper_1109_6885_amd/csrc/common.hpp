@@ -166,45 +166,6 @@ __device__ __forceinline__ void flag_error(uint32_t *err, uint32_t bit) {
     if (err) atomicOr(err, bit);
 }
 
-// Called by wave 0 of the block only.  Returns the exclusive prefix of tile
-// `tile` (sum of the aggregates of tiles 0 .. tile-1).
-__device__ inline uint64_t lookback_wave(uint64_t *status, uint32_t tile, uint64_t agg,
-                                         uint32_t *err) {
-    const int lane = lane_id();
-    if (tile == 0) {
-        if (lane == 0) st_rel(&status[0], kFlagPre | agg);
-        return 0;
-    }
-    if (lane == 0) st_rel(&status[tile], kFlagAgg | agg);
-    uint64_t prefix = 0;
-    int64_t base = (int64_t)tile - 1;
-    while (true) {
-        int64_t t = base - lane;  // lane 0 looks at the nearest predecessor
-        uint64_t s = kFlagPre;    // lanes before tile 0 act as a zero prefix
-        if (t >= 0) {
-            uint32_t spins = 0;
-            s = ld_acq(&status[t]);
-            while ((s >> 62) == 0) {
-                if (++spins > kSpinLimit) {
-                    flag_error(err, MC_DEVERR_SPIN);
-                    s = kFlagPre;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                s = ld_acq(&status[t]);
-            }
-        }
-        uint64_t pre = __ballot((s & kFlagPre) != 0);
-        int stop = pre ? (__ffsll((long long)pre) - 1) : 64;
-        uint64_t v = lane <= stop ? (s & kValMask) : 0;
-        prefix += wave_sum(v);
-        if (pre) break;
-        base -= 64;
-    }
-    if (lane == 0) st_rel(&status[tile], kFlagPre | (prefix + agg));
-    return prefix;
-}
-
 // ---------------------------------------------------------------------------
 // Everything one column's merge reads and writes.  The single-column entry
 // points pass it by value as a kernel argument; the batched entry point keeps
@@ -264,11 +225,11 @@ struct ColDesc {
     uint64_t hrow0;            // first delta row of this hashing launch (0 in a merge)
 };
 
-// The same prefix with the whole workgroup looking back: each round the 256
-// threads read the statuses of the 256 nearest unvisited predecessors at
-// once, so a tile far from the last published inclusive prefix needs
-// (distance / 256) rounds instead of (distance / 64).  Every thread of the
-// block must call it; every thread gets the exclusive prefix.  s_u64 needs
+// The whole workgroup looks back: each round the 256 threads read the
+// statuses of the 256 nearest unvisited predecessors at once, so a tile far
+// from the last published inclusive prefix needs (distance / 256) rounds.
+// Every thread of the block must call it; every thread gets the exclusive
+// prefix (the sum of the aggregates of tiles 0 .. tile-1).  s_u64 needs
 // kWaves + 1 entries and s_i32 kWaves entries of LDS.
 //
 // Split in two so that a tile can publish its own total first, do other work
@@ -319,11 +280,6 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
     }
     if (threadIdx.x == 0) st_rel(&status[tile], kFlagPre | (prefix + agg));
     return prefix;
-}
-__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t tile, uint64_t agg,
-                                          uint32_t *err, uint64_t *s_u64, int *s_i32) {
-    lookback_publish(status, tile, agg);
-    return lookback_resolve(status, tile, agg, err, s_u64, s_i32);
 }
 
 // Move n (<= SLOTS * kBlock) elements: element x = load(x) goes to
