@@ -351,7 +351,8 @@ constexpr size_t kSmemMerge = max3(sizeof(mc::MergeSmem<mc::TU32>),
 constexpr size_t kSmemSmall = 1024;
 constexpr size_t kSmemHash = max3(sizeof(mc::HashSmem<mc::TU32>), sizeof(mc::HashSmem<mc::TU64>),
                                   sizeof(mc::HashSmem<mc::TS16>));
-constexpr size_t kSmemHistScan = (mc::kWaves + 16) * 4;  // scan scratch + digits per position
+// scan scratch + distinct digits and most frequent digit's count per position
+constexpr size_t kSmemHistScan = (mc::kWaves + 32) * 4;
 
 __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, uint32_t *p1,
                                                    uint64_t n1) {
@@ -524,28 +525,48 @@ __global__ __launch_bounds__(256) void kn_hist_scan(Batch B) {
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::hist_scan_col, C, smem);
 }
-__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p) {
+// One radix pass phase for every column: each workgroup takes `group`
+// consecutive tiles (or digits, for the scan) of its column, one after the
+// other.  The fallback passes scan kFbDigitGroup digits per workgroup: when
+// they return at once (most columns) the scan dispatches that many times
+// fewer workgroups.  Their count and scatter phases keep one tile per
+// workgroup, which measured faster on a 300-column batch where some
+// columns do need the full sort.
+__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p, int group) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
     mc::PassIO io;
-    if (pass_io(C, kind, p, &io)) MC_DISPATCH(C, mc::sort_up_tile, C, io, blockIdx.x - B.map[j], smem);
+    if (!pass_io(C, kind, p, &io)) return;
+    const uint32_t t0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
+    for (int g = 0; g < group && t0 + g < C.sort_tiles; g++) {
+        if (g) __syncthreads();  // the tile before is done with the LDS
+        MC_DISPATCH(C, mc::sort_up_tile, C, io, t0 + g, smem);
+    }
 }
-__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p) {
+__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p, int group) {
     __shared__ __attribute__((aligned(16))) char smem[64];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
     mc::PassIO io;
-    if (pass_io(C, kind, p, &io))
-        MC_DISPATCH(C, mc::sort_scan_digit, C, io, blockIdx.x - B.map[j], smem);
+    if (!pass_io(C, kind, p, &io)) return;
+    const uint32_t d0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
+    for (int g = 0; g < group && d0 + g < 256u; g++) {
+        if (g) __syncthreads();
+        MC_DISPATCH(C, mc::sort_scan_digit, C, io, d0 + g, smem);
+    }
 }
-__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p) {
+__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p, int group) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
     const uint32_t j = find_col(B, blockIdx.x);
     const mc::ColDesc &C = B.cols[j];
     mc::PassIO io;
-    if (pass_io(C, kind, p, &io))
-        MC_DISPATCH(C, mc::sort_down_tile, C, io, blockIdx.x - B.map[j], smem);
+    if (!pass_io(C, kind, p, &io)) return;
+    const uint32_t t0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
+    for (int g = 0; g < group && t0 + g < C.sort_tiles; g++) {
+        if (g) __syncthreads();
+        MC_DISPATCH(C, mc::sort_down_tile, C, io, t0 + g, smem);
+    }
 }
 __global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
@@ -871,13 +892,18 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxPasses = 16;
-// map slots: 0 hist, 1 hist_scan, 2..17 pass up/down, 18..33 pass scan,
-// 34 emit, 35 merge, 36 repack, 37 X_M compaction, 38 merge tile boundaries,
-// 39 hash insert, 40 compaction of the distinct values, 41 row ranks
-constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 2 + kMaxPasses,
-              kMapEmit = 2 + 2 * kMaxPasses, kMapMerge = kMapEmit + 1, kMapRepack = kMapEmit + 2,
-              kMapXc = kMapEmit + 3, kMapMergePart = kMapEmit + 4, kMapHash = kMapEmit + 5,
-              kMapCompact = kMapEmit + 6, kMapRank = kMapEmit + 7, kNumMaps = kMapEmit + 8;
+// Tiles, and digits of the scan, per workgroup in the batched fallback passes.
+constexpr uint32_t kFbTileGroup = 1, kFbDigitGroup = 8;
+// map slots: 0 hist, 1 hist_scan, 2 sort tiles (prefix pass up/down,
+// windows), 3 prefix pass scan, 4 emit, 5 merge, 6 repack, 7 X_M compaction,
+// 8 merge tile boundaries, 9 hash insert, 10 compaction of the distinct
+// values, 11 row ranks, 12..27 fallback pass p up/down and 28..43 fallback
+// pass p scan (workgroups of kFbTileGroup tiles / kFbDigitGroup digits;
+// columns with at least p + 1 digit positions)
+constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 3, kMapEmit = 4,
+              kMapMerge = 5, kMapRepack = 6, kMapXc = 7, kMapMergePart = 8, kMapHash = 9,
+              kMapCompact = 10, kMapRank = 11, kMapFbPass = 12,
+              kMapFbScan = kMapFbPass + kMaxPasses, kNumMaps = kMapFbScan + kMaxPasses;
 
 struct BatchPlan {
     uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, total = 0;
@@ -927,10 +953,15 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
             uint64_t n = 0;
             if (m == kMapHist) n = L.hist_tiles;
             else if (m == kMapHistScan) n = has_delta ? 1 : 0;
-            else if (m >= kMapPass && m < kMapPass + kMaxPasses)
-                n = (has_delta && (uint32_t)(m - kMapPass) < L.passes) ? L.sort_tiles : 0;
-            else if (m >= kMapScan && m < kMapScan + kMaxPasses)
-                n = (has_delta && (uint32_t)(m - kMapScan) < L.passes) ? 256 : 0;
+            else if (m == kMapPass) n = has_delta ? L.sort_tiles : 0;
+            else if (m == kMapScan) n = has_delta ? 256 : 0;
+            else if (m >= kMapFbPass && m < kMapFbPass + kMaxPasses)
+                n = (has_delta && (uint32_t)(m - kMapFbPass) < L.passes)
+                        ? ceil_div(L.sort_tiles, kFbTileGroup)
+                        : 0;
+            else if (m >= kMapFbScan && m < kMapFbScan + kMaxPasses)
+                n = (has_delta && (uint32_t)(m - kMapFbScan) < L.passes) ? 256 / kFbDigitGroup
+                                                                          : 0;
             else if (m == kMapEmit) n = L.emit_tiles;
             else if (m == kMapMerge) n = L.merge_tiles ? L.merge_tiles : 1;
             else if (m == kMapRepack) n = L.repack_tiles;
@@ -984,17 +1015,22 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
     // with a delta has sort tiles there)
     auto passes = [&](int kind, uint32_t n) -> int {
         for (uint32_t p = 0; p < n; p++) {
-            const int m = kind == kPassPrefix ? 0 : (int)p;
-            const uint32_t tp = tiles(kMapPass + m);
+            // prefix passes: one tile per workgroup, every column with a
+            // delta; fallback passes: groups of tiles, the pass's own maps
+            const bool fb = kind != kPassPrefix;
+            const int mp = fb ? kMapFbPass + (int)p : kMapPass;
+            const int ms = fb ? kMapFbScan + (int)p : kMapScan;
+            const int tg = fb ? (int)kFbTileGroup : 1, dg = fb ? (int)kFbDigitGroup : 1;
+            const uint32_t tp = tiles(mp);
             if (!tp) continue;
-            hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + m),
-                               kind, (int)p);
+            hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(mp), kind,
+                               (int)p, tg);
             MC_LAUNCHED("kn_sort_up");
-            hipLaunchKernelGGL(kn_sort_scan, dim3(tiles(kMapScan + m)), dim3(mc::kBlock), 0, s,
-                               batch(kMapScan + m), kind, (int)p);
+            hipLaunchKernelGGL(kn_sort_scan, dim3(tiles(ms)), dim3(mc::kBlock), 0, s, batch(ms),
+                               kind, (int)p, dg);
             MC_LAUNCHED("kn_sort_scan");
-            hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass + m),
-                               kind, (int)p);
+            hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(mp), kind,
+                               (int)p, tg);
             MC_LAUNCHED("kn_sort_down");
         }
         return MC_OK;

@@ -15,7 +15,8 @@
 //
 // One to three global passes over the most significant varying digits (as
 // many as it takes for runs of about 32 values on average, judged from the
-// histograms) leave the values ordered by their leading bytes ("prefix"), in
+// histograms; all three when the top digit shows a few heavily repeated
+// values) leave the values ordered by their leading bytes ("prefix"), in
 // runs of equal prefix.
 // window_sort_tile then sorts every tile in LDS by the whole value: each run
 // of equal prefix inside the tile is ordered.  window_seam_tile finishes the
@@ -53,6 +54,10 @@ template <class T>
 __host__ __device__ constexpr int sort_tile() { return kBlock * SortCfg<T>::kItems; }
 
 constexpr int kHistChunk = 4096;  // delta values per workgroup in hist_tile
+
+// Runs of equal prefix longer than this are not ordered by the windows (they
+// keep their place if already ordered, else the full sort takes over).
+constexpr uint32_t kRunLimit = 256;
 
 // Buffers of pass p (selects, not indexing, so the descriptor stays in registers).
 __device__ __forceinline__ void *kbuf(const ColDesc &C, int i) { return (i & 1) ? C.keys1 : C.keys0; }
@@ -157,17 +162,19 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
     constexpr int P = T::kBytes;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
     uint32_t *ndig = tmp + kWaves;  // distinct digits per position
+    uint32_t *maxc = ndig + 16;     // count of the most frequent digit per position
     const uint64_t n = sort_n(C);
     // one wave per digit position at a time, lane l holding digits 4l..4l+3:
     // a wave scan and no block barrier per position
     const int lane = lane_id();
     for (int p = wave_id(); p < P; p += kWaves) {
-        uint32_t v[4], run = 0, nz = 0;
+        uint32_t v[4], run = 0, nz = 0, mx = 0;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             v[q] = C.gh[p * 256 + 4 * lane + q];
             run += v[q];
             nz += v[q] ? 1u : 0u;
+            mx = max(mx, v[q]);
             if (v[q] == n) C.trivial[p] = 1u;
         }
         uint32_t ex = wave_incl_scan(run) - run;
@@ -177,22 +184,36 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
             ex += v[q];
         }
         nz = wave_sum(nz);
-        if (lane == 0) ndig[p] = nz;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+        if (lane == 0) {
+            ndig[p] = nz;
+            maxc[p] = mx;
+        }
     }
     __syncthreads();  // the flags above, written by other threads of the block
     if (threadIdx.x == 0) {
         // prefix digits: the most significant varying positions, as many as
         // it takes (at most kPrefixSlots) for n / (product of their numbers
-        // of distinct digits) <= the wanted run length
+        // of distinct digits) <= the wanted run length.  If the top digit is
+        // skewed (its most frequent value holds more than kRunLimit values
+        // and more than twice the mean), a few values are heavily repeated:
+        // a run of equal prefix then holds all copies of such a value, and
+        // any other value sharing that prefix leaves a long run out of order
+        // (the full sort); every slot is used, so that the prefix almost
+        // never covers a second value.
         int pos[kPrefixSlots];
         int k = 0;
         double combos = 1.0;
+        bool skewed = false;
         const double run = C.prefix_run ? (double)C.prefix_run : kPrefixRun;
         for (int p = P - 1; p >= 0 && k < kPrefixSlots; p--) {
             if (C.trivial[p]) continue;
+            if (k == 0)
+                skewed = maxc[p] > kRunLimit && (double)maxc[p] > 2.0 * (double)n / ndig[p];
             pos[k++] = p;
             combos *= (double)ndig[p];
-            if ((double)n <= combos * run) break;
+            if ((double)n <= combos * run && !skewed) break;
         }
         for (int s = 0; s < kPrefixSlots; s++) {
             const int from_top = kPrefixSlots - 1 - s;  // the last slot takes the top digit
@@ -395,8 +416,6 @@ __device__ void sort_down_tile(const ColDesc &C, const PassIO &io, uint32_t t, c
 // order" flag at once and leaves its values, and the full LSD sort after
 // the emit starts over from the unsorted values.  window_seam_tile then
 // handles the run crossing seam (t+1)*TILE, if any.
-
-constexpr uint32_t kRunLimit = 256;
 
 // The prefix of a value: its digits at the used prefix slots (pp[s] < 0: unused).
 template <class T>
