@@ -45,8 +45,10 @@ constexpr uint32_t kFromB = 0x8000u;  // > any merge tile: marks an index into b
 
 template <class T>
 struct MergeSmem {
-    typename T::N a[merge_tile<T>() + 1];  // a[0] = U_M[i0 - 1] (predecessor)
-    typename T::N b[merge_tile<T>()];
+    // the tile's inputs in one array (a tile holds na + nb <= merge_tile
+    // entries): ab[0] = U_M[i0 - 1] (predecessor), ab[1 + x] = U_M[i0 + x]
+    // for x < na ("a"), ab[na + 1 + y] = U_D[j0 + y] for y < nb ("b")
+    typename T::N ab[merge_tile<T>() + 1];
     uint16_t src[merge_tile<T>()];  // output r of the tile: index in a, or kFromB | index in b
     int16_t xm[merge_tile<T>()];    // tile-relative U' index of a[1 + x]
     int16_t xd[merge_tile<T>()];    // tile-relative U' index of b[y] (-1: the tile before's last)
@@ -173,9 +175,10 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     if (!order_ok && threadIdx.x == 0) flag_error(C.err, MC_DEVERR_ORDER);
     const uint64_t j0 = k0 - i0, j1 = order_ok ? k1 - i1 : j0;
     const uint32_t na = order_ok ? (uint32_t)(i1 - i0) : 0u, nb = (uint32_t)(j1 - j0);
-    // stage S.a[0] = U_M[i0 - 1] (if any), S.a[1 + x] = U_M[i0 + x] and
-    // S.b[x] = U_D[j0 + x] as one range of na + 1 + nb loads
+    // stage a[0] = U_M[i0 - 1] (if any), a[1 + x] = U_M[i0 + x] and
+    // b[y] = U_D[j0 + y] as one range of na + 1 + nb loads
     typedef typename T::N N;
+    N *const sa = S.ab, *const sb = S.ab + na + 1;
     constexpr int kStageSlots = (merge_tile<T>() + 1 + kBlock - 1) / kBlock;
     stage_all<kStageSlots>(
         na + 1 + nb,
@@ -183,20 +186,15 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
             if (q <= na) return (q > 0 || i0 > 0) ? gA(i0 + q - 1) : N{};
             return gB(j0 + (q - na - 1));
         },
-        [&](uint32_t q, const N &v) {
-            if (q <= na)
-                S.a[q] = v;
-            else
-                S.b[q - na - 1] = v;
-        });
+        [&](uint32_t q, const N &v) { S.ab[q] = v; });
     __syncthreads();
 
     // this thread's slice of the tile's merged range
     const uint32_t len = na + nb;
     const uint32_t d0 = min<uint32_t>(threadIdx.x * ITEMS, len);
     const uint32_t d1 = min<uint32_t>(d0 + ITEMS, len);
-    auto lA = [&](uint64_t i) { return S.a[i + 1]; };
-    auto lB = [&](uint64_t j) { return S.b[j]; };
+    auto lA = [&](uint64_t i) { return sa[i + 1]; };
+    auto lB = [&](uint64_t j) { return sb[j]; };
     const uint32_t ia0 = (uint32_t)co_rank<T>(d0, na, nb, lA, lB);
     const uint32_t jb0 = d0 - ia0;
 
@@ -207,13 +205,13 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     {
         uint32_t ia = ia0, jb = jb0;
         for (uint32_t s = 0; s < nsteps; s++) {
-            const bool take_a = jb >= nb || (ia < na && T::le(S.a[ia + 1], S.b[jb]));
+            const bool take_a = jb >= nb || (ia < na && T::le(sa[ia + 1], sb[jb]));
             uint32_t kind;
             if (take_a) {
                 kind = kStepA;
                 ia++;
             } else {
-                kind = ((i0 + ia > 0) && T::eq(S.a[ia], S.b[jb])) ? kStepDup : kStepNew;
+                kind = ((i0 + ia > 0) && T::eq(sa[ia], sb[jb])) ? kStepDup : kStepNew;
                 jb++;
             }
             steps |= kind << (2 * s);
@@ -251,7 +249,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     for (uint32_t r = threadIdx.x; r < tot; r += kBlock) {
         const uint32_t sv = S.src[r];
         const uint64_t pos = tile_prefix + r;
-        if (pos < cap) T::store(C.u_new, pos, T::denorm((sv & kFromB) ? S.b[sv & ~kFromB] : S.a[sv]));
+        if (pos < cap) T::store(C.u_new, pos, T::denorm((sv & kFromB) ? sb[sv & ~kFromB] : sa[sv]));
     }
     if (C.x_m)
         for (uint32_t x = threadIdx.x; x < na; x += kBlock)
