@@ -56,19 +56,21 @@ constexpr int kLocalSlots = 2 * kHashTile;  // LDS table of the tile's first occ
 
 template <class T>
 struct HashSmem {
+    // the tile's values; once the global probes are done, the same bytes
+    // hold the representative row of every first occurrence (u32 each)
     typename T::K keys[kHashTile];
     uint32_t slot[kLocalSlots];  // tile-local index + 1 of a value's first occurrence
-    uint32_t lrep[kHashTile];    // first occurrence inside the tile of each row's value
-    uint32_t grep[kHashTile];    // representative row of a first occurrence
+    uint16_t lrep[kHashTile];    // first occurrence inside the tile of each row's value
 };
+static_assert(kHashTile <= 65536, "tile-local indices are 16-bit");
 
-// Find or claim the slot of `key` in the global table; returns the
+// Find or claim the slot of `key` in the global table, probing from slot h
+// on (`done` slots of its probe sequence already seen); returns the
 // representative row, or `row` itself if it claimed the slot.
 template <class T>
 __device__ __forceinline__ uint32_t global_rep(const ColDesc &C, typename T::K key, uint32_t row,
-                                               bool *ok) {
-    uint64_t h = hash_key(key) & C.hmask;
-    for (uint64_t probe = 0; probe <= C.hmask; probe++) {
+                                               uint64_t h, uint64_t done, bool *ok) {
+    for (uint64_t probe = done; probe <= C.hmask; probe++) {
         uint32_t s = __hip_atomic_load(&C.htab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (s == 0) {
             s = atomicCAS(&C.htab[h], 0u, row + 1u);
@@ -113,14 +115,69 @@ __device__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
             }
             h = (h + 1) & (kLocalSlots - 1);
         }
-        S.lrep[i] = first;
+        S.lrep[i] = (uint16_t)first;
     }
     __syncthreads();
+    // Global probes of the first occurrences.  A thread's (up to
+    // kHashItems) probes advance together, one memory round trip at a time
+    // (slot loads, then claims of empty slots, then the representatives'
+    // values), so their latencies overlap; the rare probe that meets another
+    // value continues alone along its probe sequence.
     bool ok = true;
-    for (uint32_t i = threadIdx.x; i < tn; i += kBlock)
-        if (S.lrep[i] == i) S.grep[i] = global_rep<T>(C, S.keys[i], (uint32_t)(r0 + i), &ok);
+    K kk[kHashItems];
+    uint64_t hh[kHashItems];
+    uint32_t sv[kHashItems], res[kHashItems];
+    uint32_t live = 0;  // bit j: item j is a first occurrence still probing
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) {
+        const uint32_t i = j * kBlock + threadIdx.x;
+        res[j] = 0;
+        if (i < tn && S.lrep[i] == i) {
+            kk[j] = S.keys[i];
+            hh[j] = hash_key(kk[j]) & C.hmask;
+            live |= 1u << j;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++)
+        if ((live >> j) & 1u)
+            sv[j] = __hip_atomic_load(&C.htab[hh[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++)
+        if (((live >> j) & 1u) && sv[j] == 0)
+            sv[j] = atomicCAS(&C.htab[hh[j]], 0u, (uint32_t)(r0 + j * kBlock + threadIdx.x) + 1u);
+    // sv[j] == 0 now means the claim succeeded
+    K rk[kHashItems];
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) {
+        if (((live >> j) & 1u) && sv[j] == 0) {
+            res[j] = (uint32_t)(r0 + j * kBlock + threadIdx.x);
+            live &= ~(1u << j);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++)
+        if ((live >> j) & 1u) rk[j] = T::load(C.delta, sv[j] - 1u);
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) {
+        if ((live >> j) & 1u) {
+            if (T::keq(rk[j], kk[j])) {
+                res[j] = sv[j] - 1u;
+            } else {  // another value holds the slot: go on alone
+                res[j] = global_rep<T>(C, kk[j], (uint32_t)(r0 + j * kBlock + threadIdx.x),
+                                       (hh[j] + 1) & C.hmask, 1, &ok);
+            }
+        }
+    }
+    __syncthreads();  // every thread is done reading the values
+    uint32_t *grep = reinterpret_cast<uint32_t *>(S.keys);
+#pragma unroll
+    for (int j = 0; j < kHashItems; j++) {
+        const uint32_t i = j * kBlock + threadIdx.x;
+        if (i < tn && S.lrep[i] == i) grep[i] = res[j];
+    }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) C.rep[r0 + i] = S.grep[S.lrep[i]];
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) C.rep[r0 + i] = grep[S.lrep[i]];
     if (!ok) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
 }
 
