@@ -412,7 +412,11 @@ template <class T>
 __global__ __launch_bounds__(256) void k1_sort_scan(mc::ColDesc C, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[64];
     mc::PassIO io;
-    if (pass_io(C, kind, p, &io)) mc::sort_scan_digit<T>(C, io, blockIdx.x, smem);
+    if (!pass_io(C, kind, p, &io)) return;
+    if (C.sort_tiles <= mc::kSmallScanTiles)
+        mc::sort_scan_small<T>(C, io, blockIdx.x);  // 64 digits per workgroup
+    else
+        mc::sort_scan_digit<T>(C, io, blockIdx.x, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int kind, int p) {
@@ -550,6 +554,10 @@ __global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p, in
     const mc::ColDesc &C = B.cols[j];
     mc::PassIO io;
     if (!pass_io(C, kind, p, &io)) return;
+    if (C.sort_tiles <= mc::kSmallScanTiles) {  // 64 digits per workgroup
+        MC_DISPATCH(C, mc::sort_scan_small, C, io, blockIdx.x - B.map[j]);
+        return;
+    }
     const uint32_t d0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
     for (int g = 0; g < group && d0 + g < 256u; g++) {
         if (g) __syncthreads();
@@ -672,7 +680,9 @@ int launch_passes(const mc::ColDesc &C, const ColLayout &L, int kind, int passes
     for (int p = 0; p < passes; p++) {
         hipLaunchKernelGGL(k1_sort_up<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, kind, p);
         MC_LAUNCHED("k1_sort_up");
-        hipLaunchKernelGGL(k1_sort_scan<T>, dim3(256), dim3(mc::kBlock), 0, s, C, kind, p);
+        hipLaunchKernelGGL(k1_sort_scan<T>,
+                           dim3(L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts : 256),
+                           dim3(mc::kBlock), 0, s, C, kind, p);
         MC_LAUNCHED("k1_sort_scan");
         hipLaunchKernelGGL(k1_sort_down<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, kind, p);
         MC_LAUNCHED("k1_sort_down");
@@ -954,14 +964,18 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
             if (m == kMapHist) n = L.hist_tiles;
             else if (m == kMapHistScan) n = has_delta ? 1 : 0;
             else if (m == kMapPass) n = has_delta ? L.sort_tiles : 0;
-            else if (m == kMapScan) n = has_delta ? 256 : 0;
+            else if (m == kMapScan)
+                n = has_delta ? (L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts : 256)
+                              : 0;
             else if (m >= kMapFbPass && m < kMapFbPass + kMaxPasses)
                 n = (has_delta && (uint32_t)(m - kMapFbPass) < L.passes)
                         ? ceil_div(L.sort_tiles, kFbTileGroup)
                         : 0;
             else if (m >= kMapFbScan && m < kMapFbScan + kMaxPasses)
-                n = (has_delta && (uint32_t)(m - kMapFbScan) < L.passes) ? 256 / kFbDigitGroup
-                                                                          : 0;
+                n = (has_delta && (uint32_t)(m - kMapFbScan) < L.passes)
+                        ? (L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts
+                                                               : 256 / kFbDigitGroup)
+                        : 0;
             else if (m == kMapEmit) n = L.emit_tiles;
             else if (m == kMapMerge) n = L.merge_tiles ? L.merge_tiles : 1;
             else if (m == kMapRepack) n = L.repack_tiles;

@@ -286,6 +286,45 @@ __device__ void sort_scan_digit(const ColDesc &C, const PassIO &io, uint32_t d, 
     }
 }
 
+// The same scan for a column of at most kSmallScanTiles tiles, in
+// kSmallScanParts workgroups of 64 digits each: each wave takes 16 of them,
+// with its lanes along the tiles (two chunks of 64, coalesced), and issues
+// all its loads at once.  A launch then needs 4 workgroups per such column
+// instead of 256.
+constexpr uint32_t kSmallScanTiles = 128;
+constexpr uint32_t kSmallScanParts = 4;
+
+template <class T>
+__device__ void sort_scan_small(const ColDesc &C, const PassIO &io, uint32_t part) {
+    const int p = io.p;
+    if (p < 0) return;
+    const int lane = lane_id(), wv = wave_id();
+    const uint32_t nt = (uint32_t)min<uint64_t>(C.sort_tiles,
+                                                (sort_n(C) + sort_tile<T>() - 1) / sort_tile<T>());
+    constexpr int kRound = 256 / kSmallScanParts / kWaves;  // digits per wave
+    const int d0 = (int)part * (256 / kSmallScanParts) + wv;
+    {
+        uint32_t v0[kRound], v1[kRound];
+#pragma unroll
+        for (int r = 0; r < kRound; r++) {
+            const uint32_t *row = C.tcount + (uint64_t)(d0 + r * kWaves) * C.sort_tiles;
+            v0[r] = (uint32_t)lane < nt ? row[lane] : 0u;
+            v1[r] = (uint32_t)lane + 64 < nt ? row[lane + 64] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRound; r++) {
+            const int d = d0 + r * kWaves;
+            uint32_t *row = C.tcount + (uint64_t)d * C.sort_tiles;
+            const uint32_t base = C.base[p * 256 + d];
+            const uint32_t i0 = wave_incl_scan(v0[r]);
+            const uint32_t tot0 = __shfl(i0, 63, 64);
+            const uint32_t i1 = wave_incl_scan(v1[r]);
+            if ((uint32_t)lane < nt) row[lane] = base + i0 - v0[r];
+            if ((uint32_t)lane + 64 < nt) row[lane + 64] = base + tot0 + i1 - v1[r];
+        }
+    }
+}
+
 // ---- stable rank of a tile's digits ------------------------------------------
 // Item j of thread (wave wv, lane) is tile entry wv * 64 * ITEMS + j * 64 +
 // lane (each wave owns a contiguous chunk).  Returns in slot[j] the entry's
