@@ -175,6 +175,39 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     if (!order_ok && threadIdx.x == 0) flag_error(C.err, MC_DEVERR_ORDER);
     const uint64_t j0 = k0 - i0, j1 = order_ok ? k1 - i1 : j0;
     const uint32_t na = order_ok ? (uint32_t)(i1 - i0) : 0u, nb = (uint32_t)(j1 - j0);
+    if (order_ok && nb == 0 && na > 0) {
+        // U_M entries only (large dictionaries with small deltas are mostly
+        // such tiles): U' continues U_M shifted by the tile's offset, X_M
+        // counts on from it; no walk and no staging
+        lookback_publish(C.merge_status, t, na);
+        const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, na, C.err, S.lb64, S.lb32);
+        typedef typename T::K K;
+        constexpr int kSlots = (merge_tile<T>() + kBlock - 1) / kBlock;
+        K v[kSlots];
+#pragma unroll
+        for (int q = 0; q < kSlots; q++) {
+            const uint32_t x = q * kBlock + threadIdx.x;
+            if (x < na) v[q] = T::load(C.u_m, i0 + x);
+        }
+#pragma unroll
+        for (int q = 0; q < kSlots; q++) {
+            const uint32_t x = q * kBlock + threadIdx.x;
+            if (x < na) {
+                const uint64_t pos = tile_prefix + x;
+                if (pos < cap) T::store(C.u_new, pos, v[q]);
+                if (C.x_m) C.x_m[i0 + x] = (uint32_t)pos;
+            }
+        }
+        if (threadIdx.x == 0 && k1 == total) {
+            const uint64_t n = tile_prefix + na;
+            const uint32_t w = code_width(n);
+            C.result->new_dict_len = n;
+            C.result->new_bitwidth = w;
+            C.result->new_codes_words = (C.rows_total * w + 63) / 64;
+            C.result->delta_dict_len = b;
+        }
+        return;
+    }
     // stage a[0] = U_M[i0 - 1] (if any), a[1 + x] = U_M[i0 + x] and
     // b[y] = U_D[j0 + y] as one range of na + 1 + nb loads
     typedef typename T::N N;
