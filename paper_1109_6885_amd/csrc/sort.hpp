@@ -532,11 +532,13 @@ __device__ void window_sort_tile(const ColDesc &C, uint32_t t, char *smem) {
             if (i > s && T::lt(kn, T::norm(S.keys[i - 1]))) disorder = true;
             continue;
         }
+        // one loop over the run (a wave runs as long as its longest run, once)
         uint32_t rank = 0;
 #pragma unroll 4
-        for (uint32_t q = s; q < i; q++) rank += T::le(T::norm(S.keys[q]), kn) ? 1u : 0u;
-#pragma unroll 4
-        for (uint32_t q = i + 1; q < e; q++) rank += T::lt(T::norm(S.keys[q]), kn) ? 1u : 0u;
+        for (uint32_t q = s; q < e; q++) {
+            const typename T::N o = T::norm(S.keys[q]);
+            rank += (q < i ? T::le(o, kn) : T::lt(o, kn)) ? 1u : 0u;
+        }
         npos[j] = s + rank;
     }
     if (disorder) S.tmp[0] = 1u;
@@ -617,8 +619,10 @@ __device__ void window_seam_tile(const ColDesc &C, uint32_t t, char *smem) {
         const K k = S.keys[i];
         const typename T::N kn = T::norm(k);
         uint32_t rank = 0;
-        for (uint32_t q = s; q < i; q++) rank += T::le(T::norm(S.keys[q]), kn) ? 1u : 0u;
-        for (uint32_t q = i + 1; q < e; q++) rank += T::lt(T::norm(S.keys[q]), kn) ? 1u : 0u;
+        for (uint32_t q = s; q < e; q++) {
+            const typename T::N o = T::norm(S.keys[q]);
+            rank += (q < i ? T::le(o, kn) : T::lt(o, kn)) ? 1u : 0u;
+        }
         const uint32_t np = s + rank;
         if (np != i) {
             T::store(C.keys1, lo + np, k);
