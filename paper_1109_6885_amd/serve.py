@@ -313,8 +313,12 @@ class GpuDelta:
 class GpuExecutor:
     """Resident tables on one GPU.  Appends are host-to-device copies on an
     append stream; each admitted merge is one batched launch sequence over the
-    table's columns on the next stream of a pool; commit reads the result
-    scalars once per merge."""
+    table's columns on a stream of a pool (one whose last merge has finished,
+    if any, so a short merge does not queue behind a long one), with that
+    stream's own library context (a context stages a batch's descriptors in
+    one host buffer, so a shared context would make each launch wait for the
+    previous launch's copy on another stream); commit reads the result scalars
+    once per merge."""
 
     def __init__(self, n_streams: int = 4, device: int = 0):
         import torch
@@ -323,8 +327,10 @@ class GpuExecutor:
         self.device = device
         self.append_stream = torch.cuda.Stream(device=device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.ctxs = [cm.Context(device) for _ in range(n_streams)]
+        self.last_done = [None] * n_streams  # event of each stream's last merge
         self.next = 0
-        self.ctx = cm.context(device)
+        self.ctx = cm.context(device)  # default tuning, for the bounds
 
     # mains
     def make_main(self, cols) -> GpuMain:
@@ -443,10 +449,20 @@ class GpuExecutor:
         cache[key] = total
         return total
 
+    def _pick_stream(self) -> int:
+        n = len(self.streams)
+        for k in range(n):
+            i = (self.next + k) % n
+            e = self.last_done[i]
+            if e is None or e.query():
+                return i
+        return self.next % n
+
     def launch(self, m: GpuMain, d: GpuDelta):
         torch, cm = self.torch, self.cm
-        s = self.streams[self.next % len(self.streams)]
-        self.next += 1
+        si = self._pick_stream()
+        self.next = si + 1
+        s = self.streams[si]
         cols = self._inputs(m, d)
         with torch.cuda.stream(s):
             if d.fence is not None:
@@ -462,9 +478,11 @@ class GpuExecutor:
                     None, None, res[j * cm.RESULT_BYTES:(j + 1) * cm.RESULT_BYTES],
                     col.n_main + int(col.delta.shape[0])))
             scratch = cm.alloc_scratch(cm.batched_bounds(cols, self.ctx))
-            cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s, ctx=self.ctx)
+            cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s,
+                                     ctx=self.ctxs[si])
             done = torch.cuda.Event()
             done.record(s)
+            self.last_done[si] = done
         return {"cols": cols, "outs": outs, "res": res, "scratch": scratch, "done": done,
                 "stream": s}
 
