@@ -472,14 +472,17 @@ def autotune_batched(cols, outs=None, scratch=None, stream=None, ctx=None):
 
 
 def merge_columns_batched(cols, outs=None, scratch=None, graph: bool = False, stream=None,
-                          ctx=None):
-    """mc_merge_columns_batched over a list of ColumnInput.  Returns (outs, Graph|None)."""
+                          ctx=None, descs=None):
+    """mc_merge_columns_batched over a list of ColumnInput (descs: their
+    descriptors, if already built).  Returns (outs, Graph|None)."""
     ctx = ctx or context()
+    if descs is None:
+        descs = [c.descriptor() for c in cols]
     if outs is None:
         outs = [alloc_output(c) for c in cols]
     if scratch is None:
-        scratch = alloc_scratch(batched_bounds(cols, ctx))
-    ins = (McColumnIn * len(cols))(*[c.descriptor() for c in cols])
+        scratch = alloc_scratch(batched_bounds_of(descs, ctx))
+    ins = (McColumnIn * len(cols))(*descs)
     os_ = (McColumnOut * len(cols))(*[o.descriptor() for o in outs])
     g = ctypes.c_void_p() if graph else None
     check(load().mc_merge_columns_batched(ctx.handle, ins, os_, len(cols), _ptr(scratch),

@@ -464,22 +464,26 @@ class GpuExecutor:
         self.next = si + 1
         s = self.streams[si]
         cols = self._inputs(m, d)
+        descs = [c.descriptor() for c in cols]  # built once for the bounds and the launch
+        # (one allocation per column's U' and codes: the caching allocator
+        # reuses those; one allocation of all of them, gigabytes that rarely
+        # fit a cached block, went to the device allocator and stalled merges)
         with torch.cuda.stream(s):
             if d.fence is not None:
                 s.wait_event(d.fence)          # the snapshot's appends have landed
             res = torch.zeros(len(cols) * cm.RESULT_BYTES, dtype=torch.uint8,
                               device=f"cuda:{self.device}")
             outs = []
-            for j, col in enumerate(cols):
-                dict_cap, words, _ = cm.merge_bounds(col)
+            for j, (col, desc) in enumerate(zip(cols, descs)):
+                dict_cap, words, _ = cm.bounds_of(desc)
                 outs.append(cm.MergeOutput(
                     col.vtype, cm.value_tensor_empty(col.vtype, dict_cap),
                     torch.empty(max(words, 2), dtype=torch.int64, device=f"cuda:{self.device}"),
                     None, None, res[j * cm.RESULT_BYTES:(j + 1) * cm.RESULT_BYTES],
                     col.n_main + int(col.delta.shape[0])))
-            scratch = cm.alloc_scratch(cm.batched_bounds(cols, self.ctx))
+            scratch = cm.alloc_scratch(cm.batched_bounds_of(descs, self.ctx))
             cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s,
-                                     ctx=self.ctxs[si])
+                                     ctx=self.ctxs[si], descs=descs)
             done = torch.cuda.Event()
             done.record(s)
             self.last_done[si] = done
