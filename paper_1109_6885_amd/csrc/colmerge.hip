@@ -345,9 +345,7 @@ constexpr size_t max3(A a, B b, C3 c) { return a > b ? (a > c ? a : c) : (b > c 
 constexpr size_t kSmemHist = sizeof(mc::HistSmem<mc::TS16>);
 constexpr size_t kSmemDown = max3(sizeof(mc::DownSmem<mc::TU32>), sizeof(mc::DownSmem<mc::TU64>),
                                   sizeof(mc::DownSmem<mc::TS16>));
-constexpr size_t kSmemMerge = max3(sizeof(mc::MergeSmem<mc::TU32>),
-                                   sizeof(mc::MergeSmem<mc::TU64>),
-                                   sizeof(mc::MergeSmem<mc::TS16>));
+static_assert(MC_U32 == 0 && MC_U64 == 1 && MC_STR16 == 2, "merge map slots follow mc_type");
 constexpr size_t kSmemSmall = 1024;
 constexpr size_t kSmemHash = max3(sizeof(mc::HashSmem<mc::TU32>), sizeof(mc::HashSmem<mc::TU64>),
                                   sizeof(mc::HashSmem<mc::TS16>));
@@ -618,11 +616,14 @@ __global__ __launch_bounds__(256) void kn_merge_part(Batch B) {
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::merge_partition, C, blockIdx.x - B.map[j]);
 }
+// One launch per value type (the map covers that type's columns only), so
+// that each sizes its LDS for its own type: more workgroups fit a CU for 4-
+// and 8-byte values than the 16-byte tiles allow.
+template <class T>
 __global__ __launch_bounds__(256) void kn_merge(Batch B) {
-    __shared__ __attribute__((aligned(16))) char smem[kSmemMerge];
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T>)];
     const uint32_t j = find_col(B, blockIdx.x);
-    const mc::ColDesc &C = B.cols[j];
-    MC_DISPATCH(C, mc::merge_tile, C, smem);
+    mc::merge_tile<T>(B.cols[j], smem);
 }
 __global__ __launch_bounds__(256) void kn_xcompact(Batch B) {
     const uint32_t j = find_col(B, blockIdx.x);
@@ -905,14 +906,15 @@ constexpr int kMaxPasses = 16;
 // Tiles, and digits of the scan, per workgroup in the batched fallback passes.
 constexpr uint32_t kFbTileGroup = 1, kFbDigitGroup = 8;
 // map slots: 0 hist, 1 hist_scan, 2 sort tiles (prefix pass up/down,
-// windows), 3 prefix pass scan, 4 emit, 5 merge, 6 repack, 7 X_M compaction,
-// 8 merge tile boundaries, 9 hash insert, 10 compaction of the distinct
-// values, 11 row ranks, 12..27 fallback pass p up/down and 28..43 fallback
-// pass p scan (workgroups of kFbTileGroup tiles / kFbDigitGroup digits;
-// columns with at least p + 1 digit positions)
+// windows), 3 prefix pass scan, 4 emit, 5..7 merge of the u32 / u64 / str16
+// columns, 8 repack, 9 X_M compaction, 10 merge tile boundaries, 11 hash
+// insert, 12 compaction of the distinct values, 13 row ranks, 14..29
+// fallback pass p up/down and 30..45 fallback pass p scan (workgroups of
+// kFbTileGroup tiles / kFbDigitGroup digits; columns with at least p + 1
+// digit positions)
 constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 3, kMapEmit = 4,
-              kMapMerge = 5, kMapRepack = 6, kMapXc = 7, kMapMergePart = 8, kMapHash = 9,
-              kMapCompact = 10, kMapRank = 11, kMapFbPass = 12,
+              kMapMerge = 5, kMapRepack = 8, kMapXc = 9, kMapMergePart = 10, kMapHash = 11,
+              kMapCompact = 12, kMapRank = 13, kMapFbPass = 14,
               kMapFbScan = kMapFbPass + kMaxPasses, kNumMaps = kMapFbScan + kMaxPasses;
 
 struct BatchPlan {
@@ -977,7 +979,8 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
                                                                : 256 / kFbDigitGroup)
                         : 0;
             else if (m == kMapEmit) n = L.emit_tiles;
-            else if (m == kMapMerge) n = L.merge_tiles ? L.merge_tiles : 1;
+            else if (m >= kMapMerge && m < kMapMerge + 3)
+                n = (int)ins[j].type == m - kMapMerge ? (L.merge_tiles ? L.merge_tiles : 1) : 0;
             else if (m == kMapRepack) n = L.repack_tiles;
             else if (m == kMapXc) n = L.xc_tiles;
             else if (m == kMapMergePart) n = L.partitioned ? merge_part_blocks(L.merge_tiles) : 0;
@@ -1079,10 +1082,20 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
                            batch(kMapMergePart));
         MC_LAUNCHED("kn_merge_part");
     }
-    if (tiles(kMapMerge)) {
-        hipLaunchKernelGGL(kn_merge, dim3(tiles(kMapMerge)), dim3(mc::kBlock), 0, s,
-                           batch(kMapMerge));
-        MC_LAUNCHED("kn_merge");
+    if (tiles(kMapMerge + MC_U32)) {
+        hipLaunchKernelGGL(kn_merge<mc::TU32>, dim3(tiles(kMapMerge + MC_U32)), dim3(mc::kBlock),
+                           0, s, batch(kMapMerge + MC_U32));
+        MC_LAUNCHED("kn_merge<u32>");
+    }
+    if (tiles(kMapMerge + MC_U64)) {
+        hipLaunchKernelGGL(kn_merge<mc::TU64>, dim3(tiles(kMapMerge + MC_U64)), dim3(mc::kBlock),
+                           0, s, batch(kMapMerge + MC_U64));
+        MC_LAUNCHED("kn_merge<u64>");
+    }
+    if (tiles(kMapMerge + MC_STR16)) {
+        hipLaunchKernelGGL(kn_merge<mc::TS16>, dim3(tiles(kMapMerge + MC_STR16)),
+                           dim3(mc::kBlock), 0, s, batch(kMapMerge + MC_STR16));
+        MC_LAUNCHED("kn_merge<str16>");
     }
     if (tiles(kMapXc)) {
         hipLaunchKernelGGL(kn_xcompact, dim3(tiles(kMapXc)), dim3(mc::kBlock), 0, s, batch(kMapXc));
