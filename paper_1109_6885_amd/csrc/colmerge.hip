@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256) void k1_xcompact(mc::ColDesc C) {
 }
 template <int CODES>
 __global__ __launch_bounds__(256) void k1_repack(mc::ColDesc C) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmemT<CODES>)];
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackOutSmem<CODES>)];
     mc::repack_tile<CODES>(C, blockIdx.x, smem);
 }
 
@@ -527,51 +527,51 @@ __global__ __launch_bounds__(256) void kn_hist_scan(Batch B) {
     const mc::ColDesc &C = B.cols[j];
     MC_DISPATCH(C, mc::hist_scan_col, C, smem);
 }
-// One radix pass phase for every column: each workgroup takes `group`
-// consecutive tiles (or digits, for the scan) of its column, one after the
-// other.  The fallback passes scan kFbDigitGroup digits per workgroup: when
-// they return at once (most columns) the scan dispatches that many times
-// fewer workgroups.  Their count and scatter phases keep one tile per
-// workgroup, which measured faster on a 300-column batch where some
-// columns do need the full sort.
-__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p, int group) {
+// One radix pass phase for every column.  Workgroup b of the map takes tile
+// (or, for the scan, digit / part) b - map[j] of column j; a launch with fewer
+// workgroups than the map's total strides over it (the fallback passes, whose
+// maps are built on the device and hold only the columns the prefix sort left
+// unsorted, so an unneeded pass is a launch of workgroups that return).
+__device__ __forceinline__ uint32_t map_total(const Batch &B) { return B.map[B.ncols]; }
+
+__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
-    const uint32_t j = find_col(B, blockIdx.x);
-    const mc::ColDesc &C = B.cols[j];
-    mc::PassIO io;
-    if (!pass_io(C, kind, p, &io)) return;
-    const uint32_t t0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
-    for (int g = 0; g < group && t0 + g < C.sort_tiles; g++) {
-        if (g) __syncthreads();  // the tile before is done with the LDS
-        MC_DISPATCH(C, mc::sort_up_tile, C, io, t0 + g, smem);
+    const uint32_t total = map_total(B);
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        if (b != blockIdx.x) __syncthreads();  // the tile before is done with the LDS
+        const uint32_t j = find_col(B, b);
+        const mc::ColDesc &C = B.cols[j];
+        mc::PassIO io;
+        if (!pass_io(C, kind, p, &io)) continue;
+        MC_DISPATCH(C, mc::sort_up_tile, C, io, b - B.map[j], smem);
     }
 }
-__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p, int group) {
+__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[64];
-    const uint32_t j = find_col(B, blockIdx.x);
-    const mc::ColDesc &C = B.cols[j];
-    mc::PassIO io;
-    if (!pass_io(C, kind, p, &io)) return;
-    if (C.sort_tiles <= mc::kSmallScanTiles) {  // 64 digits per workgroup
-        MC_DISPATCH(C, mc::sort_scan_small, C, io, blockIdx.x - B.map[j]);
-        return;
-    }
-    const uint32_t d0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
-    for (int g = 0; g < group && d0 + g < 256u; g++) {
-        if (g) __syncthreads();
-        MC_DISPATCH(C, mc::sort_scan_digit, C, io, d0 + g, smem);
+    const uint32_t total = map_total(B);
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        if (b != blockIdx.x) __syncthreads();
+        const uint32_t j = find_col(B, b);
+        const mc::ColDesc &C = B.cols[j];
+        mc::PassIO io;
+        if (!pass_io(C, kind, p, &io)) continue;
+        if (C.sort_tiles <= mc::kSmallScanTiles) {  // 64 digits per workgroup
+            MC_DISPATCH(C, mc::sort_scan_small, C, io, b - B.map[j]);
+        } else {
+            MC_DISPATCH(C, mc::sort_scan_digit, C, io, b - B.map[j], smem);
+        }
     }
 }
-__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p, int group) {
+__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
-    const uint32_t j = find_col(B, blockIdx.x);
-    const mc::ColDesc &C = B.cols[j];
-    mc::PassIO io;
-    if (!pass_io(C, kind, p, &io)) return;
-    const uint32_t t0 = (blockIdx.x - B.map[j]) * (uint32_t)group;
-    for (int g = 0; g < group && t0 + g < C.sort_tiles; g++) {
-        if (g) __syncthreads();
-        MC_DISPATCH(C, mc::sort_down_tile, C, io, t0 + g, smem);
+    const uint32_t total = map_total(B);
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        if (b != blockIdx.x) __syncthreads();
+        const uint32_t j = find_col(B, b);
+        const mc::ColDesc &C = B.cols[j];
+        mc::PassIO io;
+        if (!pass_io(C, kind, p, &io)) continue;
+        MC_DISPATCH(C, mc::sort_down_tile, C, io, b - B.map[j], smem);
     }
 }
 __global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
@@ -584,14 +584,21 @@ __global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
         MC_DISPATCH(C, mc::window_seam_tile, C, blockIdx.x - B.map[j], smem);
     }
 }
+// Strides like the passes: emit_tile takes its tile from a per-column ticket
+// (a workgroup holds one ticket at a time and waits only on lower ones, all
+// held by running workgroups), emit_distinct_tile waits on no other tile.
 __global__ __launch_bounds__(256) void kn_emit(Batch B, int again) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];
-    const uint32_t j = find_col(B, blockIdx.x);
-    const mc::ColDesc &C = B.cols[j];
-    if (C.drankd) {  // hashing route: the sorted values are distinct
-        MC_DISPATCH(C, mc::emit_distinct_tile, C, blockIdx.x - B.map[j], again != 0);
-    } else {
-        MC_DISPATCH(C, mc::emit_tile, C, smem, again != 0);
+    const uint32_t total = map_total(B);
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        if (b != blockIdx.x) __syncthreads();
+        const uint32_t j = find_col(B, b);
+        const mc::ColDesc &C = B.cols[j];
+        if (C.drankd) {  // hashing route: the sorted values are distinct
+            MC_DISPATCH(C, mc::emit_distinct_tile, C, b - B.map[j], again != 0);
+        } else {
+            MC_DISPATCH(C, mc::emit_tile, C, smem, again != 0);
+        }
     }
 }
 // Step 1(a)'s hashing route for the columns whose deltas take it
@@ -631,7 +638,7 @@ __global__ __launch_bounds__(256) void kn_xcompact(Batch B) {
 }
 template <int CODES>
 __global__ __launch_bounds__(256) void kn_repack(Batch B) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackSmemT<CODES>)];
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::RepackOutSmem<CODES>)];
     const uint32_t j = find_col(B, blockIdx.x);
     mc::repack_tile<CODES>(B.cols[j], blockIdx.x - B.map[j], smem);
 }
@@ -903,22 +910,64 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxPasses = 16;
-// Tiles, and digits of the scan, per workgroup in the batched fallback passes.
-constexpr uint32_t kFbTileGroup = 1, kFbDigitGroup = 8;
+// Workgroups of each batched fallback launch (they stride over the device-built
+// map of the columns that need the full sort).
+constexpr uint32_t kFbGrid = 2048;
 // map slots: 0 hist, 1 hist_scan, 2 sort tiles (prefix pass up/down,
 // windows), 3 prefix pass scan, 4 emit, 5..7 merge of the u32 / u64 / str16
 // columns, 8 repack, 9 X_M compaction, 10 merge tile boundaries, 11 hash
 // insert, 12 compaction of the distinct values, 13 row ranks, 14..29
-// fallback pass p up/down and 30..45 fallback pass p scan (workgroups of
-// kFbTileGroup tiles / kFbDigitGroup digits; columns with at least p + 1
-// digit positions)
+// fallback pass p up/down (tiles) and 30..45 fallback pass p scan (digits or
+// parts), columns with at least p + 1 digit positions, 46 fallback emit: the
+// per-column counts of every column with a delta, from which kn_fb_plan builds
+// the device maps of the columns that need the full sort (device slot p: pass
+// p, kMaxPasses + p: scan p, 2 kMaxPasses: emit)
 constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 3, kMapEmit = 4,
               kMapMerge = 5, kMapRepack = 8, kMapXc = 9, kMapMergePart = 10, kMapHash = 11,
               kMapCompact = 12, kMapRank = 13, kMapFbPass = 14,
-              kMapFbScan = kMapFbPass + kMaxPasses, kNumMaps = kMapFbScan + kMaxPasses;
+              kMapFbScan = kMapFbPass + kMaxPasses, kMapFbEmit = kMapFbScan + kMaxPasses,
+              kNumMaps = kMapFbEmit + 1;
+constexpr int kNumDevMaps = 2 * kMaxPasses + 1;
+
+// The fallback's maps, one workgroup per device slot: column j keeps its count
+// of the host slot when the prefix sort left it unsorted, else 0; exclusive
+// prefix over the columns, the total in entry ncols.
+__global__ __launch_bounds__(256) void kn_fb_plan(Batch B, const uint32_t *hmaps,
+                                                  uint32_t *dmaps, uint32_t npass) {
+    __shared__ uint32_t part[256];
+    const uint32_t s = blockIdx.x;
+    const uint32_t hs = s < npass ? kMapFbPass + s
+                                  : (s < 2 * npass ? kMapFbScan + (s - npass) : kMapFbEmit);
+    const uint32_t ds = s < npass ? s : (s < 2 * npass ? kMaxPasses + (s - npass) : 2 * kMaxPasses);
+    const uint32_t n = B.ncols;
+    const uint32_t *src = hmaps + (size_t)hs * (n + 1);
+    uint32_t *dst = dmaps + (size_t)ds * (n + 1);
+    const uint32_t per = (n + 255) / 256;
+    const uint32_t j0 = min(n, threadIdx.x * per), j1 = min(n, j0 + per);
+    auto count = [&](uint32_t j) -> uint32_t {
+        const uint32_t c = src[j + 1] - src[j];
+        return c && B.cols[j].sflags[mc::kSfUnsorted] ? c : 0u;
+    };
+    uint32_t sum = 0;
+    for (uint32_t j = j0; j < j1; j++) sum += count(j);
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {  // inclusive scan of the parts
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t acc = part[threadIdx.x] - sum;
+    for (uint32_t j = j0; j < j1; j++) {
+        dst[j] = acc;
+        acc += count(j);
+    }
+    if (threadIdx.x == 255) dst[n] = part[255];
+}
 
 struct BatchPlan {
-    uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, total = 0;
+    uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, dmap_off = 0, total = 0;
     std::vector<uint64_t> z_off, b_off;
     std::vector<ColLayout> L;
     std::vector<uint32_t> maps;  // kNumMaps x (ncols + 1)
@@ -954,7 +1003,8 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
     P.b_total = align_up(b, 256);
     P.desc_off = P.z_total + P.b_total;
     P.map_off = P.desc_off + align_up((uint64_t)ncols * sizeof(mc::ColDesc), 256);
-    P.total = P.map_off + align_up((uint64_t)P.maps.size() * 4, 256);
+    P.dmap_off = P.map_off + align_up((uint64_t)P.maps.size() * 4, 256);
+    P.total = P.dmap_off + align_up((uint64_t)kNumDevMaps * (ncols + 1) * 4, 256);
     // tile-count prefixes per phase
     auto at = [&](int m, uint32_t j) -> uint32_t & { return P.maps[(size_t)m * (ncols + 1) + j]; };
     for (int m = 0; m < kNumMaps; m++) {
@@ -971,14 +1021,15 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
                               : 0;
             else if (m >= kMapFbPass && m < kMapFbPass + kMaxPasses)
                 n = (has_delta && (uint32_t)(m - kMapFbPass) < L.passes)
-                        ? ceil_div(L.sort_tiles, kFbTileGroup)
+                        ? L.sort_tiles
                         : 0;
             else if (m >= kMapFbScan && m < kMapFbScan + kMaxPasses)
                 n = (has_delta && (uint32_t)(m - kMapFbScan) < L.passes)
                         ? (L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts
-                                                               : 256 / kFbDigitGroup)
+                                                               : 256u)
                         : 0;
             else if (m == kMapEmit) n = L.emit_tiles;
+            else if (m == kMapFbEmit) n = has_delta ? L.emit_tiles : 0;
             else if (m >= kMapMerge && m < kMapMerge + 3)
                 n = (int)ins[j].type == m - kMapMerge ? (L.merge_tiles ? L.merge_tiles : 1) : 0;
             else if (m == kMapRepack) n = L.repack_tiles;
@@ -1000,10 +1051,18 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
 int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
     const mc::ColDesc *d_cols = reinterpret_cast<const mc::ColDesc *>(ws + P.desc_off);
     const uint32_t *d_maps = reinterpret_cast<const uint32_t *>(ws + P.map_off);
+    uint32_t *d_dmaps = reinterpret_cast<uint32_t *>(ws + P.dmap_off);
     auto batch = [&](int m) {
         Batch B;
         B.cols = d_cols;
         B.map = d_maps + (size_t)m * (ncols + 1);
+        B.ncols = ncols;
+        return B;
+    };
+    auto dbatch = [&](int ds) {  // a device-built fallback map
+        Batch B;
+        B.cols = d_cols;
+        B.map = d_dmaps + (size_t)ds * (ncols + 1);
         B.ncols = ncols;
         return B;
     };
@@ -1028,26 +1087,24 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
                            batch(kMapHistScan));
         MC_LAUNCHED("kn_hist_scan");
     }
-    // passes of kind `kind`: the prefix passes use pass 0's maps (every column
-    // with a delta has sort tiles there)
+    // passes of kind `kind`: the prefix passes take one workgroup per tile of
+    // every column with a delta; the fallback passes a fixed grid striding over
+    // the device-built maps (upper bound: the host slot's total)
     auto passes = [&](int kind, uint32_t n) -> int {
         for (uint32_t p = 0; p < n; p++) {
-            // prefix passes: one tile per workgroup, every column with a
-            // delta; fallback passes: groups of tiles, the pass's own maps
             const bool fb = kind != kPassPrefix;
-            const int mp = fb ? kMapFbPass + (int)p : kMapPass;
-            const int ms = fb ? kMapFbScan + (int)p : kMapScan;
-            const int tg = fb ? (int)kFbTileGroup : 1, dg = fb ? (int)kFbDigitGroup : 1;
-            const uint32_t tp = tiles(mp);
+            const uint32_t tp = tiles(fb ? kMapFbPass + (int)p : kMapPass);
+            const uint32_t ts = tiles(fb ? kMapFbScan + (int)p : kMapScan);
             if (!tp) continue;
-            hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(mp), kind,
-                               (int)p, tg);
+            const Batch bp = fb ? dbatch((int)p) : batch(kMapPass);
+            const Batch bs = fb ? dbatch(kMaxPasses + (int)p) : batch(kMapScan);
+            const uint32_t gp = fb ? std::min(tp, kFbGrid) : tp;
+            const uint32_t gs = fb ? std::min(ts, kFbGrid) : ts;
+            hipLaunchKernelGGL(kn_sort_up, dim3(gp), dim3(mc::kBlock), 0, s, bp, kind, (int)p);
             MC_LAUNCHED("kn_sort_up");
-            hipLaunchKernelGGL(kn_sort_scan, dim3(tiles(ms)), dim3(mc::kBlock), 0, s, batch(ms),
-                               kind, (int)p, dg);
+            hipLaunchKernelGGL(kn_sort_scan, dim3(gs), dim3(mc::kBlock), 0, s, bs, kind, (int)p);
             MC_LAUNCHED("kn_sort_scan");
-            hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(mp), kind,
-                               (int)p, tg);
+            hipLaunchKernelGGL(kn_sort_down, dim3(gp), dim3(mc::kBlock), 0, s, bp, kind, (int)p);
             MC_LAUNCHED("kn_sort_down");
         }
         return MC_OK;
@@ -1062,14 +1119,21 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
         }
     }
     if (tiles(kMapEmit)) {
-        for (int again = 0; again < 2; again++) {
-            if (again) {
-                rc = passes(kPassFull, P.max_passes);
-                if (rc) return rc;
+        hipLaunchKernelGGL(kn_emit, dim3(tiles(kMapEmit)), dim3(mc::kBlock), 0, s,
+                           batch(kMapEmit), 0);
+        MC_LAUNCHED("kn_emit");
+        if (P.max_passes) {  // the full sort of the columns found unsorted, and their emit
+            hipLaunchKernelGGL(kn_fb_plan, dim3(2 * P.max_passes + 1), dim3(256), 0, s,
+                               batch(0), d_maps, d_dmaps, P.max_passes);
+            MC_LAUNCHED("kn_fb_plan");
+            rc = passes(kPassFull, P.max_passes);
+            if (rc) return rc;
+            const uint32_t te = tiles(kMapFbEmit);
+            if (te) {
+                hipLaunchKernelGGL(kn_emit, dim3(std::min(te, kFbGrid)), dim3(mc::kBlock), 0, s,
+                                   dbatch(2 * kMaxPasses), 1);
+                MC_LAUNCHED("kn_emit");
             }
-            hipLaunchKernelGGL(kn_emit, dim3(tiles(kMapEmit)), dim3(mc::kBlock), 0, s,
-                               batch(kMapEmit), again);
-            MC_LAUNCHED("kn_emit");
         }
     }
     if (tiles(kMapRank)) {
@@ -1600,7 +1664,7 @@ int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
 
     // descriptors + maps, staged in the context's pinned buffer and copied on
     // the stream (the previous batch's copy must have left the buffer)
-    const uint64_t meta = P.total - P.desc_off;
+    const uint64_t meta = P.dmap_off - P.desc_off;  // the device-built maps stay out
     if (ctx->meta_event) MC_HIP(hipEventSynchronize(ctx->meta_event));
     if (ctx->meta_cap < meta) {
         if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);

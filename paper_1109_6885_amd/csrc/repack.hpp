@@ -7,11 +7,15 @@
 // default 2048, or what the batched autotuner picked).  Because 64 codes of
 // width w fill exactly w 64-bit words, a tile of CODES rows starts on an even
 // word boundary both in the input (CODES/64*w words) and in the output, so
-// tiles never share a word and need no atomics.  The tile's input words are
-// staged in LDS with 128-bit loads, each thread decodes CODES/256 codes and
-// gathers their new codes from X_M (X_D for delta rows) into an LDS code
-// array, and then each thread assembles whole output words from the codes
-// that overlap them and writes them with coalesced 128-bit stores.
+// tiles never share a word and need no atomics in global memory.  The tile's
+// input words are staged in LDS with 128-bit loads; each thread decodes
+// CODES/256 consecutive codes, gathers their new codes from X_M (X_D for
+// delta rows) and writes them as one run of bits into an LDS copy of the
+// tile's output words (an LDS OR, since neighbouring threads share the words
+// at the ends of their runs); the words then leave with coalesced 128-bit
+// stores.  (Assembling each output word from a code array instead leaves
+// only 16*w' threads busy, each with about 64/w' dependent LDS reads: three
+// times slower at w' = 4 on a 32M-row column with a 6-entry dictionary.)
 #pragma once
 
 #include "common.hpp"
@@ -29,6 +33,12 @@ struct RepackSmemT {
     uint32_t code[CODES];
 };
 typedef RepackSmemT<kRepackCodes> RepackSmem;
+// the re-encode's tile: input words, and the output words (w' <= 32) being built
+template <int CODES>
+struct RepackOutSmem {
+    uint64_t in[CODES / 64 * 32 + 2];
+    unsigned long long out[CODES / 64 * 32];
+};
 
 // ---------------------------------------------------------------------------
 // Compact X_M.  The gathers X_M[c] dominate Step 2(b), and their cost grows
@@ -145,10 +155,10 @@ __device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint3
 
 template <int CODES = kRepackCodes>
 __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
-    constexpr int PER = CODES / kBlock;  // codes per thread
-    RepackSmemT<CODES> &S = *reinterpret_cast<RepackSmemT<CODES> *>(smem);
+    constexpr int PER = CODES / kBlock;  // consecutive codes per thread
+    RepackOutSmem<CODES> &S = *reinterpret_cast<RepackOutSmem<CODES> *>(smem);
     uint64_t *s_in = S.in;
-    uint32_t *s_code = S.code;
+    unsigned long long *s_out = S.out;
 
     const uint32_t w = C.w;
     const uint32_t wn = C.result->new_bitwidth;
@@ -157,7 +167,13 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     const uint64_t c0 = t * CODES;
     if (c0 >= n_out) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(CODES, n_out - c0);
+    if (wn - 1u >= 32u) {  // the merge writes 1 <= w' <= 32 (|U'| <= 2^32); never past s_out
+        if (threadIdx.x == 0) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+        return;
+    }
+    const uint32_t nwo = (CODES / 64) * wn;  // output words of a full tile (even)
 
+    for (uint32_t x = threadIdx.x; x < nwo; x += kBlock) s_out[x] = 0ull;
     stage_main_words<CODES>(C, c0, s_in);
     __syncthreads();
 
@@ -165,12 +181,13 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     const uint64_t mask = (1ull << w) - 1ull;
     const bool compact = C.xdev != nullptr && *C.xflag == 0;
     const uint64_t A = compact ? xm_line_slope(C) : 0;
+    const uint32_t i0 = threadIdx.x * PER;  // tile-local index of the thread's first code
     const uint32_t *tab[PER];
     uint32_t idx[PER];
     uint32_t bad = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
-        const uint32_t i = j * kBlock + threadIdx.x;
+        const uint32_t i = i0 + j;
         const uint64_t g = c0 + i;
         tab[j] = nullptr;
         idx[j] = 0;
@@ -208,12 +225,42 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
 #pragma unroll
         for (int j = 0; j < PER; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
     }
-#pragma unroll
-    for (int j = 0; j < PER; j++) s_code[j * kBlock + threadIdx.x] = nc[j];
     if (bad) flag_error(C.err, bad);
+
+    // the thread's codes are tile bits [i0 * wn, (i0 + PER) * wn): fill 64-bit
+    // words from the low end and OR each finished one into LDS (rows past the
+    // tile's end are 0 and add nothing)
+    uint32_t wi = (i0 * wn) >> 6, nb = (i0 * wn) & 63u;
+    uint64_t cur = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const uint64_t c = nc[j];
+        cur |= c << nb;
+        nb += wn;
+        if (nb >= 64) {
+            atomicOr(&s_out[wi], (unsigned long long)cur);
+            wi++;
+            nb -= 64;
+            cur = nb ? (c >> (wn - nb)) : 0ull;
+        }
+    }
+    if (nb) atomicOr(&s_out[wi], (unsigned long long)cur);
     __syncthreads();
 
-    pack_store_tile<CODES>(C, t, s_code, wn, n_out);
+    // coalesced 128-bit stores, cut at the column's last word (and the
+    // buffer's capacity)
+    const uint64_t obase = t * (uint64_t)nwo;
+    const uint64_t wres = (n_out * wn + 63) / 64;
+    const uint64_t wlim = min<uint64_t>(C.out_cap, (wres + 1) & ~1ull);
+    const u64x2 *src2 = reinterpret_cast<const u64x2 *>(s_out);
+    for (uint32_t k2 = threadIdx.x; k2 < nwo / 2; k2 += kBlock) {
+        const uint64_t gw = obase + 2ull * k2;
+        if (gw + 1 < wlim) {
+            __builtin_nontemporal_store(src2[k2], reinterpret_cast<u64x2 *>(C.out + gw));
+        } else if (gw < wlim) {
+            C.out[gw] = s_out[2 * k2];
+        }
+    }
 }
 
 }  // namespace mc

@@ -68,9 +68,9 @@ def test_batched_partitioned_merge():
 
 
 def test_batched_prefix_sort_fallback():
-    """Columns whose values share their leading bytes (the order check fails
-    and the persistent full sort runs for them) between ordinary columns, in
-    one batch; twice, through a graph, so the full sort's counters restart."""
+    """Columns whose values share their leading bytes between ordinary
+    columns, in one batch; twice, through a graph, so the sort's counters
+    restart."""
     rng = np.random.default_rng(8)
     cols = []
     for vt in ("u64", "u32", "str16"):
@@ -87,6 +87,58 @@ def test_batched_prefix_sort_fallback():
                                d[rng.permutation(d.shape[0])]))
         cols.append(gen.random_column(rng, vt, 5000, 20_000, 7_000, 0.5))
     say(f"case batched prefix-sort fallback, {len(cols)} columns")
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, graph = cm.merge_columns_batched(dcols, graph=True)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    for o in outs:
+        o.new_codes.zero_()
+        o.new_dict.zero_()
+    graph.launch()
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+
+
+def few_prefix_values(rng, vtype, n):
+    """n values whose three leading bytes each take one of two values and
+    whose other bytes are random: every run of equal prefix holds about n / 8
+    values in no order, so the prefix sort leaves them unsorted and the full
+    sort has to run."""
+    top = [rng.integers(0, 2, n) * 0x40 + 0x21 for _ in range(3)]
+    if vtype == "str16":
+        d = rng.integers(0x20, 0x7F, size=(n, 16), dtype=np.uint8)
+        for i in range(3):
+            d[:, i] = top[i]
+        return d
+    if vtype == "u32":
+        v = rng.integers(0, 256, n).astype(np.uint32)
+        for i in range(3):
+            v |= top[i].astype(np.uint32) << np.uint32(24 - 8 * i)
+        return v
+    v = rng.integers(0, 1 << 40, n, dtype=np.uint64)
+    for i in range(3):
+        v |= top[i].astype(np.uint64) << np.uint64(56 - 8 * i)
+    return v
+
+
+def test_batched_full_sort_many_columns():
+    """Ten columns that all need the full sort, 600,000 delta rows each,
+    between ordinary columns: the full sort's launches have fewer workgroups
+    than those columns' tiles, digits and emit tiles, so each workgroup takes
+    several, across column boundaries.  Through a graph, twice."""
+    rng = np.random.default_rng(17)
+    cols = []
+    for i, vt in enumerate(("u64", "u32", "str16") * 3 + ("u64",)):
+        base = gen.random_column(rng, vt, 3000, 20_000, 0)
+        d = np.concatenate([few_prefix_values(rng, vt, 600_000),
+                            base.u_m[rng.integers(0, 3000, 50)]])
+        cols.append(gen.Column(vt, base.u_m, base.main_packed, base.n_main, base.w,
+                               d[rng.permutation(d.shape[0])]))
+        if i % 3 == 0:
+            cols.append(gen.random_column(rng, vt, 4000, 30_000, 9_000, 0.5))
+    say(f"case batched full sort, {len(cols)} columns")
     dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
     outs, graph = cm.merge_columns_batched(dcols, graph=True)
     torch.cuda.synchronize()
