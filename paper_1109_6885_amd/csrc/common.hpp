@@ -225,12 +225,16 @@ struct ColDesc {
     uint64_t hrow0;            // first delta row of this hashing launch (0 in a merge)
 };
 
-// The whole workgroup looks back: each round the 256 threads read the
-// statuses of the 256 nearest unvisited predecessors at once, so a tile far
-// from the last published inclusive prefix needs (distance / 256) rounds.
-// Every thread of the block must call it; every thread gets the exclusive
-// prefix (the sum of the aggregates of tiles 0 .. tile-1).  s_u64 needs
-// kWaves + 1 entries and s_i32 kWaves entries of LDS.
+// Decoupled look-back over the tiles' status words.  One wave looks back:
+// each round its 64 lanes read the statuses of the 64 nearest unvisited
+// predecessors at once, waits only for the lanes up to the nearest one that
+// holds an inclusive prefix (the others are not needed), and sums the
+// aggregates up to that one; a tile far from the last published inclusive
+// prefix needs (distance / 64) rounds.  (All 256 threads polling, each
+// waiting for its own predecessor, put four times the agent-scope loads on
+// the same few status lines.)  Every thread of the block must call it; every
+// thread gets the exclusive prefix (the sum of the aggregates of tiles
+// 0 .. tile-1), after a barrier.  s_prefix: one 64-bit word of LDS.
 //
 // Split in two so that a tile can publish its own total first, do other work
 // while its predecessors finish, and only then wait for their prefix.
@@ -238,48 +242,43 @@ __device__ inline void lookback_publish(uint64_t *status, uint32_t tile, uint64_
     if (threadIdx.x == 0) st_rel(&status[tile], (tile == 0 ? kFlagPre : kFlagAgg) | agg);
 }
 __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uint64_t agg,
-                                            uint32_t *err, uint64_t *s_u64, int *s_i32) {
+                                            uint32_t *err, uint64_t *s_prefix) {
     if (tile == 0) return 0;
-    const int lane = lane_id(), wv = wave_id();
-    uint64_t prefix = 0;
-    int64_t base = (int64_t)tile - 1;
-    while (true) {
-        const int64_t t = base - (int64_t)threadIdx.x;  // thread 0: nearest predecessor
-        uint64_t s = kFlagPre;                         // before tile 0: zero prefix
-        if (t >= 0) {
-            uint32_t spins = 0;
-            s = ld_acq(&status[t]);
-            while ((s >> 62) == 0) {
-                if (++spins > kSpinLimit) {
-                    flag_error(err, MC_DEVERR_SPIN);
-                    s = kFlagPre;
+    if (wave_id() == 0) {
+        const int lane = lane_id();
+        uint64_t prefix = 0;
+        int64_t base = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (true) {
+            const int64_t t = base - lane;  // lane 0: nearest predecessor
+            uint64_t s = t >= 0 ? ld_acq(&status[t]) : kFlagPre;  // before tile 0: zero prefix
+            while (true) {
+                const uint64_t pre = __ballot((s & kFlagPre) != 0);
+                // lanes up to and including the nearest inclusive prefix
+                const uint64_t need = pre ? ((pre & (~pre + 1)) << 1) - 1 : ~0ull;
+                const uint64_t wait = __ballot((s >> 62) == 0) & need;
+                if (!wait) break;
+                if (++spins > kSpinLimit) {  // give up: unpublished statuses count as zero
+                    if (lane == 0) flag_error(err, MC_DEVERR_SPIN);
+                    if ((s >> 62) == 0) s = kFlagPre;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                s = ld_acq(&status[t]);
+                if ((wait >> lane) & 1ull) s = ld_acq(&status[t]);
             }
+            const uint64_t pre = __ballot((s & kFlagPre) != 0);
+            const int stop = pre ? __ffsll((long long)pre) - 1 : 64;
+            prefix += wave_sum(lane <= stop ? (s & kValMask) : 0ull);
+            if (stop < 64) break;
+            base -= 64;
         }
-        // nearest predecessor (smallest thread index) holding an inclusive prefix
-        const uint64_t pre = __ballot((s & kFlagPre) != 0);
-        if (lane == 0) s_i32[wv] = pre ? wv * 64 + (__ffsll((long long)pre) - 1) : kBlock;
-        __syncthreads();
-        int stop = kBlock;
-#pragma unroll
-        for (int x = 0; x < kWaves; x++) stop = min(stop, s_i32[x]);
-        const uint64_t v = (int)threadIdx.x <= stop ? (s & kValMask) : 0;
-        const uint64_t ws = wave_sum(v);
-        if (lane == 0) s_u64[wv] = ws;
-        __syncthreads();
-        uint64_t round = 0;
-#pragma unroll
-        for (int x = 0; x < kWaves; x++) round += s_u64[x];
-        prefix += round;
-        __syncthreads();  // s_i32 / s_u64 are reused next round
-        if (stop < kBlock) break;
-        base -= kBlock;
+        if (lane == 0) {
+            st_rel(&status[tile], kFlagPre | (prefix + agg));
+            *s_prefix = prefix;
+        }
     }
-    if (threadIdx.x == 0) st_rel(&status[tile], kFlagPre | (prefix + agg));
-    return prefix;
+    __syncthreads();
+    return *s_prefix;
 }
 
 // Move n (<= SLOTS * kBlock) elements: element x = load(x) goes to

@@ -55,8 +55,7 @@ struct MergeSmem {
     uint32_t tile;
     uint32_t tmp[kWaves];
     uint64_t i0, i1;
-    uint64_t lb64[kWaves + 1];
-    int lb32[kWaves];
+    uint64_t lb;  // look-back result
 };
 
 // Number of U_M entries among the first k merged elements (ties: U_M first).
@@ -180,7 +179,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
         // such tiles): U' continues U_M shifted by the tile's offset, X_M
         // counts on from it; no walk and no staging
         lookback_publish(C.merge_status, t, na);
-        const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, na, C.err, S.lb64, S.lb32);
+        const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, na, C.err, &S.lb);
         typedef typename T::K K;
         constexpr int kSlots = (merge_tile<T>() + kBlock - 1) / kBlock;
         K v[kSlots];
@@ -276,7 +275,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
             }
         }
     }
-    const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, tot, C.err, S.lb64, S.lb32);
+    const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, tot, C.err, &S.lb);
     __syncthreads();  // staging complete (the look-back may return without a barrier)
 
     for (uint32_t r = threadIdx.x; r < tot; r += kBlock) {

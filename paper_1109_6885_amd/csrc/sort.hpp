@@ -642,8 +642,7 @@ struct EmitSmem {
     uint16_t head[kEmitTile];           // LDS slot of the tile's r-th run head
     uint32_t tile;
     uint32_t tmp[kWaves];
-    uint64_t lb64[kWaves + 1];
-    int lb32[kWaves];
+    uint64_t lb;  // look-back result
 };
 
 // again = false: the emit after the prefix sort, which also checks the
@@ -699,7 +698,7 @@ __device__ void emit_tile(const ColDesc &C, char *smem, bool again) {
         for (int j = 0; j < kEmitItems; j++)
             if ((head >> j) & 1u) S.head[lo++] = (uint16_t)(l0 + j + 1);
     }
-    const uint64_t tile_prefix = lookback_resolve(status, t, tot, C.err, S.lb64, S.lb32);
+    const uint64_t tile_prefix = lookback_resolve(status, t, tot, C.err, &S.lb);
     __syncthreads();  // head slots complete
     for (uint32_t r = threadIdx.x; r < tot; r += kBlock) {
         const uint64_t idx = tile_prefix + r;
