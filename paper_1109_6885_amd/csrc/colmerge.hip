@@ -23,6 +23,7 @@
 
 struct mc_ctx {
     int device = 0;
+    uint32_t cus = 0;  // compute units of the device (grid of the one-launch full sort)
     int timing = 0;
     // one set of five events per timed merge since timing was enabled
     std::vector<std::array<hipEvent_t, 5>> ev;
@@ -422,6 +423,51 @@ __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int kind, int
     mc::PassIO io;
     if (pass_io(C, kind, p, &io)) mc::sort_down_tile<T>(C, io, blockIdx.x, smem);
 }
+// The full LSD sort (every digit position) in one launch.  It runs only
+// when the prefix sort left the values out of order; otherwise every
+// workgroup returns at once, where a launch per phase and pass (3 x 4, 8 or
+// 16 of them) would each cost a kernel boundary.  The grid has at most one
+// workgroup per compute unit, so all are resident together; they stride over
+// the tiles (or digits) of each phase, with a grid-wide barrier between
+// phases.  Every pass reads what the previous pass wrote, exactly as the
+// per-phase launches do.
+template <class T>
+__global__ __launch_bounds__(256) void k1_full_sort(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
+    __shared__ uint32_t s_ok;
+    if (C.sflags[mc::kSfUnsorted] == 0) return;
+    const uint32_t G = gridDim.x;
+    const bool small = C.sort_tiles <= mc::kSmallScanTiles;
+    const uint32_t scan_units = small ? mc::kSmallScanParts : 256u;
+    uint32_t *bar = &C.sflags[mc::kSfGridBar];
+    uint32_t target = 0;
+    for (int p = 0; p < T::kBytes; p++) {
+        const mc::PassIO io = mc::lsd_io(C, p);
+        for (uint32_t t = blockIdx.x; t < C.sort_tiles; t += G) {
+            mc::sort_up_tile<T>(C, io, t, smem);
+            __syncthreads();
+        }
+        target += G;
+        if (!mc::grid_barrier(bar, target, C.err, &s_ok)) return;
+        for (uint32_t d = blockIdx.x; d < scan_units; d += G) {
+            if (small)
+                mc::sort_scan_small<T>(C, io, d);
+            else
+                mc::sort_scan_digit<T>(C, io, d, smem);
+            __syncthreads();
+        }
+        target += G;
+        if (!mc::grid_barrier(bar, target, C.err, &s_ok)) return;
+        for (uint32_t t = blockIdx.x; t < C.sort_tiles; t += G) {
+            mc::sort_down_tile<T>(C, io, t, smem);
+            __syncthreads();
+        }
+        if (p + 1 < T::kBytes) {
+            target += G;
+            if (!mc::grid_barrier(bar, target, C.err, &s_ok)) return;
+        }
+    }
+}
 // round 0: every tile sorted in LDS; round 1: the runs crossing tile seams
 template <class T>
 __global__ __launch_bounds__(256) void k1_window(mc::ColDesc C, int round) {
@@ -699,7 +745,7 @@ int launch_passes(const mc::ColDesc &C, const ColLayout &L, int kind, int passes
 }
 
 template <class T>
-int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_t s,
+int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, uint32_t cus, hipStream_t s,
                             hipEvent_t after_sort) {
     int rc = MC_OK;
     if (C.nd == 0) {
@@ -728,9 +774,10 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, hipStream_
     // emit (checks the order), then the full sort and a second emit, which
     // return at once unless the check failed
     for (int again = 0; again < 2; again++) {
-        if (again) {
-            rc = launch_passes<T>(C, L, kPassFull, T::kBytes, s);
-            if (rc) return rc;
+        if (again && L.sort_tiles) {
+            const uint32_t grid = std::min<uint32_t>(L.sort_tiles, cus ? cus : 1u);
+            hipLaunchKernelGGL(k1_full_sort<T>, dim3(grid), dim3(mc::kBlock), 0, s, C);
+            MC_LAUNCHED("k1_full_sort");
         }
         if (L.hashed) {
             hipLaunchKernelGGL(k1_emit_distinct<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C,
@@ -869,7 +916,7 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
                                static_cast<char *>(ix->workspace) + X.scal + 80));
         MC_LAUNCHED("k_or_word");
     }
-    rc = launch_delta_dictionary<T>(C, L, s, ev ? ev[1] : nullptr);
+    rc = launch_delta_dictionary<T>(C, L, ctx->cus, s, ev ? ev[1] : nullptr);
     if (rc) return rc;
     if (ev) MC_HIP(hipEventRecord(ev[2], s));
     rc = launch_merge<T>(C, L.merge_tiles, s);
@@ -1195,6 +1242,13 @@ int mc_ctx_create(int device, mc_ctx **out) {
     mc_ctx *c = new (std::nothrow) mc_ctx();
     if (!c) return fail(MC_E_NOMEM, "context allocation failed");
     c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus <= 0) {
+        delete c;
+        return fail(MC_E_HIP, "cannot read the device's compute unit count");
+    }
+    c->cus = (uint32_t)cus;
     *out = c;
     return MC_OK;
 }
@@ -1297,9 +1351,9 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     int rc = launch_fill(za, L.z_size, d_count, 8, s);
     if (rc) return rc;
     switch (type) {
-        case MC_U32: return launch_delta_dictionary<mc::TU32>(C, L, s, nullptr);
-        case MC_U64: return launch_delta_dictionary<mc::TU64>(C, L, s, nullptr);
-        default: return launch_delta_dictionary<mc::TS16>(C, L, s, nullptr);
+        case MC_U32: return launch_delta_dictionary<mc::TU32>(C, L, ctx->cus, s, nullptr);
+        case MC_U64: return launch_delta_dictionary<mc::TU64>(C, L, ctx->cus, s, nullptr);
+        default: return launch_delta_dictionary<mc::TS16>(C, L, ctx->cus, s, nullptr);
     }
 }
 

@@ -14,11 +14,12 @@ constexpr int kWaves = kBlock / 64;
 
 // Slots of ColDesc::sflags: the digit positions (+ 1, 0 = unused) of the
 // prefix passes, the flag "the prefix sort left the values out of order",
-// and the tile tickets of the two emits.
+// the tile tickets of the two emits, and the arrival count of the full
+// sort's grid-wide barriers.
 constexpr int kPrefixSlots = 3;     // at most this many prefix passes
 constexpr double kPrefixRun = 32.0;  // default wanted values per run of equal prefix
 constexpr int kSfPrefix = 0, kSfUnsorted = kPrefixSlots, kSfEmitTicket = kPrefixSlots + 1,
-              kSfEmitTicket2 = kPrefixSlots + 2, kSfSlots = 8;
+              kSfEmitTicket2 = kPrefixSlots + 2, kSfGridBar = kPrefixSlots + 3, kSfSlots = 8;
 
 // ---------------------------------------------------------------------------
 // Value traits.  Stored values are always the caller's raw bytes.  For
@@ -279,6 +280,37 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
     }
     __syncthreads();
     return *s_prefix;
+}
+
+// Barrier over every workgroup of a launch whose workgroups are all resident
+// at once (the caller launches at most one per compute unit).  ctr is a
+// zeroed word that only grows: the caller's b-th barrier passes target =
+// b * gridDim.x.  The workgroups may sit on different XCDs, whose L2 caches
+// are not coherent with each other, so every thread releases its writes to
+// the device before arriving and acquires after leaving.  The wait is
+// bounded: on overrun the error word gets MC_DEVERR_SPIN and false returns
+// (the caller then stops; every workgroup ends the same way, at this or its
+// next barrier).  s_ok: one word of LDS.
+__device__ inline bool grid_barrier(uint32_t *ctr, uint32_t target, uint32_t *err,
+                                    uint32_t *s_ok) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0, ok = 1;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpinLimit) {
+                flag_error(err, MC_DEVERR_SPIN);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return *s_ok != 0;
 }
 
 // Move n (<= SLOTS * kBlock) elements: element x = load(x) goes to

@@ -467,6 +467,29 @@ def test_prefix_sort_fallback_hash_route():
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+@pytest.mark.parametrize("vtype,nd", [("u64", 300_000), ("u64", 1_500_000),
+                                      ("str16", 300_000), ("u32", 2_000_000)])
+def test_full_sort_grid_shapes(vtype, nd):
+    """The full sort runs as one launch of at most one workgroup per compute
+    unit that strides over tiles and digits: deltas of 147-977 sort tiles
+    (fewer tiles than digits, more tiles than workgroups), almost all values
+    behind one 2-byte prefix so that the full sort must run."""
+    rng = np.random.default_rng(93)
+    base = gen.random_column(rng, vtype, 2000, 10_000, 0)
+    if vtype == "str16":
+        d = rng.integers(0x20, 0x7F, size=(nd, 16), dtype=np.uint8)
+        d[:, 0], d[:, 1] = ord("q"), ord("r")
+    elif vtype == "u32":
+        d = (np.uint32(0x4321) << np.uint32(16)) | rng.integers(0, 1 << 16, nd).astype(np.uint32)
+    else:
+        d = (np.uint64(0x4321) << np.uint64(48)) | rng.integers(0, 1 << 48, nd, dtype=np.uint64)
+    d = np.concatenate([d, gen.random_values(rng, vtype, 30)])
+    d = d[rng.permutation(d.shape[0])]
+    col = gen.Column(vtype, base.u_m, base.main_packed, base.n_main, base.w, d)
+    say(f"case full sort grid shapes {vtype} nd={col.n_delta}")
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
 def _seam_delta(rng, vtype, long_runs):
     """256 runs of values sharing their leading byte (the run number), the
     rest random, shuffled: with a prefix-run target of 1024 the prefix sort
