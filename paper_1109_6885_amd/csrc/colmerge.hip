@@ -123,7 +123,7 @@ struct ColLayout {
              merge_status = 0, mbound = 0, dcount = 0, htab = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
-             drank = 0, x_d = 0, x_m = 0, xdev = 0, rep = 0, dindex = 0, dkeys = 0, drankd = 0,
+             drank = 0, x_d = 0, x_m = 0, xdev = 0, xsp = 0, rep = 0, dindex = 0, dkeys = 0, drankd = 0,
              b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
@@ -204,6 +204,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.x_d = b.take(nd * 4);
     L.x_m = b.take(n_um * 4);
     L.xdev = b.take(n_um * 2);
+    L.xsp = b.take(ceil_div(n_um, mc::kXspBlock) * 16);
     if (L.hashed && !L.indexed) {
         L.rep = b.take(nd * 4);
         L.dindex = b.take(nd * 4);
@@ -283,6 +284,7 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.u_d = zb + L.u_d;
     C.drank = reinterpret_cast<uint32_t *>(zb + L.drank);
     C.xdev = L.xc_tiles ? reinterpret_cast<int16_t *>(zb + L.xdev) : nullptr;
+    C.xsp = L.xc_tiles ? reinterpret_cast<uint4 *>(zb + L.xsp) : nullptr;
     C.xflag = reinterpret_cast<uint32_t *>(za + L.xflag);
     set_hash_fields(C, za, zb, L);
     return C;
@@ -514,7 +516,8 @@ __global__ __launch_bounds__(256) void k1_naive(mc::ColDesc C) {
     mc::naive_tile<T>(C, blockIdx.x, smem);
 }
 __global__ __launch_bounds__(256) void k1_xcompact(mc::ColDesc C) {
-    mc::xcompact_tile(C, blockIdx.x);
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::XCompactSmem)];
+    mc::xcompact_tile(C, blockIdx.x, smem);
 }
 template <int CODES>
 __global__ __launch_bounds__(256) void k1_repack(mc::ColDesc C) {
@@ -679,8 +682,9 @@ __global__ __launch_bounds__(256) void kn_merge(Batch B) {
     mc::merge_tile<T>(B.cols[j], smem);
 }
 __global__ __launch_bounds__(256) void kn_xcompact(Batch B) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::XCompactSmem)];
     const uint32_t j = find_col(B, blockIdx.x);
-    mc::xcompact_tile(B.cols[j], blockIdx.x - B.map[j]);
+    mc::xcompact_tile(B.cols[j], blockIdx.x - B.map[j], smem);
 }
 template <int CODES>
 __global__ __launch_bounds__(256) void kn_repack(Batch B) {

@@ -212,7 +212,9 @@ struct ColDesc {
     void *u_d;                 // U_D
     uint32_t *drank;           // index in U_D of every delta row
     int16_t *xdev;             // compact X_M (see repack.hpp), n_um entries, or null
-    uint32_t *xflag;           // nonzero: a compact entry overflowed, use x_m (zeroed)
+    uint4 *xsp;                // sparse X_M records (see repack.hpp), one per 128 codes, or null
+    uint32_t *xflag;           // [0] nonzero: a compact entry overflowed, use x_m;
+                               // [1] sparse records that overflowed (zeroed)
     // Step 1(a) by hashing first (see hash.hpp); unused when htab is null
     const void *sort_src;      // input of radix pass 0 (delta, or the distinct values)
     const uint64_t *sort_n;    // device count of values to sort, or null for nd

@@ -64,22 +64,122 @@ __device__ __forceinline__ uint64_t xm_line(uint64_t c, uint64_t A) {
     return (hi << 32) | (lo >> 32);
 }
 
-__device__ inline void xcompact_tile(const ColDesc &C, uint64_t t) {
+// ---------------------------------------------------------------------------
+// Sparse X_M.  When few new delta values fall between neighbouring U_M
+// entries (a large main dictionary and a small delta), g(c) = X_M[c] - c is
+// nearly constant over runs of codes.  One 16-byte record per block of 128
+// codes then holds g at the block's first code (bits 0-29; bit 31 flags an
+// overflowed record) and up to 12 insertion offsets, one byte each (unused:
+// 0xFF): offset i in 1..127 appears once for every new value between
+// U_M[c0 + i - 1] and U_M[c0 + i], where c0 is the block's first code.  Then
+// g(c0 + j) = g(c0) + (number of offsets <= j), exactly.  The records take
+// n_um / 8 bytes, a sixteenth of the 16-bit deviation table, so the tables of
+// dictionaries up to about 256K entries stay in a compute unit's L1 and those
+// of about 30M entries in one XCD's L2, where the 16-bit table would need the
+// MALL.  A block with more than 12 insertions is flagged, and the re-encode
+// reads X_M itself for its codes.
+// ---------------------------------------------------------------------------
+
+constexpr int kXspBlock = 128;            // codes per record
+constexpr int kXspSlots = 12;             // insertion offsets per record
+constexpr uint32_t kXspOver = 1u << 31;   // record flag: more than kXspSlots insertions
+constexpr uint64_t kXspMinDict = 1u << 14;  // smaller dictionaries keep the 16-bit table (L1)
+
+// Are the sparse records worth building?  They need a large enough
+// dictionary (below kXspMinDict the 16-bit table already sits in L1) and few
+// new values per block: at more than 8 on average (c2: about 110) most
+// records would overflow, and building them would only cost time.
+constexpr uint64_t kXspMaxMean = 8;
+__device__ __forceinline__ bool xsp_build(const ColDesc &C) {
+    if (!C.xsp || C.n_um < kXspMinDict) return false;
+    const uint64_t added = C.result->new_dict_len - C.n_um;  // new delta values
+    return added * kXspBlock <= kXspMaxMean * C.n_um;
+}
+// Does the re-encode of this column read them?  When they were built and at
+// most 1 in 32 of them overflowed.
+__device__ __forceinline__ bool xsp_use(const ColDesc &C) {
+    if (!xsp_build(C)) return false;
+    const uint64_t nrec = (C.n_um + kXspBlock - 1) / kXspBlock;
+    return (uint64_t)C.xflag[1] * 32u <= nrec;
+}
+
+// Number of offset bytes of word x that are <= j, for jj = j * 0x01010101 |
+// 0x80808080 and 0 <= j <= 127.  Per byte, (128 + j) - (x & 127) lies in
+// [1, 255], so the 32-bit subtraction borrows across no byte; its bit 7 is
+// set exactly when x & 127 <= j, and ~x clears it for unused bytes (0xFF).
+__device__ __forceinline__ uint32_t xsp_le(uint32_t x, uint32_t jj) {
+    return (uint32_t)__popc((jj - (x & 0x7F7F7F7Fu)) & ~x & 0x80808080u);
+}
+__device__ __forceinline__ uint32_t xsp_lookup(const uint4 &r, uint32_t c) {
+    const uint32_t jj = (c & (kXspBlock - 1)) * 0x01010101u | 0x80808080u;
+    return c + r.x + xsp_le(r.y, jj) + xsp_le(r.z, jj) + xsp_le(r.w, jj);
+}
+
+// LDS of one X_M compaction tile: its X_M entries, one pad word after every
+// 128 (entry j at j + j / 128), so that the 32 threads walking the records'
+// blocks side by side read 32 different banks.
+struct XCompactSmem { uint32_t x[kXCompactTile + kXCompactTile / kXspBlock]; };
+__device__ __forceinline__ uint32_t xs_at(uint32_t j) { return j + j / kXspBlock; }
+
+// Both compact forms of one tile of X_M: the 16-bit deviations of every
+// entry and, if the column has room for them, the sparse records of the
+// tile's 32 blocks.
+__device__ inline void xcompact_tile(const ColDesc &C, uint64_t t, char *smem) {
+    uint32_t *s_x = reinterpret_cast<XCompactSmem *>(smem)->x;
+    const uint64_t c0 = t * kXCompactTile;
+    if (c0 >= C.n_um) return;
+    const uint32_t tn = (uint32_t)min<uint64_t>(kXCompactTile, C.n_um - c0);
+    stage_all<kXCompactTile / kBlock>(
+        tn, [&](uint32_t j) { return C.x_m[c0 + j]; }, [&](uint32_t j, uint32_t v) { s_x[xs_at(j)] = v; });
+    __syncthreads();
     const uint64_t A = xm_line_slope(C);
     bool bad = false;
-    for (uint32_t j = threadIdx.x; j < kXCompactTile; j += kBlock) {
-        const uint64_t c = t * kXCompactTile + j;
-        if (c < C.n_um) {
-            const int64_t dev = (int64_t)C.x_m[c] - (int64_t)c - (int64_t)xm_line(c, A);
-            if (dev < -32768 || dev > 32767) {
-                bad = true;
-                C.xdev[c] = 0;
-            } else {
-                C.xdev[c] = (int16_t)dev;
-            }
+    for (uint32_t j = threadIdx.x; j < tn; j += kBlock) {
+        const uint64_t c = c0 + j;
+        const int64_t dev = (int64_t)s_x[xs_at(j)] - (int64_t)c - (int64_t)xm_line(c, A);
+        if (dev < -32768 || dev > 32767) {
+            bad = true;
+            C.xdev[c] = 0;
+        } else {
+            C.xdev[c] = (int16_t)dev;
         }
     }
-    if (bad) atomicOr(C.xflag, 1u);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(C.xflag, 1u);
+    if (!xsp_build(C)) return;  // the re-encode will not read them
+    // one thread per record (lanes 0-31 of wave 0), walking its block's
+    // entries in LDS
+    const uint32_t b = threadIdx.x;
+    if (b >= kXCompactTile / kXspBlock) return;
+    bool over = false;
+    if (b * kXspBlock < tn) {
+        const uint32_t r0 = b * kXspBlock;
+        const uint32_t rn = min<uint32_t>(kXspBlock, tn - r0);
+        uint64_t lo = ~0ull;  // offset slots 0-7
+        uint32_t hi = ~0u;    // offset slots 8-11
+        uint32_t k = 0;
+        uint32_t prev = s_x[xs_at(r0)];
+        for (uint32_t i = 1; i < rn; i++) {
+            const uint32_t x = s_x[xs_at(r0 + i)];
+            uint32_t gap = x - prev - 1u;  // new values between U_M[c - 1] and U_M[c]
+            prev = x;
+            for (; gap && k < (uint32_t)kXspSlots; gap--, k++) {
+                if (k < 8)
+                    lo = (lo & ~(0xFFull << (8 * k))) | ((uint64_t)i << (8 * k));
+                else
+                    hi = (hi & ~(0xFFu << (8 * (k - 8)))) | (i << (8 * (k - 8)));
+            }
+            if (gap) {  // more than kXspSlots insertions: the record is not used
+                over = true;
+                break;
+            }
+        }
+        const uint32_t g0 = s_x[xs_at(r0)] - (uint32_t)(c0 + r0);  // < 2^30: at most N_D new values
+        C.xsp[(c0 + r0) / kXspBlock] =
+            make_uint4(g0 | (over ? kXspOver : 0u), (uint32_t)lo, (uint32_t)(lo >> 32), hi);
+    }
+    // one count per tile (a column like c2 overflows every record)
+    const uint32_t n_over = (uint32_t)__popcll(__ballot(over));
+    if (b == 0 && n_over) atomicAdd(&C.xflag[1], n_over);
 }
 
 // Stage the packed main words of the tile starting at row c0 into LDS with
@@ -182,20 +282,19 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     const bool compact = C.xdev != nullptr && *C.xflag == 0;
     const uint64_t A = compact ? xm_line_slope(C) : 0;
     const uint32_t i0 = threadIdx.x * PER;  // tile-local index of the thread's first code
-    const uint32_t *tab[PER];
     uint32_t idx[PER];
+    uint32_t mm = 0, dm = 0;  // bit j: row j reads X_M (a main row) / X_D (a delta row)
     uint32_t bad = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
         const uint32_t i = i0 + j;
         const uint64_t g = c0 + i;
-        tab[j] = nullptr;
         idx[j] = 0;
         if (i < tn) {
             if (g < C.n_main) {
                 const uint32_t c = decode_code(s_in, i, w, mask);
                 if (c < C.n_um) {
-                    tab[j] = C.x_m;
+                    mm |= 1u << j;
                     idx[j] = c;
                 } else {
                     bad |= MC_DEVERR_CODE_RANGE;
@@ -203,7 +302,7 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
             } else {
                 const uint32_t r = C.drank[g - C.n_main];
                 if (r < n_ud) {
-                    tab[j] = C.x_d;
+                    dm |= 1u << j;
                     idx[j] = r;
                 } else {
                     bad |= MC_DEVERR_DELTA_RANGE;
@@ -212,18 +311,43 @@ __device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
         }
     }
     uint32_t nc[PER];
-    if (compact) {
+    if (xsp_use(C)) {
+        // main rows: a 16-byte record per 128 codes (X_M itself for the codes
+        // of an overflowed record); delta rows gather X_D.  Groups of 4 rows,
+        // so that the records in flight take 16 registers, not 4 * PER.
+        constexpr int GRP = PER < 4 ? PER : 4;
+#pragma unroll
+        for (int j0 = 0; j0 < PER; j0 += GRP) {
+            uint4 rec[GRP];
+#pragma unroll
+            for (int k = 0; k < GRP; k++) {
+                const int j = j0 + k;
+                nc[j] = 0u;
+                if ((mm >> j) & 1u)
+                    rec[k] = C.xsp[idx[j] / kXspBlock];
+                else if ((dm >> j) & 1u)
+                    nc[j] = C.x_d[idx[j]];
+            }
+#pragma unroll
+            for (int k = 0; k < GRP; k++) {
+                const int j = j0 + k;
+                if ((mm >> j) & 1u)
+                    nc[j] = (rec[k].x & kXspOver) ? C.x_m[idx[j]] : xsp_lookup(rec[k], idx[j]);
+            }
+        }
+    } else if (compact) {
         // main rows: X_M[c] = c + a(c) + d(c); delta rows gather X_D
 #pragma unroll
         for (int j = 0; j < PER; j++) {
-            if (tab[j] == C.x_m)
+            if ((mm >> j) & 1u)
                 nc[j] = idx[j] + (uint32_t)xm_line(idx[j], A) + (uint32_t)(int32_t)C.xdev[idx[j]];
             else
-                nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+                nc[j] = ((dm >> j) & 1u) ? C.x_d[idx[j]] : 0u;
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < PER; j++) nc[j] = tab[j] ? tab[j][idx[j]] : 0u;
+        for (int j = 0; j < PER; j++)
+            nc[j] = ((mm >> j) & 1u) ? C.x_m[idx[j]] : ((dm >> j) & 1u) ? C.x_d[idx[j]] : 0u;
     }
     if (bad) flag_error(C.err, bad);
 

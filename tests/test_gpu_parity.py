@@ -490,6 +490,39 @@ def test_full_sort_grid_shapes(vtype, nd):
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+@pytest.mark.parametrize("vtype,n_um,nd,frac_new,clusters,size", [
+    ("u64", 20_000, 3_000, 0.3, 0, 0),       # sparse records, few insertions per block
+    ("u64", 300_001, 20_000, 0.5, 0, 0),     # many compaction tiles, ragged last record
+    ("u64", 100_000, 5_000, 0.2, 1, 400),    # 400 new values in one gap: an overflowed record
+    ("u32", 50_000, 2_000, 1.0, 1, 13),      # 13 new values in one gap: one past the slots
+    ("str16", 70_000, 8_000, 0.4, 0, 0),
+    ("u64", 16_384, 0, 0.0, 5, 13),          # 5 of 128 records overflow: the 16-bit table serves
+    ("u64", 16_384, 60_000, 1.0, 0, 0),      # dense insertions: no records built
+])
+def test_sparse_xm_records(vtype, n_um, nd, frac_new, clusters, size):
+    """Main dictionaries of at least 2^14 entries with few new values per
+    block of 128 codes: the re-encode reads X_M from one 16-byte record per
+    block (base and insertion offsets); codes of overflowed records read X_M
+    itself.  New values packed into one gap of U_M overflow a record; with
+    more than 1 in 32 records overflowed, or many new values per block, the
+    16-bit table is used instead."""
+    rng = np.random.default_rng(94)
+    col = gen.random_column(rng, vtype, n_um, 200_000, nd, frac_new)
+    if clusters:
+        parts = [col.delta]
+        for q in range(clusters):
+            k = n_um * (q + 1) // (clusters + 2)
+            lo = int(col.u_m[k])
+            extra = np.arange(lo + 1, lo + 1 + size, dtype=np.uint64)
+            assert int(extra[-1]) < int(col.u_m[k + 1])
+            parts += [extra.astype(col.u_m.dtype), extra[:3].astype(col.u_m.dtype)]
+        d = np.concatenate(parts)
+        col = gen.Column(vtype, col.u_m, col.main_packed, col.n_main, col.w,
+                         d[rng.permutation(d.shape[0])])
+    say(f"case sparse X_M records {vtype} n_um={n_um} nd={col.n_delta} clusters={clusters}x{size}")
+    assert_same(gpu_merge(col), ora_merge(col))
+
+
 def _seam_delta(rng, vtype, long_runs):
     """256 runs of values sharing their leading byte (the run number), the
     rest random, shuffled: with a prefix-run target of 1024 the prefix sort
