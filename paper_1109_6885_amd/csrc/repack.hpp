@@ -118,7 +118,10 @@ __device__ __forceinline__ uint32_t xsp_lookup(const uint4 &r, uint32_t c) {
 // LDS of one X_M compaction tile: its X_M entries, one pad word after every
 // 128 (entry j at j + j / 128), so that the 32 threads walking the records'
 // blocks side by side read 32 different banks.
-struct XCompactSmem { uint32_t x[kXCompactTile + kXCompactTile / kXspBlock]; };
+struct XCompactSmem {
+    uint32_t x[kXCompactTile + kXCompactTile / kXspBlock];
+    uint32_t slot[kXCompactTile / kXspBlock * 4];  // each record's offset bytes (12 used)
+};
 __device__ __forceinline__ uint32_t xs_at(uint32_t j) { return j + j / kXspBlock; }
 
 // Both compact forms of one tile of X_M: the 16-bit deviations of every
@@ -146,40 +149,44 @@ __device__ inline void xcompact_tile(const ColDesc &C, uint64_t t, char *smem) {
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(C.xflag, 1u);
     if (!xsp_build(C)) return;  // the re-encode will not read them
-    // one thread per record (lanes 0-31 of wave 0), walking its block's
-    // entries in LDS
-    const uint32_t b = threadIdx.x;
-    if (b >= kXCompactTile / kXspBlock) return;
-    bool over = false;
-    if (b * kXspBlock < tn) {
-        const uint32_t r0 = b * kXspBlock;
-        const uint32_t rn = min<uint32_t>(kXspBlock, tn - r0);
-        uint64_t lo = ~0ull;  // offset slots 0-7
-        uint32_t hi = ~0u;    // offset slots 8-11
-        uint32_t k = 0;
-        uint32_t prev = s_x[xs_at(r0)];
-        for (uint32_t i = 1; i < rn; i++) {
-            const uint32_t x = s_x[xs_at(r0 + i)];
-            uint32_t gap = x - prev - 1u;  // new values between U_M[c - 1] and U_M[c]
-            prev = x;
-            for (; gap && k < (uint32_t)kXspSlots; gap--, k++) {
-                if (k < 8)
-                    lo = (lo & ~(0xFFull << (8 * k))) | ((uint64_t)i << (8 * k));
-                else
-                    hi = (hi & ~(0xFFu << (8 * (k - 8)))) | (i << (8 * (k - 8)));
-            }
-            if (gap) {  // more than kXspSlots insertions: the record is not used
-                over = true;
-                break;
-            }
-        }
-        const uint32_t g0 = s_x[xs_at(r0)] - (uint32_t)(c0 + r0);  // < 2^30: at most N_D new values
-        C.xsp[(c0 + r0) / kXspBlock] =
-            make_uint4(g0 | (over ? kXspOver : 0u), (uint32_t)lo, (uint32_t)(lo >> 32), hi);
+    // 8 threads per record (the tile's 32 records side by side): each takes
+    // 16 consecutive entries of the block and counts the new values between
+    // them, a prefix over the 8 counts gives each its first slot, and each
+    // writes its insertion offsets into the record's slot bytes in LDS.
+    uint32_t *s_slot = reinterpret_cast<XCompactSmem *>(smem)->slot;
+    for (uint32_t x = threadIdx.x; x < kXCompactTile / kXspBlock * 4; x += kBlock) s_slot[x] = ~0u;
+    const uint32_t rb = threadIdx.x / 8, q = threadIdx.x % 8;
+    const uint32_t r0 = rb * kXspBlock;                        // the record's first entry
+    const uint32_t rn = r0 < tn ? min<uint32_t>(kXspBlock, tn - r0) : 0u;
+    const uint32_t i_beg = q ? q * 16 : 1, i_end = min<uint32_t>(q * 16 + 16, rn);
+    uint32_t cnt = 0;  // new values before the entries i_beg .. i_end - 1
+    for (uint32_t i = i_beg; i < i_end; i++)
+        cnt += s_x[xs_at(r0 + i)] - s_x[xs_at(r0 + i - 1)] - 1u;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, 8);
+        if (q >= (uint32_t)d) incl += v;
     }
-    // one count per tile (a column like c2 overflows every record)
+    const uint32_t total = __shfl(incl, 7, 8);  // insertions in the whole block
+    __syncthreads();  // slots initialised
+    if (total <= (uint32_t)kXspSlots && cnt) {
+        uint8_t *slot = reinterpret_cast<uint8_t *>(s_slot) + rb * 16;
+        uint32_t k = incl - cnt;
+        for (uint32_t i = i_beg; i < i_end; i++)
+            for (uint32_t g = s_x[xs_at(r0 + i)] - s_x[xs_at(r0 + i - 1)] - 1u; g; g--)
+                slot[k++] = (uint8_t)i;
+    }
+    __syncthreads();
+    const bool over = rn && q == 0 && total > (uint32_t)kXspSlots;
+    if (rn && q == 0) {
+        const uint32_t g0 = s_x[xs_at(r0)] - (uint32_t)(c0 + r0);  // < 2^30: at most N_D new values
+        C.xsp[(c0 + r0) / kXspBlock] = make_uint4(g0 | (over ? kXspOver : 0u), s_slot[rb * 4],
+                                                  s_slot[rb * 4 + 1], s_slot[rb * 4 + 2]);
+    }
+    // one count per wave (a column with many new values overflows most records)
     const uint32_t n_over = (uint32_t)__popcll(__ballot(over));
-    if (b == 0 && n_over) atomicAdd(&C.xflag[1], n_over);
+    if (lane_id() == 0 && n_over) atomicAdd(&C.xflag[1], n_over);
 }
 
 // Stage the packed main words of the tile starting at row c0 into LDS with
