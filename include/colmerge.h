@@ -47,7 +47,13 @@
  *
  * Threading: an mc_ctx is used from one host thread at a time.  Different
  * contexts, or one context on different streams with different scratch
- * buffers, may run concurrently.
+ * buffers, may run concurrently.  One kernel of a single-column merge (the
+ * full sort that Step 1(a) falls back on when values share long prefixes)
+ * needs all of its workgroups resident at once; it launches at most one per
+ * two compute units, so six such merges can run it side by side (HIP runs
+ * at most 4 kernels at a time with its default of 4 hardware queues).  Should
+ * more ever compete, its bounded waits end with MC_DEVERR_SPIN in
+ * mc_result.error instead of hanging.
  */
 #ifndef COLMERGE_H
 #define COLMERGE_H

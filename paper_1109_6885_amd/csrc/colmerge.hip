@@ -429,10 +429,10 @@ __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int kind, int
 // when the prefix sort left the values out of order; otherwise every
 // workgroup returns at once, where a launch per phase and pass (3 x 4, 8 or
 // 16 of them) would each cost a kernel boundary.  The grid has at most one
-// workgroup per compute unit, so all are resident together; they stride over
-// the tiles (or digits) of each phase, with a grid-wide barrier between
-// phases.  Every pass reads what the previous pass wrote, exactly as the
-// per-phase launches do.
+// workgroup per two compute units, so all are resident together, also beside
+// the same kernel of other merges; they stride over the tiles (or digits) of
+// each phase, with a grid-wide barrier between phases.  Every pass reads
+// what the previous pass wrote, exactly as the per-phase launches do.
 template <class T>
 __global__ __launch_bounds__(256) void k1_full_sort(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
@@ -779,7 +779,10 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, uint32_t c
     // return at once unless the check failed
     for (int again = 0; again < 2; again++) {
         if (again && L.sort_tiles) {
-            const uint32_t grid = std::min<uint32_t>(L.sort_tiles, cus ? cus : 1u);
+            // at most half the CUs: a CU holds at least 3 of its workgroups
+            // (VGPRs), so the launches of up to 6 concurrent merges on other
+            // streams are resident together
+            const uint32_t grid = std::min<uint32_t>(L.sort_tiles, cus > 1 ? cus / 2 : 1u);
             hipLaunchKernelGGL(k1_full_sort<T>, dim3(grid), dim3(mc::kBlock), 0, s, C);
             MC_LAUNCHED("k1_full_sort");
         }

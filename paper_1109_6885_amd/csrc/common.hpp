@@ -285,7 +285,7 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
 }
 
 // Barrier over every workgroup of a launch whose workgroups are all resident
-// at once (the caller launches at most one per compute unit).  ctr is a
+// at once (the caller launches at most one per two compute units).  ctr is a
 // zeroed word that only grows: the caller's b-th barrier passes target =
 // b * gridDim.x.  The workgroups may sit on different XCDs, whose L2 caches
 // are not coherent with each other, so every thread releases its writes to

@@ -490,6 +490,36 @@ def test_full_sort_grid_shapes(vtype, nd):
     assert_same(gpu_merge(col), ora_merge(col))
 
 
+def test_full_sort_concurrent_streams():
+    """Six merges whose deltas (1M str16 rows, almost all behind one 2-byte
+    prefix) need the full sort, enqueued on six streams at once: their
+    one-launch full sorts (512 workgroups each) compete for the compute
+    units, so not all of a launch's workgroups need be resident together;
+    each result must equal the oracle's."""
+    rng = np.random.default_rng(95)
+    cols = []
+    for i in range(6):
+        base = gen.random_column(rng, "str16", 3000, 50_000, 0)
+        d = rng.integers(0x20, 0x7F, size=(1_000_000, 16), dtype=np.uint8)
+        d[:, 0], d[:, 1] = ord("k"), ord("a") + i
+        d = np.concatenate([d, gen.random_values(rng, "str16", 30)])
+        cols.append(gen.Column("str16", base.u_m, base.main_packed, base.n_main, base.w,
+                               d[rng.permutation(d.shape[0])]))
+    say("case full sort on six streams at once, str16, 1M delta rows each")
+    dev = torch.cuda.current_device()
+    streams = [torch.cuda.Stream() for _ in cols]
+    ctxs = [cm.Context(dev) for _ in cols]
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs = [cm.alloc_output(d, tables=True) for d in dcols]
+    scratch = [cm.alloc_scratch(cm.merge_bounds(d, x)[2]) for d, x in zip(dcols, ctxs)]
+    torch.cuda.synchronize()
+    for d, o, sc, s, x in zip(dcols, outs, scratch, streams, ctxs):
+        cm.merge_column(d, out=o, scratch=sc, stream=s, ctx=x)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        assert_same(o.fetch(), ora_merge(c))
+
+
 @pytest.mark.parametrize("vtype,n_um,nd,frac_new,clusters,size", [
     ("u64", 20_000, 3_000, 0.3, 0, 0),       # sparse records, few insertions per block
     ("u64", 300_001, 20_000, 0.5, 0, 0),     # many compaction tiles, ragged last record
