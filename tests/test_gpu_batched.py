@@ -67,6 +67,38 @@ def test_batched_partitioned_merge():
         check_col(c, o.fetch())
 
 
+def test_batched_sparse_xm_records():
+    """Columns whose re-encode reads the sparse X_M records (dictionaries of
+    16K-300K entries with few new values; one with new values bunched into
+    one gap so that a record overflows) between columns that keep the 16-bit
+    table (dense insertions, small dictionaries), in one batched call and
+    replayed from a graph."""
+    rng = np.random.default_rng(96)
+    cols = [gen.random_column(rng, "u64", 20_000, 150_000, 3_000, 0.3),
+            gen.random_column(rng, "u32", 300, 2000, 100, 0.5),
+            gen.random_column(rng, "str16", 70_000, 100_000, 8_000, 0.4),
+            gen.random_column(rng, "u64", 16_384, 80_000, 60_000, 1.0),
+            gen.random_column(rng, "u32", 300_001, 120_000, 20_000, 0.5)]
+    c = gen.random_column(rng, "u64", 100_000, 90_000, 5_000, 0.2)
+    lo = int(c.u_m[40_000])
+    extra = np.arange(lo + 1, lo + 401, dtype=np.uint64)
+    assert int(extra[-1]) < int(c.u_m[40_001])
+    d = np.concatenate([c.delta, extra])
+    cols.append(gen.Column("u64", c.u_m, c.main_packed, c.n_main, c.w,
+                           d[rng.permutation(d.shape[0])]))
+    say(f"case batched sparse X_M records, {len(cols)} columns")
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, graph = cm.merge_columns_batched(dcols, graph=True)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    for _ in range(2):
+        graph.launch()
+        torch.cuda.synchronize()
+        for c, o in zip(cols, outs):
+            check_col(c, o.fetch())
+
+
 def test_batched_prefix_sort_fallback():
     """Columns whose values share their leading bytes between ordinary
     columns, in one batch; twice, through a graph, so the sort's counters
