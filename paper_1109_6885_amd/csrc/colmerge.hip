@@ -180,7 +180,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.n_ud = z.take(8);
     L.err = z.take(8);
     L.xflag = z.take(8);
-    L.gh = z.take((uint64_t)L.passes * 256 * 4);
+    L.gh = z.take((uint64_t)mc::kGhCopies * L.passes * 256 * 4);
     L.trivial = z.take(16 * 4);
     L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
     L.emit_status2 = z.take((uint64_t)L.emit_tiles * 8);

@@ -54,6 +54,11 @@ template <class T>
 __host__ __device__ constexpr int sort_tile() { return kBlock * SortCfg<T>::kItems; }
 
 constexpr int kHistChunk = 4096;  // delta values per workgroup in hist_tile
+// Copies of a column's digit histograms that hist_tile's workgroups add
+// into (workgroup b into copy b % kGhCopies) and hist_scan_col sums: the
+// global atomic adds on each counter then come from 1/kGhCopies of the
+// workgroups.
+constexpr int kGhCopies = 8;
 
 // Runs of equal prefix longer than this are not ordered by the windows (they
 // keep their place if already ordered, else the full sort takes over).
@@ -153,8 +158,9 @@ __device__ void hist_tile(const ColDesc &C, uint32_t blk, char *smem) {
         }
     }
     __syncthreads();
+    uint32_t *gh = C.gh + (uint64_t)(blk % kGhCopies) * (P * 256);
     for (int i = threadIdx.x; i < P * 256; i += kBlock)
-        if (S.h[i]) atomicAdd(&C.gh[i], S.h[i]);
+        if (S.h[i]) atomicAdd(&gh[i], S.h[i]);
 }
 
 template <class T>
@@ -171,7 +177,12 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
         uint32_t v[4], run = 0, nz = 0, mx = 0;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            v[q] = C.gh[p * 256 + 4 * lane + q];
+            v[q] = 0;
+#pragma unroll
+            for (int c = 0; c < kGhCopies; c++) v[q] += C.gh[(c * P + p) * 256 + 4 * lane + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
             run += v[q];
             nz += v[q] ? 1u : 0u;
             mx = max(mx, v[q]);
