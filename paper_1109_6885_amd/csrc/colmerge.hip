@@ -79,11 +79,19 @@ uint32_t value_len(int32_t type) {
     }
 }
 
-uint32_t merge_tile_of(int32_t type) {
+// Merged positions per merge tile: the batched merge's tiles, or a
+// single-column merge's (larger for 4- and 8-byte values).
+uint32_t merge_tile_of(int32_t type, bool batched) {
     switch (type) {
-        case MC_U32: return mc::merge_tile<mc::TU32>();
-        case MC_U64: return mc::merge_tile<mc::TU64>();
-        default: return mc::merge_tile<mc::TS16>();
+        case MC_U32:
+            return batched ? mc::merge_tile<mc::TU32>()
+                           : mc::merge_tile<mc::TU32, mc::MergeCfg<mc::TU32>::kItemsSingle>();
+        case MC_U64:
+            return batched ? mc::merge_tile<mc::TU64>()
+                           : mc::merge_tile<mc::TU64, mc::MergeCfg<mc::TU64>::kItemsSingle>();
+        default:
+            return batched ? mc::merge_tile<mc::TS16>()
+                           : mc::merge_tile<mc::TS16, mc::MergeCfg<mc::TS16>::kItemsSingle>();
     }
 }
 uint32_t sort_tile_of(int32_t type) {
@@ -153,7 +161,7 @@ const mc_tuning kDefaultTuning = {2048u, 32u, 0u, 0u};
 
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
                      bool allow_hash = true, const mc_tuning &tune = kDefaultTuning,
-                     bool indexed = false) {
+                     bool indexed = false, bool batched = false) {
     ColLayout L;
     L.repack_codes = tune.repack_codes;
     L.prefix_run = tune.prefix_run;
@@ -171,7 +179,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.sort_tiles = (uint32_t)ceil_div(nd, sort_tile_of(type));
     L.emit_tiles = (uint32_t)ceil_div(nd, mc::kEmitTile);
     L.hist_tiles = (uint32_t)ceil_div(nd, mc::kHistChunk);
-    L.merge_tiles = ceil_div(n_um + nd, merge_tile_of(type));
+    L.merge_tiles = ceil_div(n_um + nd, merge_tile_of(type, batched));
     L.repack_tiles = ceil_div(n_main + nd, L.repack_codes);
     L.xc_tiles = n_main ? ceil_div(n_um, mc::kXCompactTile) : 0;
     Carver z;
@@ -503,12 +511,13 @@ __global__ __launch_bounds__(256) void k1_rank_rows(mc::ColDesc C) {
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_merge_part(mc::ColDesc C) {
-    mc::merge_partition<T>(C, blockIdx.x);
+    mc::merge_partition<T, mc::MergeCfg<T>::kItemsSingle>(C, blockIdx.x);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_merge(mc::ColDesc C) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T>)];
-    mc::merge_tile<T>(C, smem);
+    constexpr int kItems = mc::MergeCfg<T>::kItemsSingle;
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::MergeSmem<T, kItems>)];
+    mc::merge_tile<T, kItems>(C, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_naive(mc::ColDesc C) {
@@ -1046,7 +1055,8 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
         if (rc) return rc;
         // each column takes the Step 1(a) route it would take alone
         P.L[i] = col_layout(ins[i].type, ins[i].main_dict_len, ins[i].delta_rows,
-                            ins[i].main_rows, /*allow_hash=*/true, tune);
+                            ins[i].main_rows, /*allow_hash=*/true, tune, /*indexed=*/false,
+                            /*batched=*/true);
         P.z_off[i] = z;
         z += P.L[i].z_size;
         P.b_off[i] = b;

@@ -29,29 +29,40 @@
 
 namespace mc {
 
-// Merged positions per thread, 8 for every value type.  Half the tile for
-// 16-byte values would fit four workgroups in one CU's LDS instead of two,
-// but measured slower on a 10M-entry string dictionary (0.33 ms against
-// 0.26 ms for the dictionary merge step): more tiles, more look-back.
+// Merged positions per thread: 8 in the batched merge (many columns, mostly
+// small: more, smaller tiles keep more workgroups per CU), 16 in a
+// single-column merge of 4- and 8-byte values (one large merge: half the
+// tiles, half the look-back; c2's dictionary merge 38 -> 28.5 us, while
+// the 300-column batch measured 10.27 -> 10.43 ms with 16).  Half the tile
+// for 16-byte values would fit four workgroups in one CU's LDS instead of
+// two, but measured slower on a 10M-entry string dictionary (0.33 ms
+// against 0.26 ms for the dictionary merge step): more tiles, more
+// look-back.
 template <class T>
-struct MergeCfg { static constexpr int kItems = 8; };
+struct MergeCfg {
+    static constexpr int kItems = 8;         // batched
+    static constexpr int kItemsSingle = 16;  // single column
+};
 template <>
-struct MergeCfg<TS16> { static constexpr int kItems = 8; };
-template <class T>
-__host__ __device__ constexpr int merge_tile() { return kBlock * MergeCfg<T>::kItems; }
+struct MergeCfg<TS16> {
+    static constexpr int kItems = 8;
+    static constexpr int kItemsSingle = 8;
+};
+template <class T, int ITEMS = MergeCfg<T>::kItems>
+__host__ __device__ constexpr int merge_tile() { return kBlock * ITEMS; }
 
 constexpr uint32_t kStepA = 0, kStepNew = 1, kStepDup = 2;
 constexpr uint32_t kFromB = 0x8000u;  // > any merge tile: marks an index into b
 
-template <class T>
+template <class T, int ITEMS = MergeCfg<T>::kItems>
 struct MergeSmem {
     // the tile's inputs in one array (a tile holds na + nb <= merge_tile
     // entries): ab[0] = U_M[i0 - 1] (predecessor), ab[1 + x] = U_M[i0 + x]
     // for x < na ("a"), ab[na + 1 + y] = U_D[j0 + y] for y < nb ("b")
-    typename T::N ab[merge_tile<T>() + 1];
-    uint16_t src[merge_tile<T>()];  // output r of the tile: index in a, or kFromB | index in b
-    int16_t xm[merge_tile<T>()];    // tile-relative U' index of a[1 + x]
-    int16_t xd[merge_tile<T>()];    // tile-relative U' index of b[y] (-1: the tile before's last)
+    typename T::N ab[merge_tile<T, ITEMS>() + 1];
+    uint16_t src[merge_tile<T, ITEMS>()];  // output r of the tile: index in a, or kFromB | index in b
+    int16_t xm[merge_tile<T, ITEMS>()];    // tile-relative U' index of a[1 + x]
+    int16_t xd[merge_tile<T, ITEMS>()];    // tile-relative U' index of b[y] (-1: the tile before's last)
     uint32_t tile;
     uint32_t tmp[kWaves];
     uint64_t i0, i1;
@@ -111,13 +122,13 @@ __device__ __forceinline__ uint64_t co_rank_wave(uint64_t k, uint64_t a, uint64_
 // U_M entries precede merged position q * merge_tile (q = 0 .. tiles), so the
 // merge tiles start without a search through global memory.  Each wave
 // returns on its own; there is no barrier.
-template <class T>
+template <class T, int ITEMS = MergeCfg<T>::kItems>
 __device__ void merge_partition(const ColDesc &C, uint32_t blk) {
     const uint64_t q = (uint64_t)blk * kWaves + wave_id();
     const uint64_t a = C.n_um;
     const uint64_t b = min(*C.n_ud_in, C.nd_max);
     const uint64_t total = a + b;
-    constexpr uint64_t TILE = merge_tile<T>();
+    constexpr uint64_t TILE = merge_tile<T, ITEMS>();
     if (q > (total + TILE - 1) / TILE) return;
     const uint64_t k = min<uint64_t>(q * TILE, total);
     auto gA = [&](uint64_t i) { return T::norm(T::load(C.u_m, i)); };
@@ -126,9 +137,9 @@ __device__ void merge_partition(const ColDesc &C, uint32_t blk) {
     if (lane_id() == 0) C.mbound[q] = r;
 }
 
-template <class T>
+template <class T, int ITEMS = MergeCfg<T>::kItems>
 __device__ void merge_tile(const ColDesc &C, char *smem) {
-    MergeSmem<T> &S = *reinterpret_cast<MergeSmem<T> *>(smem);
+    MergeSmem<T, ITEMS> &S = *reinterpret_cast<MergeSmem<T, ITEMS> *>(smem);
     if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[1], 1u);
     __syncthreads();
     const uint32_t t = S.tile;
@@ -136,8 +147,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     const uint64_t b = min(*C.n_ud_in, C.nd_max);  // never read past U_D's buffer
     const uint64_t cap = C.u_new_cap;
     const uint64_t total = a + b;
-    constexpr int ITEMS = MergeCfg<T>::kItems;
-    const uint64_t k0 = (uint64_t)t * merge_tile<T>();
+    const uint64_t k0 = (uint64_t)t * merge_tile<T, ITEMS>();
     if (k0 >= total) {
         if (t == 0 && threadIdx.x == 0) {  // nothing to merge at all
             C.result->new_dict_len = 0;
@@ -147,7 +157,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
         }
         return;
     }
-    const uint64_t k1 = min<uint64_t>(k0 + merge_tile<T>(), total);
+    const uint64_t k1 = min<uint64_t>(k0 + merge_tile<T, ITEMS>(), total);
     auto gA = [&](uint64_t i) { return T::norm(T::load(C.u_m, i)); };
     auto gB = [&](uint64_t j) { return T::norm(T::load(C.u_d, j)); };
     uint64_t i0, i1;
@@ -181,7 +191,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
         lookback_publish(C.merge_status, t, na);
         const uint64_t tile_prefix = lookback_resolve(C.merge_status, t, na, C.err, &S.lb);
         typedef typename T::K K;
-        constexpr int kSlots = (merge_tile<T>() + kBlock - 1) / kBlock;
+        constexpr int kSlots = (merge_tile<T, ITEMS>() + kBlock - 1) / kBlock;
         K v[kSlots];
 #pragma unroll
         for (int q = 0; q < kSlots; q++) {
@@ -211,7 +221,7 @@ __device__ void merge_tile(const ColDesc &C, char *smem) {
     // b[y] = U_D[j0 + y] as one range of na + 1 + nb loads
     typedef typename T::N N;
     N *const sa = S.ab, *const sb = S.ab + na + 1;
-    constexpr int kStageSlots = (merge_tile<T>() + 1 + kBlock - 1) / kBlock;
+    constexpr int kStageSlots = (merge_tile<T, ITEMS>() + 1 + kBlock - 1) / kBlock;
     stage_all<kStageSlots>(
         na + 1 + nb,
         [&](uint32_t q) -> N {
