@@ -131,8 +131,8 @@ struct ColLayout {
              merge_status = 0, mbound = 0, dcount = 0, htab = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
-             drank = 0, x_d = 0, x_m = 0, xdev = 0, xsp = 0, rep = 0, dindex = 0, dkeys = 0, drankd = 0,
-             b_size = 0;
+             drank = 0, x_d = 0, x_m = 0, xdev = 0, xsp = 0, rep = 0, dindex = 0, dkeys = 0,
+             drankd = 0, b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
     uint32_t repack_codes = mc::kRepackCodes, prefix_run = 0;  // launch shapes
