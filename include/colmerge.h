@@ -168,6 +168,29 @@ int mc_merge_column_naive(mc_ctx *ctx, const mc_column_in *in,
                           const mc_column_out *out, void *scratch,
                           uint64_t scratch_bytes, struct ihipStream_t *stream);
 
+/* ---- allocation-free merge -------------------------------------------- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the merge
+ * of mc_merge_column (same kernels, same results, same outputs) with its
+ * workspace in a device array of MC_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on, from the first mc_ctx_create on that device
+ * until the process ends.  The caller still passes the inputs and outputs.
+ * The call allocates nothing: no hipMalloc / hipFree, no allocating library
+ * routine, no step-timing events (mc_ctx_set_timing does not apply to it).
+ *
+ * Limit: a column whose workspace (scratch_bytes of mc_merge_bounds_ctx on
+ * ctx) exceeds MC_NOALLOC_SCRATCH_BYTES is rejected with MC_E_CAP before
+ * anything is enqueued; 64 MiB holds, e.g., a 1M-row u64 delta against a
+ * 1M-entry dictionary.  Every call on one GPU shares that GPU's array (the
+ * part that must start at zero is cleared by each call on its stream), so
+ * calls whose work overlaps on one GPU -- different streams, or different
+ * host threads -- race; serialize them on one stream. */
+#define MC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int mc_merge_column_noalloc(mc_ctx *ctx, const mc_column_in *in,
+                            const mc_column_out *out,
+                            struct ihipStream_t *stream);
+
 /* ---- single steps (the same kernels as mc_merge_column) --------------- */
 
 /* Step 1(a), modified form (Sections 5.1 and 5.3): sorted unique delta

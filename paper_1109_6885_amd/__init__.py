@@ -274,6 +274,18 @@ def merge_column(col: ColumnInput, out: MergeOutput | None = None,
     return out
 
 
+def merge_column_noalloc(col: ColumnInput, out: MergeOutput, stream=None,
+                         ctx: Context | None = None) -> MergeOutput:
+    """mc_merge_column_noalloc: the merge of one column with the library's
+    own per-device workspace (no allocation in the call; `out` must be
+    allocated beforehand)."""
+    ctx = ctx or context()
+    din, dout = col.descriptor(), out.descriptor()
+    check(load().mc_merge_column_noalloc(ctx.handle, ctypes.byref(din), ctypes.byref(dout),
+                                         _stream(stream)), "mc_merge_column_noalloc")
+    return out
+
+
 def merge_column_naive(col: ColumnInput, out: MergeOutput | None = None,
                        scratch: torch.Tensor | None = None, tables: bool = False,
                        stream=None, ctx: Context | None = None) -> MergeOutput:

@@ -33,7 +33,11 @@ EXPORTS = [
     "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched", "mc_merge_bounds_ctx",
     "mc_delta_index_bytes", "mc_delta_index_reset", "mc_delta_index_append",
     "mc_merge_indexed_bounds", "mc_merge_column_indexed", "mc_merge_batched_bounds_ctx",
+    "mc_merge_column_noalloc",
 ]
+
+# Workspace of mc_merge_column_noalloc (MC_NOALLOC_SCRATCH_BYTES in colmerge.h).
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class McResult(ctypes.Structure):
@@ -102,6 +106,7 @@ def load():
                                                    u64, p]),
         "mc_merge_column": (ctypes.c_int, [p, pin, pout, p, u64, p]),
         "mc_merge_column_naive": (ctypes.c_int, [p, pin, pout, p, u64, p]),
+        "mc_merge_column_noalloc": (ctypes.c_int, [p, pin, pout, p]),
         "mc_delta_dictionary": (ctypes.c_int, [p, i32, p, u64, p, p, p, p, u64, p]),
         "mc_delta_dictionary_scratch": (ctypes.c_int, [i32, u64, pu64]),
         "mc_merge_dictionaries": (ctypes.c_int, [p, i32, p, u64, p, p, u64, p, p, p, u64, p, p,

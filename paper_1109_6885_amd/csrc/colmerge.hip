@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,6 +35,8 @@ struct mc_ctx {
     hipEvent_t meta_event = nullptr;
     // launch shapes (mc_ctx_set_tuning / mc_autotune_batched)
     mc_tuning tune = {2048u, 32u, 0u, 0u};
+    // device address of this device's allocation-free workspace
+    void *noalloc_scratch = nullptr;
 };
 
 struct mc_graph {
@@ -41,9 +44,20 @@ struct mc_graph {
     hipGraphExec_t exec = nullptr;
 };
 
+// Workspace of mc_merge_column_noalloc: one copy per device, held from the
+// library's load until the process ends.  Host code never uses this name as
+// an address (on the host it only names the symbol); the device address of
+// each device's copy comes from hipGetSymbolAddress in mc_ctx_create.
+static __device__ __align__(256) unsigned char noalloc_scratch[MC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
+
+// hipGetSymbolAddress results per device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -910,11 +924,11 @@ int launch_naive(const mc::ColDesc &C, hipStream_t s) {
 template <class T>
 int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out, char *ws,
                    const ColLayout &L, hipStream_t s, bool naive = false,
-                   const mc_delta_index *ix = nullptr) {
+                   const mc_delta_index *ix = nullptr, bool timed = true) {
     mc::ColDesc C = make_desc(in, out, ws, ws + L.z_size, L);
     if (ix) set_index_fields(C, ix);
     hipEvent_t *ev = nullptr;
-    if (ctx->timing) {
+    if (ctx->timing && timed) {
         if (ctx->used == ctx->ev.size()) {
             std::array<hipEvent_t, 5> set{};
             for (auto &e : set) MC_HIP(hipEventCreate(&e));
@@ -1266,6 +1280,30 @@ int mc_ctx_create(int device, mc_ctx **out) {
         return fail(MC_E_HIP, "cannot read the device's compute unit count");
     }
     c->cus = (uint32_t)cus;
+    // the allocation-free workspace of this device: its device address,
+    // looked up once per device with that device current
+    if (device >= kMaxDevices) {
+        delete c;
+        return fail(MC_E_ARG, "device index above the library's limit of 64");
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[device]) {
+            int prev = 0;
+            hipError_t e = hipGetDevice(&prev);
+            if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+            void *ptr = nullptr;
+            if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+            if (prev != device) (void)hipSetDevice(prev);
+            if (e != hipSuccess || !ptr) {
+                delete c;
+                return e != hipSuccess ? hip_fail(e, "hipGetSymbolAddress(noalloc_scratch)")
+                                       : fail(MC_E_HIP, "no device address for noalloc_scratch");
+            }
+            g_noalloc_ptr[device] = ptr;
+        }
+        c->noalloc_scratch = g_noalloc_ptr[device];
+    }
     *out = c;
     return MC_OK;
 }
@@ -1306,6 +1344,29 @@ int mc_merge_bounds(const mc_column_in *in, uint64_t *dict_cap, uint64_t *codes_
 int mc_merge_column(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out, void *scratch,
                     uint64_t scratch_bytes, hipStream_t stream) {
     return merge_column_impl(ctx, in, out, scratch, scratch_bytes, stream);
+}
+
+int mc_merge_column_noalloc(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out,
+                            hipStream_t stream) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    int rc = check_in(in);
+    if (rc) return rc;
+    rc = check_out(in, out);
+    if (rc) return rc;
+    if (!ctx->noalloc_scratch) return fail(MC_E_ARG, "context has no allocation-free workspace");
+    const ColLayout L =
+        col_layout(in->type, in->main_dict_len, in->delta_rows, in->main_rows, true, ctx->tune);
+    if (single_scratch(L) > MC_NOALLOC_SCRATCH_BYTES)
+        return fail(MC_E_CAP, "column needs " + std::to_string(single_scratch(L)) +
+                                  " bytes of workspace, above MC_NOALLOC_SCRATCH_BYTES (" +
+                                  std::to_string(MC_NOALLOC_SCRATCH_BYTES) + ")");
+    // the device address looked up in mc_ctx_create, never the array's name
+    char *ws = static_cast<char *>(ctx->noalloc_scratch);
+    switch (in->type) {
+        case MC_U32: return merge_column_t<mc::TU32>(ctx, in, out, ws, L, stream, false, nullptr, false);
+        case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, stream, false, nullptr, false);
+        default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, stream, false, nullptr, false);
+    }
 }
 
 int mc_merge_column_naive(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out,
