@@ -90,6 +90,95 @@ def reencode_bytes(col, n_new, w_new, n_ud):
             + 4 * col.u_m.shape[0] + 4 * n_ud)
 
 
+def compare_with_oracle(col, got):
+    """Every output of one merge against the oracle's whole merge of the same
+    column: |U'|, w', W', U' and all W' result words (no sampling)."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    ref = oracle.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w, col.delta)
+    bad_words = int(np.count_nonzero(got["codes"] != ref["codes"])) \
+        if got["codes"].shape == ref["codes"].shape else None
+    ok = (got["error"] == 0 and got["n_new"] == ref["n_new"] and got["w_new"] == ref["w_new"]
+          and got["words"] == ref["n_words"] and np.array_equal(got["u_new"], ref["u_new"])
+          and bad_words == 0)
+    return bool(ok), {"words_compared": int(ref["n_words"]), "words_differing": bad_words}
+
+
+def bench_single(cm, torch, col, steps, warmup, stream, ctx, spread=False, parity=True):
+    """One single-column configuration: `warmup` merges, then `steps` timed
+    merges (wall clock around them, device synchronized on both sides), then
+    the same merges again with HIP events around every step on the launch
+    stream (step split, the re-encode kernel alone for the roofline), and
+    with spread=True once more with an event pair around each merge.  With
+    parity=True the last merge's outputs are compared with the oracle's."""
+    dcol = cm.ColumnInput.from_numpy(col)
+    out = cm.alloc_output(dcol, tables=False)
+    scratch = cm.alloc_scratch(cm.merge_bounds(dcol, ctx)[2])
+    for _ in range(warmup):
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+    torch.cuda.synchronize()
+    sc = out.scalars()
+    assert sc["error"] == 0, sc
+    log(f"{col.meta.get('config', col.vtype)}: |U'|={sc['n_new']} w'={sc['w_new']} "
+        f"words={sc['words']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    ctx.set_timing(True)
+    for _ in range(steps):
+        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+    st = ctx.step_times()
+    ctx.set_timing(False)
+    torch.cuda.synchronize()
+    dist = None
+    if spread:
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for a, b in evs:
+            a.record(stream)
+            cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        per = sorted(a.elapsed_time(b) for a, b in evs)
+        dist = {"median": per[len(per) // 2], "min": per[0],
+                "p90": per[min(len(per) - 1, int(0.9 * len(per)))], "n": len(per)}
+    n_out = col.n_main + col.n_delta
+    b_alg = algorithmic_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
+    b_re = reencode_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
+    kernel_ms = st[5]
+    achieved = b_re / (kernel_ms / 1000.0) / 1e9
+    res = {"workload": col.meta.get("config"), "scalars": sc,
+           "ms_per_merge": ms, "tuples_s": n_out / (ms / 1000.0),
+           "bytes_alg": b_alg, "hbm_gbs_alg": b_alg / (ms / 1000.0) / 1e9,
+           "hbm_frac_alg": b_alg / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
+           "w": col.w, "w_new": sc["w_new"], "new_dict": sc["n_new"],
+           "steps_ms": st,
+           "step_ms": {"clear+sort": st[0], "emit": st[1], "merge_dict": st[2],
+                       "reencode": st[3], "whole": st[4], "reencode_kernel": st[5]},
+           "merge_ms_dist": dist,
+           "roofline": {"kernel": "k1_repack (Step 2(b))", "bound": "hbm",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "bytes_per_launch": b_re, "kernel_ms": kernel_ms,
+                        "timing": "HIP events around the re-encode kernel alone on its "
+                                  "launch stream, averaged over the timed merges"}}
+    res["parity"] = None
+    if parity:
+        t = time.time()
+        ok, detail = compare_with_oracle(col, out.fetch())
+        res["parity"] = ok
+        res["parity_detail"] = detail
+        log(f"{col.meta.get('config', col.vtype)}: parity with the oracle {ok} "
+            f"({time.time() - t:.1f}s)")
+    del out, scratch, dcol
+    return res
+
+
 def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
     """300 columns of mixed types and sizes: one batched launch sequence
     replayed from a HIP graph, against one mc_merge_column call per column
@@ -133,8 +222,11 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
             cm.merge_column(d, out=o, scratch=scratch, stream=stream, ctx=ctx)
     torch.cuda.synchronize()
     t_p = (_t.perf_counter() - t0) / steps
-    same = all(torch.equal(a.new_codes[: s["words"]], b.new_codes[: s["words"]])
-               for a, b, s in zip(outs, pouts, scal))
+    same = True
+    for a, b, s in zip(outs, pouts, scal):
+        sb = b.scalars()
+        same &= (sb == s and torch.equal(a.new_codes[: s["words"]], b.new_codes[: s["words"]])
+                 and torch.equal(a.new_dict[: s["n_new"]], b.new_dict[: s["n_new"]]))
     del graph, outs, pouts, scratch, dcols
     torch.cuda.empty_cache()
     return {"workload": "300 columns, rows log-uniform [1M, 20M], distinct log-uniform [2, 10M], "
@@ -539,6 +631,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3],
                     help="single-column workload (2 is the reported one; 1 and 3 for profiling)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-column configurations (c1, c3)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 300-column batched vs plain comparison")
     ap.add_argument("--gen-workers", type=int, default=16,
@@ -572,6 +666,9 @@ def main():
         print(json.dumps(fn[args.sweep](args)), flush=True)
         return
 
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
     import numpy as np
     import torch
 
@@ -582,7 +679,13 @@ def main():
         from paper_1109_6885_amd import build as hipbuild
         hipbuild.build()
 
-    # inputs first: the generator's worker processes start before the GPU is used
+    # inputs first: the generators' worker processes start before the GPU is
+    # used; the 16-byte-string column generates in a process of its own while
+    # the others run
+    side, fut3 = None, None
+    if not args.no_configs and args.config != 3:
+        side = cf.ProcessPoolExecutor(max_workers=1, mp_context=mp.get_context("spawn"))
+        fut3 = side.submit(gen.config_column, 3)
     t = time.time()
     col = gen.config_column(args.config)
     log(f"generated config {args.config} in {time.time() - t:.1f}s")
@@ -595,49 +698,14 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
-    dcol = cm.ColumnInput.from_numpy(col)
-    out = cm.alloc_output(dcol, tables=False)
-    _, _, sbytes = cm.merge_bounds(dcol)
-    scratch = cm.alloc_scratch(sbytes)
     ctx = cm.context()
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
-    torch.cuda.synchronize()
-    sc = out.scalars()
-    assert sc["error"] == 0, sc
-    log(f"|U'|={sc['n_new']} w'={sc['w_new']} words={sc['words']}")
-
-    # timed region: K whole merges, wall clock around them
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-
-    # the same K merges again with HIP events around every step on the
-    # launch stream: per-step averages
-    ctx.set_timing(True)
-    for _ in range(args.steps):
-        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
-    steps_ms = ctx.step_times()
-    ctx.set_timing(False)
-    torch.cuda.synchronize()
-
-    # and once more with an event pair around every merge: the spread
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
-        cm.merge_column(dcol, out=out, scratch=scratch, ctx=ctx, stream=stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    per = sorted(a.elapsed_time(b) for a, b in evs)
-    dist = {"median": per[len(per) // 2], "min": per[0],
-            "p90": per[min(len(per) - 1, int(0.9 * len(per)))], "n": len(per)}
+    main_leg = bench_single(cm, torch, col, args.steps, args.warmup, stream, ctx,
+                            spread=True, parity=not args.no_cpu)
+    sc = main_leg["scalars"]
+    ms_per_step = main_leg["ms_per_merge"]
+    steps_ms = main_leg["steps_ms"]
 
     # achievable streaming bandwidth: the library's plain 128-bit copy of
     # 1 GiB (2 GiB moved per copy), timed with events on the same stream
@@ -676,6 +744,25 @@ def main():
         del tab
     del idx, gout
 
+    # the other single-column configurations, each with its own roofline and
+    # its parity against the oracle
+    configs = {}
+    if not args.no_configs:
+        for k in (1, 3):
+            if k == args.config:
+                continue
+            t = time.time()
+            ck = gen.config_column(k) if fut3 is None or k == 1 else fut3.result()
+            log(f"config {k} ready after {time.time() - t:.1f}s")
+            leg = bench_single(cm, torch, ck, args.steps, args.warmup, stream, ctx,
+                               spread=False, parity=not args.no_cpu)
+            leg.pop("scalars")
+            configs[f"c{k}"] = leg
+            del ck
+            torch.cuda.empty_cache()
+        if side is not None:
+            side.shutdown()
+
     batched = None
     if bcols is not None:
         batched = bench_batched(cm, torch, bcols, args.steps, args.warmup, stream, ctx)
@@ -683,23 +770,35 @@ def main():
 
     n_out = col.n_main + col.n_delta
     value = n_out / (ms_per_step / 1000.0)
-    b_alg = algorithmic_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
-    b_re = reencode_bytes(col, sc["n_new"], sc["w_new"], sc["n_ud"])
-    re_ms = steps_ms[3]
-    achieved = b_re / (re_ms / 1000.0) / 1e9
+    b_alg = main_leg["bytes_alg"]
+    roof = main_leg["roofline"]
+    roof["traffic"] = measured_traffic() if args.config == 2 else None
+    # the kernel's real limit: one random translation-table read per row; the
+    # plain gather reference does the same number of reads from a table of
+    # the same size
+    roof["gather_ceiling"] = {"reference_lookups": col.n_main, "reference_us": gather_us[2],
+                              "kernel_us": roof["kernel_ms"] * 1000.0,
+                              "frac": gather_us[2] / (roof["kernel_ms"] * 1000.0)}
 
     cpu = None
     if not args.no_cpu:
+        # the serial oracle on one core of the host (this thread pinned to the
+        # first core it may use), the whole column, one run
         import oracle
         oracle.build(force=False)
-        t = time.perf_counter()
-        ref = oracle.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w,
-                                  col.delta)
-        dt = time.perf_counter() - t
-        assert ref["n_new"] == sc["n_new"]
+        allowed = os.sched_getaffinity(0)
+        core = min(allowed)
+        os.sched_setaffinity(0, {core})
+        try:
+            t = time.perf_counter()
+            oracle.merge_column(col.vtype, col.u_m, col.main_packed, col.n_main, col.w, col.delta)
+            dt = time.perf_counter() - t
+        finally:
+            os.sched_setaffinity(0, allowed)
         cpu = {"value": n_out / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
                "sample": "the whole 101M-tuple column, one serial run of the C oracle "
-                         f"({dt:.1f} s)", "host": host_cpu()}
+                         f"({dt:.1f} s) on one core (thread pinned to CPU {core})",
+               "host": host_cpu()}
 
     cpu_par = None
     if not args.no_cpu:
@@ -726,6 +825,10 @@ def main():
                    "host": host_cpu()}
         del o, r
 
+    parity = {"c%d" % args.config: main_leg["parity"]}
+    parity.update({k: v["parity"] for k, v in configs.items()})
+    if batched is not None:
+        parity["c4_batched_equals_plain"] = batched["batched_equals_plain"]
     line = {
         "metric": "merged tuples/s and achieved HBM GB/s (% of peak); batched vs per-column plain",
         "value": value,
@@ -743,38 +846,32 @@ def main():
                    "main_rows": col.n_main, "delta_rows": col.n_delta,
                    "dict": int(col.u_m.shape[0]), "w": col.w, "w_new": sc["w_new"],
                    "new_dict": sc["n_new"]},
+        "parity": parity,
         "hbm_gbs_alg": b_alg / (ms_per_step / 1000.0) / 1e9,
         "hbm_frac_alg": b_alg / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS,
         "bytes_alg": b_alg,
-        "merge_ms_dist": dist,
-        "step_ms": {"clear+sort": steps_ms[0], "emit": steps_ms[1], "merge_dict": steps_ms[2],
-                    "reencode": steps_ms[3], "whole": steps_ms[4]},
-        "roofline": {"kernel": "k_repack (Step 2(b))", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.config == 2 else None,
-                     "bytes_per_launch": b_re,
-                     # the kernel's real limit: one random translation-table
-                     # read per row; the plain gather reference does the same
-                     # number of reads from a table of the same size
-                     "gather_ceiling": {"reference_lookups": col.n_main,
-                                        "reference_us": gather_us[2],
-                                        "kernel_us": re_ms * 1000.0,
-                                        "frac": gather_us[2] / (re_ms * 1000.0)}},
+        "merge_ms_dist": main_leg["merge_ms_dist"],
+        "step_ms": main_leg["step_ms"],
+        "roofline": roof,
         "copy_kernel_gbs": copy_gbs,
         "gather_ref_us": {"rows": col.n_main, "table_entries": int(col.u_m.shape[0]),
                           "u32_table": gather_us[4], "u16_table": gather_us[2],
                           "note": "random lookups + 4-byte index read + 4-byte write per row"},
-        "reencode_frac_of_copy": achieved / copy_gbs,
+        "reencode_frac_of_copy": roof["achieved"] / copy_gbs,
+        "configs": configs,
         "cpu_baseline": cpu,
         "cpu_parallel": cpu_par,
         "batched": batched,
     }
     if not args.no_serve:
         # the served stream allocates most of HBM: free the single-column buffers first
-        del dcol, out, scratch
+        del main_leg
         torch.cuda.empty_cache()
         line["served"] = bench_serve(args)
     print(json.dumps(line), flush=True)
+    if not all(v is not False for v in parity.values()):
+        log(f"PARITY FAILURE: {parity}")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

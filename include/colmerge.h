@@ -77,7 +77,7 @@ typedef enum mc_status {
     MC_E_CAP = -2,   /* an output or scratch capacity is below the bounds    */
     MC_E_NOMEM = -3, /* host-side allocation failed                           */
     MC_E_HIP = -4,   /* a HIP runtime call failed (see mc_last_error)         */
-    MC_E_DATA = -5   /* invalid data reported by the device                   */
+    MC_E_DATA = -5   /* invalid data found by the device (validate mode)      */
 } mc_status;
 
 /* Bits of mc_result.error. */
@@ -85,10 +85,10 @@ typedef enum mc_status {
 #define MC_DEVERR_DELTA_RANGE 2u /* a delta index >= |U_D| (internal)        */
 #define MC_DEVERR_SPIN 4u        /* a cross-workgroup wait hit its bound     */
 #define MC_DEVERR_ORDER 8u       /* a dictionary is not strictly increasing  */
-/* The device does not check the order of U_M (a full check would cost a
- * pass over it); a U_M out of order gives an undefined result, and where a
- * merge tile meets the inconsistency it stays empty and sets
- * MC_DEVERR_ORDER instead of reading past its inputs. */
+/* Outside validate mode (mc_ctx_set_validate) the device does not check the
+ * order of U_M (a full check costs a pass over it); a U_M out of order gives
+ * an undefined result, and where a merge tile meets the inconsistency it
+ * stays empty and sets MC_DEVERR_ORDER instead of reading past its inputs. */
 
 /* Result scalars, written by the device (caller-allocated device memory). */
 typedef struct mc_result {
@@ -130,6 +130,23 @@ void mc_ctx_destroy(mc_ctx *ctx);
 
 /* Message for the calling thread's last failed call ("" if none). */
 const char *mc_last_error(void);
+
+/* Validate mode (off by default).  The paper's main dictionary is sorted and
+ * free of duplicates and every main code indexes it (Sections 3 and 4.1);
+ * the merge relies on both.  With validate mode on, mc_merge_column,
+ * mc_merge_column_naive, mc_merge_column_indexed and
+ * mc_merge_columns_batched become synchronous checkers:
+ *  1. a device pass checks that every U_M is strictly increasing and the
+ *     call waits for it; a dictionary out of order returns MC_E_DATA (the
+ *     result's error word holds MC_DEVERR_ORDER; nothing else is written);
+ *  2. the merge is enqueued as usual, the call waits for the stream, and
+ *     returns MC_E_DATA if the device found a main code >= |U_M|
+ *     (MC_DEVERR_CODE_RANGE) or any other data error bit.
+ * mc_last_error names the column and the bit.  Validate mode must not be on
+ * while the stream is being captured into a graph (the call waits on it);
+ * a batched call that captures a graph (graph != NULL) validates before the
+ * capture and waits after the launch. */
+int mc_ctx_set_validate(mc_ctx *ctx, int enable);
 
 /* ---- sizing (host only, no device access) ---------------------------- */
 
@@ -347,11 +364,14 @@ int mc_autotune_batched(mc_ctx *ctx, const mc_column_in *ins,
 /* Enabling (or re-enabling) timing starts a new measurement: from then on
  * every mc_merge_column call records HIP events around each step on its
  * own stream.  mc_ctx_step_times waits for the last recorded merge and
- * returns the AVERAGE milliseconds over the recorded merges for:
+ * writes the AVERAGE milliseconds over the recorded merges of the first n
+ * (<= MC_STEP_TIMES) of:
  * [0] workspace clear + delta sort, [1] delta dictionary emit,
- * [2] dictionary merge and width, [3] re-encode, [4] whole call. */
+ * [2] dictionary merge and width, [3] re-encode (X_M compaction and the
+ * re-encode kernel), [4] whole call, [5] the re-encode kernel alone. */
+#define MC_STEP_TIMES 6
 int mc_ctx_set_timing(mc_ctx *ctx, int enable);
-int mc_ctx_step_times(mc_ctx *ctx, float *ms5);
+int mc_ctx_step_times(mc_ctx *ctx, float *ms, uint32_t n);
 
 /* ---- measurement ------------------------------------------------------- */
 

@@ -45,10 +45,16 @@ class Context:
         check(load().mc_ctx_set_timing(self.handle, int(bool(on))), "mc_ctx_set_timing")
 
     def step_times(self):
-        """ms for [delta sort, delta dictionary emit, dictionary merge, re-encode, whole]."""
-        arr = (ctypes.c_float * 5)()
-        check(load().mc_ctx_step_times(self.handle, arr), "mc_ctx_step_times")
+        """Average ms over the timed merges for [delta sort, delta dictionary
+        emit, dictionary merge, re-encode, whole, re-encode kernel alone]."""
+        arr = (ctypes.c_float * _lib.STEP_TIMES)()
+        check(load().mc_ctx_step_times(self.handle, arr, _lib.STEP_TIMES), "mc_ctx_step_times")
         return list(arr)
+
+    def set_validate(self, on: bool):
+        """mc_ctx_set_validate: synchronous merges that check U_M's order and
+        the main codes' range on the device and raise MC_E_DATA."""
+        check(load().mc_ctx_set_validate(self.handle, int(bool(on))), "mc_ctx_set_validate")
 
     def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32, hash_min_rows: int = 0):
         """mc_ctx_set_tuning: launch shapes for every later merge on this context."""

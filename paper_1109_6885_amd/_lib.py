@@ -33,8 +33,11 @@ EXPORTS = [
     "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched", "mc_merge_bounds_ctx",
     "mc_delta_index_bytes", "mc_delta_index_reset", "mc_delta_index_append",
     "mc_merge_indexed_bounds", "mc_merge_column_indexed", "mc_merge_batched_bounds_ctx",
-    "mc_merge_column_noalloc",
+    "mc_merge_column_noalloc", "mc_ctx_set_validate",
 ]
+
+# Entries of mc_ctx_step_times (MC_STEP_TIMES in colmerge.h).
+STEP_TIMES = 6
 
 # Workspace of mc_merge_column_noalloc (MC_NOALLOC_SCRATCH_BYTES in colmerge.h).
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -120,7 +123,8 @@ def load():
         "mc_graph_launch": (ctypes.c_int, [p, p]),
         "mc_graph_destroy": (None, [p]),
         "mc_ctx_set_timing": (ctypes.c_int, [p, ctypes.c_int]),
-        "mc_ctx_step_times": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_float)]),
+        "mc_ctx_step_times": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_float), u32]),
+        "mc_ctx_set_validate": (ctypes.c_int, [p, ctypes.c_int]),
         "mc_copy_bytes": (ctypes.c_int, [p, p, p, u64, p]),
         "mc_gather_ref": (ctypes.c_int, [p, p, u64, p, u32, u32, p, p]),
         "mc_ctx_set_tuning": (ctypes.c_int, [p, ctypes.POINTER(McTuning)]),

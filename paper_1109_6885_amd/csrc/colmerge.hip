@@ -26,8 +26,8 @@ struct mc_ctx {
     int device = 0;
     uint32_t cus = 0;  // compute units of the device (grid of the one-launch full sort)
     int timing = 0;
-    // one set of five events per timed merge since timing was enabled
-    std::vector<std::array<hipEvent_t, 5>> ev;
+    // one set of six events per timed merge since timing was enabled
+    std::vector<std::array<hipEvent_t, 6>> ev;
     size_t used = 0;
     // pinned staging of batched descriptors, and the event of its last copy
     void *meta_host = nullptr;
@@ -37,6 +37,8 @@ struct mc_ctx {
     mc_tuning tune = {2048u, 32u, 0u, 0u};
     // device address of this device's allocation-free workspace
     void *noalloc_scratch = nullptr;
+    // validate mode (mc_ctx_set_validate)
+    int validate = 0;
 };
 
 struct mc_graph {
@@ -384,6 +386,16 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p0, uint64_t n0, ui
         p0[i] = 0u;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride)
         p1[i] = 0u;
+}
+
+// Validate mode: err |= MC_DEVERR_ORDER unless u[0..n) is strictly increasing.
+template <class T>
+__global__ __launch_bounds__(256) void k_check_order(const void *u, uint64_t n, uint32_t *err) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += stride)
+        bad |= !T::lt(T::norm(T::load(u, i - 1)), T::norm(T::load(u, i)));
+    if (bad) atomicOr(err, MC_DEVERR_ORDER);
 }
 
 // Plain 128-bit copy: the achievable streaming bandwidth on this GPU, and
@@ -838,12 +850,14 @@ int launch_merge(const mc::ColDesc &C, uint64_t merge_tiles, hipStream_t s) {
     return MC_OK;
 }
 
-int launch_repack(const mc::ColDesc &C, uint32_t codes, hipStream_t s) {
+int launch_repack(const mc::ColDesc &C, uint32_t codes, hipStream_t s,
+                  hipEvent_t before_repack = nullptr) {
     if (C.xdev && C.n_um) {
         hipLaunchKernelGGL(k1_xcompact, dim3((uint32_t)ceil_div(C.n_um, mc::kXCompactTile)),
                            dim3(mc::kBlock), 0, s, C);
         MC_LAUNCHED("k1_xcompact");
     }
+    if (before_repack) MC_HIP(hipEventRecord(before_repack, s));
     const uint64_t grid = ceil_div(C.n_main + C.nd, codes);
     if (grid == 0) return MC_OK;
     switch (codes) {
@@ -858,6 +872,12 @@ int launch_repack(const mc::ColDesc &C, uint32_t codes, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Argument checks
 // ---------------------------------------------------------------------------
+
+// Rows of one column: at 1024 rows per re-encode tile this keeps a launch
+// below 2^24 workgroups of 256 threads (2^32 work-items).
+constexpr uint64_t kMaxRows = (1ull << 34) - 1024;
+// Workgroups of one batched launch (one per tile of every column).
+constexpr uint64_t kMaxLaunchTiles = (1ull << 24) - 1;
 
 uint64_t codes_words_bound(uint64_t rows, uint64_t dict_cap) {
     const uint32_t w = mc::code_width(dict_cap);
@@ -875,7 +895,10 @@ int check_in(const mc_column_in *in) {
     if (in->delta_rows >= (1ull << 30)) return fail(MC_E_ARG, "delta_rows must be < 2^30");
     if (in->main_dict_len + in->delta_rows > (1ull << 32))
         return fail(MC_E_ARG, "|U_M| + N_D must be <= 2^32");
-    if (in->main_rows > (1ull << 40)) return fail(MC_E_ARG, "main_rows must be <= 2^40");
+    // every per-row launch is a 1-D grid of 256-thread workgroups of at least
+    // 1024 rows, and HIP takes fewer than 2^32 work-items per dimension
+    if (in->main_rows + in->delta_rows > kMaxRows)
+        return fail(MC_E_ARG, "main_rows + delta_rows must be <= 2^34 - 1024");
     if (in->main_dict_len > 0 && !in->main_dict) return fail(MC_E_ARG, "null main_dict");
     if (in->main_rows > 0 && !in->main_codes) return fail(MC_E_ARG, "null main_codes");
     if (in->delta_rows > 0 && !in->delta_values) return fail(MC_E_ARG, "null delta_values");
@@ -912,6 +935,69 @@ int check_out(const mc_column_in *in, const mc_column_out *out) {
     return MC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Validate mode: U_M order checked on the device before the merge, the error
+// word read back after it.
+// ---------------------------------------------------------------------------
+
+int launch_check_order(const mc_column_in *in, uint32_t *err, hipStream_t s) {
+    if (in->main_dict_len < 2) return MC_OK;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ceil_div(in->main_dict_len, 256), 2048);
+    switch (in->type) {
+        case MC_U32:
+            hipLaunchKernelGGL(k_check_order<mc::TU32>, dim3(grid), dim3(256), 0, s,
+                               in->main_dict, in->main_dict_len, err);
+            break;
+        case MC_U64:
+            hipLaunchKernelGGL(k_check_order<mc::TU64>, dim3(grid), dim3(256), 0, s,
+                               in->main_dict, in->main_dict_len, err);
+            break;
+        default:
+            hipLaunchKernelGGL(k_check_order<mc::TS16>, dim3(grid), dim3(256), 0, s,
+                               in->main_dict, in->main_dict_len, err);
+            break;
+    }
+    MC_LAUNCHED("k_check_order");
+    return MC_OK;
+}
+
+// Read the error words of n results after the stream is done; MC_E_DATA
+// naming the first column with a data error bit.
+int read_errors(const mc_column_out *outs, uint32_t n, hipStream_t s, const char *when) {
+    MC_HIP(hipStreamSynchronize(s));
+    for (uint32_t j = 0; j < n; j++) {
+        uint32_t e = 0;
+        MC_HIP(hipMemcpy(&e, &outs[j].result->error, sizeof(e), hipMemcpyDeviceToHost));
+        const uint32_t data = e & (MC_DEVERR_CODE_RANGE | MC_DEVERR_DELTA_RANGE | MC_DEVERR_ORDER);
+        if (data)
+            return fail(MC_E_DATA, std::string(when) + ": column " + std::to_string(j) + ": " +
+                                       (data & MC_DEVERR_ORDER ? "main dictionary not strictly "
+                                                                 "increasing"
+                                        : data & MC_DEVERR_CODE_RANGE
+                                            ? "a main code >= |U_M|"
+                                            : "a delta index out of range") +
+                                       " (error word " + std::to_string(e) + ")");
+    }
+    return MC_OK;
+}
+
+// Step 1 of validate mode for n columns: zero each result, check each U_M's
+// order into its error word, wait, report.
+int validate_dicts(const mc_column_in *ins, const mc_column_out *outs, uint32_t n,
+                   hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    MC_HIP(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(MC_E_ARG, "validate mode cannot run on a stream under graph capture");
+    for (uint32_t j = 0; j < n; j++) {
+        int rc = launch_fill(outs[j].result, sizeof(mc_result), nullptr, 0, s);
+        if (rc) return rc;
+        rc = launch_check_order(&ins[j], &outs[j].result->error, s);
+        if (rc) return rc;
+    }
+    return read_errors(outs, n, s, "validate");
+}
+
 template <class T>
 int launch_naive(const mc::ColDesc &C, hipStream_t s) {
     const uint64_t grid = ceil_div(C.n_main + C.nd, mc::kRepackCodes);
@@ -930,7 +1016,7 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
     hipEvent_t *ev = nullptr;
     if (ctx->timing && timed) {
         if (ctx->used == ctx->ev.size()) {
-            std::array<hipEvent_t, 5> set{};
+            std::array<hipEvent_t, 6> set{};
             for (auto &e : set) MC_HIP(hipEventCreate(&e));
             ctx->ev.push_back(set);
         }
@@ -952,10 +1038,15 @@ int merge_column_t(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *out
     rc = launch_merge<T>(C, L.merge_tiles, s);
     if (rc) return rc;
     if (ev) MC_HIP(hipEventRecord(ev[3], s));
-    rc = naive ? launch_naive<T>(C, s) : launch_repack(C, L.repack_codes, s);
+    if (naive) {
+        if (ev) MC_HIP(hipEventRecord(ev[4], s));
+        rc = launch_naive<T>(C, s);
+    } else {
+        rc = launch_repack(C, L.repack_codes, s, ev ? ev[4] : nullptr);
+    }
     if (rc) return rc;
     if (ev) {
-        MC_HIP(hipEventRecord(ev[4], s));
+        MC_HIP(hipEventRecord(ev[5], s));
         ctx->used++;
     }
     return MC_OK;
@@ -973,12 +1064,18 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
     if (!scratch || scratch_bytes < single_scratch(L))
         return fail(MC_E_CAP, "scratch below mc_merge_bounds");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
+    if (ctx->validate) {
+        rc = validate_dicts(in, out, 1, s);
+        if (rc) return rc;
+    }
     char *ws = static_cast<char *>(scratch);
     switch (in->type) {
-        case MC_U32: return merge_column_t<mc::TU32>(ctx, in, out, ws, L, s, naive);
-        case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, s, naive);
-        default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, s, naive);
+        case MC_U32: rc = merge_column_t<mc::TU32>(ctx, in, out, ws, L, s, naive); break;
+        case MC_U64: rc = merge_column_t<mc::TU64>(ctx, in, out, ws, L, s, naive); break;
+        default: rc = merge_column_t<mc::TS16>(ctx, in, out, ws, L, s, naive); break;
     }
+    if (rc == MC_OK && ctx->validate) rc = read_errors(out, 1, s, "merge");
+    return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,7 +1215,8 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
                 n = L.hashed ? ceil_div(ins[j].delta_rows, mc::kCompactTile) : 0;
             at(m, j) = (uint32_t)acc;
             acc += n;
-            if (acc >= (1ull << 31)) return fail(MC_E_ARG, "batch has too many tiles for one launch");
+            if (acc > kMaxLaunchTiles)
+                return fail(MC_E_ARG, "batch has too many tiles for one launch (2^24 - 1)");
         }
         at(m, ncols) = (uint32_t)acc;
     }
@@ -1529,21 +1627,24 @@ int mc_ctx_set_timing(mc_ctx *ctx, int enable) {
     return MC_OK;
 }
 
-int mc_ctx_step_times(mc_ctx *ctx, float *ms5) {
-    if (!ctx || !ms5) return fail(MC_E_ARG, "null argument");
+int mc_ctx_step_times(mc_ctx *ctx, float *ms, uint32_t n) {
+    if (!ctx || (!ms && n)) return fail(MC_E_ARG, "null argument");
+    if (n > MC_STEP_TIMES) return fail(MC_E_ARG, "at most MC_STEP_TIMES step times");
     if (ctx->used == 0) return fail(MC_E_ARG, "no timed merge recorded");
-    MC_HIP(hipEventSynchronize(ctx->ev[ctx->used - 1][4]));
-    double acc[5] = {0, 0, 0, 0, 0};
+    MC_HIP(hipEventSynchronize(ctx->ev[ctx->used - 1][5]));
+    double acc[MC_STEP_TIMES] = {0, 0, 0, 0, 0, 0};
+    // event k: 0 start, 1 after the delta sort, 2 after the emit, 3 after the
+    // dictionary merge, 4 before the re-encode kernel, 5 end
+    const int from[MC_STEP_TIMES] = {0, 1, 2, 3, 0, 4}, to[MC_STEP_TIMES] = {1, 2, 3, 5, 5, 5};
     for (size_t i = 0; i < ctx->used; i++) {
         const auto &e = ctx->ev[i];
-        const int from[5] = {0, 1, 2, 3, 0}, to[5] = {1, 2, 3, 4, 4};
-        for (int k = 0; k < 5; k++) {
-            float ms = 0.f;
-            MC_HIP(hipEventElapsedTime(&ms, e[from[k]], e[to[k]]));
-            acc[k] += ms;
+        for (uint32_t k = 0; k < n; k++) {
+            float x = 0.f;
+            MC_HIP(hipEventElapsedTime(&x, e[from[k]], e[to[k]]));
+            acc[k] += x;
         }
     }
-    for (int k = 0; k < 5; k++) ms5[k] = (float)(acc[k] / (double)ctx->used);
+    for (uint32_t k = 0; k < n; k++) ms[k] = (float)(acc[k] / (double)ctx->used);
     return MC_OK;
 }
 
@@ -1666,12 +1767,18 @@ int mc_merge_column_indexed(mc_ctx *ctx, const mc_column_in *in, const mc_delta_
     if (!scratch || scratch_bytes < single_scratch(L))
         return fail(MC_E_CAP, "scratch below mc_merge_indexed_bounds");
     if (!aligned16(scratch)) return fail(MC_E_ARG, "scratch must be 16-byte aligned");
+    if (ctx->validate) {
+        rc = validate_dicts(in, out, 1, s);
+        if (rc) return rc;
+    }
     char *ws = static_cast<char *>(scratch);
     switch (in->type) {
-        case MC_U32: return merge_column_t<mc::TU32>(ctx, in, out, ws, L, s, false, ix);
-        case MC_U64: return merge_column_t<mc::TU64>(ctx, in, out, ws, L, s, false, ix);
-        default: return merge_column_t<mc::TS16>(ctx, in, out, ws, L, s, false, ix);
+        case MC_U32: rc = merge_column_t<mc::TU32>(ctx, in, out, ws, L, s, false, ix); break;
+        case MC_U64: rc = merge_column_t<mc::TU64>(ctx, in, out, ws, L, s, false, ix); break;
+        default: rc = merge_column_t<mc::TS16>(ctx, in, out, ws, L, s, false, ix); break;
     }
+    if (rc == MC_OK && ctx->validate) rc = read_errors(out, 1, s, "merge");
+    return rc;
 }
 
 int mc_merge_batched_bounds_ctx(const mc_ctx *ctx, const mc_column_in *ins, uint32_t ncols,
@@ -1692,7 +1799,26 @@ int mc_merge_columns_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_colu
                              uint32_t ncols, void *scratch, uint64_t scratch_bytes,
                              hipStream_t stream, mc_graph **graph) {
     if (!ctx) return fail(MC_E_ARG, "null context");
-    return batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, ctx->tune, graph);
+    if (!ctx->validate)
+        return batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, ctx->tune,
+                           graph);
+    if (ncols && (!ins || !outs)) return fail(MC_E_ARG, "null descriptors");
+    for (uint32_t j = 0; j < ncols; j++) {  // the checks batched_run makes, before any launch
+        int rc = check_in(&ins[j]);
+        if (rc == MC_OK) rc = check_out(&ins[j], &outs[j]);
+        if (rc) return rc;
+    }
+    int rc = validate_dicts(ins, outs, ncols, stream);
+    if (rc) return rc;
+    rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, ctx->tune, graph);
+    if (rc) return rc;
+    return read_errors(outs, ncols, stream, "batched merge");
+}
+
+int mc_ctx_set_validate(mc_ctx *ctx, int enable) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    ctx->validate = enable ? 1 : 0;
+    return MC_OK;
 }
 
 int mc_ctx_set_tuning(mc_ctx *ctx, const mc_tuning *t) {

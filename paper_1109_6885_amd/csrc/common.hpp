@@ -156,10 +156,14 @@ constexpr uint64_t kFlagPre = 2ull << 62;
 constexpr uint64_t kValMask = kFlagAgg - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ uint64_t ld_acq(const uint64_t *p) {
+// Agent-scope relaxed atomics on the look-back status words.  Relaxed is
+// enough: a status word carries the value it publishes (flag and count in
+// one 64-bit word), so a reader needs no other data ordered with it, and
+// agent scope keeps the word coherent across the XCDs' L2 caches.
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(uint64_t *p, uint64_t v) {
+__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -242,7 +246,7 @@ struct ColDesc {
 // Split in two so that a tile can publish its own total first, do other work
 // while its predecessors finish, and only then wait for their prefix.
 __device__ inline void lookback_publish(uint64_t *status, uint32_t tile, uint64_t agg) {
-    if (threadIdx.x == 0) st_rel(&status[tile], (tile == 0 ? kFlagPre : kFlagAgg) | agg);
+    if (threadIdx.x == 0) st_relaxed(&status[tile], (tile == 0 ? kFlagPre : kFlagAgg) | agg);
 }
 __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uint64_t agg,
                                             uint32_t *err, uint64_t *s_prefix) {
@@ -254,7 +258,7 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
         uint32_t spins = 0;
         while (true) {
             const int64_t t = base - lane;  // lane 0: nearest predecessor
-            uint64_t s = t >= 0 ? ld_acq(&status[t]) : kFlagPre;  // before tile 0: zero prefix
+            uint64_t s = t >= 0 ? ld_relaxed(&status[t]) : kFlagPre;  // before tile 0: zero prefix
             while (true) {
                 const uint64_t pre = __ballot((s & kFlagPre) != 0);
                 // lanes up to and including the nearest inclusive prefix
@@ -267,7 +271,7 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                if ((wait >> lane) & 1ull) s = ld_acq(&status[t]);
+                if ((wait >> lane) & 1ull) s = ld_relaxed(&status[t]);
             }
             const uint64_t pre = __ballot((s & kFlagPre) != 0);
             const int stop = pre ? __ffsll((long long)pre) - 1 : 64;
@@ -276,7 +280,7 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
             base -= 64;
         }
         if (lane == 0) {
-            st_rel(&status[tile], kFlagPre | (prefix + agg));
+            st_relaxed(&status[tile], kFlagPre | (prefix + agg));
             *s_prefix = prefix;
         }
     }

@@ -38,7 +38,8 @@
 namespace mc {
 
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
-    // finalizer of a 64-bit multiplicative hash (xor-shift / multiply rounds)
+    // MurmurHash3's 64-bit finalizer "fmix64" (Austin Appleby, public
+    // domain): xor-shift / multiply rounds with its published constants
     x ^= x >> 33;
     x *= 0xff51afd7ed558ccdull;
     x ^= x >> 33;

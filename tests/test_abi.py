@@ -148,3 +148,14 @@ def test_delta_index_bytes_and_argument_checks(lib):
     ix = _lib.McDeltaIndex(None, 0, 10, 1, 0)
     assert lib.mc_delta_index_reset(None, ctypes.byref(ix), None) == -1
     assert lib.mc_delta_index_append(None, ctypes.byref(ix), None, 0, 1, None) == -1
+
+
+def test_row_limit_matches_launch_limit(lib):
+    """Rows of one column are limited so that every per-row launch stays under
+    HIP's 2^32 work-items (1024-row tiles of 256 threads): 2^34 - 1024 rows in
+    all is accepted, one more is refused on the host."""
+    rc, *_ = _bounds(lib, _in(n_main=(1 << 34) - 1024 - 1_000_000))
+    assert rc == 0
+    rc, *_ = _bounds(lib, _in(n_main=(1 << 34) - 1024 - 1_000_000 + 1))
+    assert rc == -1
+    assert b"2^34" in lib.mc_last_error()

@@ -324,3 +324,51 @@ def test_hypothesis_batches(cols):
     torch.cuda.synchronize()
     for c, o in zip(cols, outs):
         check_col(c, o.fetch())
+
+
+@pytest.mark.slow
+def test_batched_full_c4_against_oracle():
+    """The whole 300-column batched workload (1.96e9 rows, u32/u64/str16,
+    rows log-uniform in [1M, 20M], distinct counts log-uniform in [2, 10M],
+    delta 1% of rows, half new values), replayed from a HIP graph as the
+    benchmark runs it: every column's |U'|, w', W', U' and all of its result
+    words against the oracle's merge of the same column.  The oracle runs in
+    worker processes that return SHA-256 digests of U' and of the result
+    words (equal digests: equal bytes); a column whose digests differ is
+    merged again by the oracle here and compared element by element."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+
+    import oracle_pool
+
+    workers = min(16, os.cpu_count() or 1)
+    shapes = gen.batched_shapes(300)
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
+        # largest columns first, so the pool's tail is short
+        order = sorted(range(len(shapes)), key=lambda i: -shapes[i][1])
+        futs = {i: pool.submit(oracle_pool.oracle_digest, shapes[i]) for i in order}
+        cols = gen.batched_columns(300, workers=workers)
+        say(f"case full batched workload, {len(cols)} columns, "
+            f"{sum(c.n_main + c.n_delta for c in cols)} rows")
+        dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+        outs, graph = cm.merge_columns_batched(dcols, graph=True)
+        torch.cuda.synchronize()
+        for o in outs:                    # the replay must write everything again
+            o.new_codes.zero_()
+            o.new_dict.zero_()
+        graph.launch()
+        torch.cuda.synchronize()
+        for j, (c, o) in enumerate(zip(cols, outs)):
+            got, ref = o.fetch(), futs[j].result()
+            assert got["error"] == 0, (j, got["error"])
+            same = ((got["n_new"], got["w_new"], got["words"]) ==
+                    (ref["n_new"], ref["w_new"], ref["n_words"])
+                    and oracle_pool.digest(got["u_new"]) == ref["u_new"]
+                    and oracle_pool.digest(got["codes"]) == ref["codes"])
+            if not same:
+                check_col(c, got)         # element-wise, to name what differs
+                raise AssertionError(f"column {j}: digests differ")
+    del graph, outs, dcols
+    torch.cuda.empty_cache()
