@@ -307,8 +307,24 @@ int mc_merge_batched_bounds_ctx(const mc_ctx *ctx, const mc_column_in *ins,
                                 uint32_t ncols, uint64_t *scratch_bytes);
 
 /* Enqueue the merge of ncols independent columns (uneven sizes and value
- * types) as one batched launch sequence: every kernel covers the tiles of
- * all columns, so the launch count does not grow with ncols.  If `graph`
+ * types).  Two forms, chosen by the context's tuning (batched_launch):
+ *  MC_BATCHED_PHASES      one launch per phase, each covering the tiles of
+ *                         all columns (about 70 launches whatever ncols);
+ *  MC_BATCHED_PERSISTENT  (disabled: mc_ctx_set_tuning refuses it with
+ *                         MC_E_ARG; its launch stalled on the GPU, also
+ *                         with one workgroup, and the cause is not found)
+ *                         one persistent launch (after a small clearing
+ *                         kernel): its workgroups take work items -- a tile
+ *                         or a slice of one step of one column -- from one
+ *                         device counter, in an order where every item's
+ *                         inputs come from items taken before it, so a
+ *                         workgroup only ever waits for items that running
+ *                         workgroups hold (Section 6.2.1, scheme (i), a
+ *                         task queue).  Columns overlap: one column's merge
+ *                         runs beside another's sort.  Every wait is bounded
+ *                         and reports MC_DEVERR_SPIN in the column's error
+ *                         word if it ever overruns.
+ * Both give the same results.  If `graph`
  * is non-NULL the sequence is captured once into a HIP graph (returned in
  * *graph, reusable with mc_graph_launch for the same buffers) and launched;
  * otherwise it is enqueued directly.  ins/outs are host arrays of ncols
@@ -331,12 +347,26 @@ void mc_graph_destroy(mc_graph *graph);
  *                 (4 .. 1024, default 32; more runs -> more radix passes,
  *                 longer runs -> more work in the LDS windows);
  *   hash_min_rows: deltas of at least this many rows deduplicate by hashing
- *                 before sorting (0: the default, 2^21; 1: always).
+ *                 before sorting (0: the default, 2^21; 1: always);
+ *   batched_launch: MC_BATCHED_PHASES (0, default); MC_BATCHED_PERSISTENT
+ *                 is refused for now (see mc_merge_columns_batched);
+ *   persist_workers: workgroups of the persistent launch (0: as many as the
+ *                 GPU holds at once; any count >= 1 completes);
+ *   persist_repack: Step 2(b) tiles per work item of the persistent launch
+ *                 (0: default 4; at most 1024);
+ *   persist_merge: dictionary-merge tiles per work item (0: default 2; at
+ *                 most 1024).
  * The results do not depend on them. */
+#define MC_BATCHED_PHASES 0u
+#define MC_BATCHED_PERSISTENT 1u
 typedef struct mc_tuning {
     uint32_t repack_codes;
     uint32_t prefix_run;
     uint32_t hash_min_rows;
+    uint32_t batched_launch;
+    uint32_t persist_workers;
+    uint32_t persist_repack;
+    uint32_t persist_merge;
     uint32_t reserved; /* zero */
 } mc_tuning;
 

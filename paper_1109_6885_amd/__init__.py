@@ -56,16 +56,22 @@ class Context:
         the main codes' range on the device and raise MC_E_DATA."""
         check(load().mc_ctx_set_validate(self.handle, int(bool(on))), "mc_ctx_set_validate")
 
-    def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32, hash_min_rows: int = 0):
-        """mc_ctx_set_tuning: launch shapes for every later merge on this context."""
-        t = McTuning(repack_codes, prefix_run, hash_min_rows)
+    TUNING_FIELDS = ("repack_codes", "prefix_run", "hash_min_rows", "batched_launch",
+                     "persist_workers", "persist_repack", "persist_merge")
+
+    def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32, hash_min_rows: int = 0,
+                   batched_launch: int = 0, persist_workers: int = 0, persist_repack: int = 0,
+                   persist_merge: int = 0):
+        """mc_ctx_set_tuning: launch shapes for every later merge on this context
+        (batched_launch: 0 one launch per phase, 1 one persistent launch)."""
+        t = McTuning(repack_codes, prefix_run, hash_min_rows, batched_launch, persist_workers,
+                     persist_repack, persist_merge, 0)
         check(load().mc_ctx_set_tuning(self.handle, ctypes.byref(t)), "mc_ctx_set_tuning")
 
     def get_tuning(self) -> dict:
         t = McTuning()
         check(load().mc_ctx_get_tuning(self.handle, ctypes.byref(t)), "mc_ctx_get_tuning")
-        return {"repack_codes": t.repack_codes, "prefix_run": t.prefix_run,
-                "hash_min_rows": t.hash_min_rows}
+        return {f: getattr(t, f) for f in self.TUNING_FIELDS}
 
     def __del__(self):
         try:
@@ -485,8 +491,7 @@ def autotune_batched(cols, outs=None, scratch=None, stream=None, ctx=None):
     check(load().mc_autotune_batched(ctx.handle, ins, os_, len(cols), _ptr(scratch),
                                      scratch.numel(), _stream(stream), ctypes.byref(t), times),
           "mc_autotune_batched")
-    return ({"repack_codes": t.repack_codes, "prefix_run": t.prefix_run,
-             "hash_min_rows": t.hash_min_rows}, list(times), outs)
+    return ({f: getattr(t, f) for f in Context.TUNING_FIELDS}, list(times), outs)
 
 
 def merge_columns_batched(cols, outs=None, scratch=None, graph: bool = False, stream=None,

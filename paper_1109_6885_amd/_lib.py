@@ -63,9 +63,14 @@ class McColumnOut(ctypes.Structure):
                 ("result", ctypes.c_void_p)]
 
 
+MC_BATCHED_PHASES, MC_BATCHED_PERSISTENT = 0, 1
+
+
 class McTuning(ctypes.Structure):
     _fields_ = [("repack_codes", ctypes.c_uint32), ("prefix_run", ctypes.c_uint32),
-                ("hash_min_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("hash_min_rows", ctypes.c_uint32), ("batched_launch", ctypes.c_uint32),
+                ("persist_workers", ctypes.c_uint32), ("persist_repack", ctypes.c_uint32),
+                ("persist_merge", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class McDeltaIndex(ctypes.Structure):

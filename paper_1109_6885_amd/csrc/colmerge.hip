@@ -19,6 +19,7 @@
 #include "hash.hpp"
 #include "merge.hpp"
 #include "naive.hpp"
+#include "queue.hpp"
 #include "repack.hpp"
 #include "sort.hpp"
 
@@ -34,7 +35,7 @@ struct mc_ctx {
     uint64_t meta_cap = 0;
     hipEvent_t meta_event = nullptr;
     // launch shapes (mc_ctx_set_tuning / mc_autotune_batched)
-    mc_tuning tune = {2048u, 32u, 0u, 0u};
+    mc_tuning tune = {2048u, 32u, 0u, MC_BATCHED_PHASES, 0u, 0u, 0u, 0u};
     // device address of this device's allocation-free workspace
     void *noalloc_scratch = nullptr;
     // validate mode (mc_ctx_set_validate)
@@ -173,7 +174,16 @@ constexpr uint64_t kMergePartMinTiles = 512;
 // Workgroups of merge_partition: one wave per tile boundary (tiles + 1).
 uint64_t merge_part_blocks(uint64_t merge_tiles) { return ceil_div(merge_tiles + 1, mc::kWaves); }
 
-const mc_tuning kDefaultTuning = {2048u, 32u, 0u, 0u};
+const mc_tuning kDefaultTuning = {2048u, 32u, 0u, MC_BATCHED_PHASES, 0u, 0u, 0u, 0u};
+// Tiles per work item of the persistent batched launch (defaults).
+constexpr uint32_t kPersistRepack = 4, kPersistMerge = 2;
+// Items of each global fallback phase of the persistent launch (they stride
+// over the device-built maps of the columns that need the full sort).
+constexpr uint32_t kPersistFbItems = 32;
+// Queue counters of the persistent launch, after the batch's zeroed parts:
+// the ticket, finished emit items, finished fallback items, error bits of the
+// fallback chain's waits, then one finished-item count per column.
+constexpr int kQTicket = 0, kQEmitDone = 1, kQFbDone = 2, kQErr = 3, kQColDone = 4;
 
 ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
                      bool allow_hash = true, const mc_tuning &tune = kDefaultTuning,
@@ -586,6 +596,13 @@ __device__ __forceinline__ uint32_t find_col(const Batch &B, uint32_t b) {
         case MC_U32: FN<mc::TU32>(__VA_ARGS__); break;              \
         case MC_U64: FN<mc::TU64>(__VA_ARGS__); break;              \
         default: FN<mc::TS16>(__VA_ARGS__); break;                  \
+    }
+// out = FN<T>(C) for the column's value type
+#define MC_DISPATCH_R(C, OUT, FN)                                   \
+    switch ((C).type) {                                             \
+        case MC_U32: OUT = FN<mc::TU32>(C); break;                  \
+        case MC_U64: OUT = FN<mc::TU64>(C); break;                  \
+        default: OUT = FN<mc::TS16>(C); break;                      \
     }
 
 __global__ __launch_bounds__(256) void kn_zero_results(Batch B) {
@@ -1103,13 +1120,12 @@ constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 3, kMapEm
               kNumMaps = kMapFbEmit + 1;
 constexpr int kNumDevMaps = 2 * kMaxPasses + 1;
 
-// The fallback's maps, one workgroup per device slot: column j keeps its count
-// of the host slot when the prefix sort left it unsorted, else 0; exclusive
-// prefix over the columns, the total in entry ncols.
-__global__ __launch_bounds__(256) void kn_fb_plan(Batch B, const uint32_t *hmaps,
-                                                  uint32_t *dmaps, uint32_t npass) {
-    __shared__ uint32_t part[256];
-    const uint32_t s = blockIdx.x;
+// The fallback's maps, one workgroup per device slot s: column j keeps its
+// count of the host slot when the prefix sort left it unsorted, else 0;
+// exclusive prefix over the columns, the total in entry ncols.  part: 256
+// words of LDS.
+__device__ void fb_plan_slot(const Batch &B, const uint32_t *hmaps, uint32_t *dmaps,
+                             uint32_t npass, uint32_t s, uint32_t *part) {
     const uint32_t hs = s < npass ? kMapFbPass + s
                                   : (s < 2 * npass ? kMapFbScan + (s - npass) : kMapFbEmit);
     const uint32_t ds = s < npass ? s : (s < 2 * npass ? kMaxPasses + (s - npass) : 2 * kMaxPasses);
@@ -1139,6 +1155,11 @@ __global__ __launch_bounds__(256) void kn_fb_plan(Batch B, const uint32_t *hmaps
     }
     if (threadIdx.x == 255) dst[n] = part[255];
 }
+__global__ __launch_bounds__(256) void kn_fb_plan(Batch B, const uint32_t *hmaps,
+                                                  uint32_t *dmaps, uint32_t npass) {
+    __shared__ uint32_t part[256];
+    fb_plan_slot(B, hmaps, dmaps, npass, blockIdx.x, part);
+}
 
 struct BatchPlan {
     uint64_t z_total = 0, b_total = 0, desc_off = 0, map_off = 0, dmap_off = 0, total = 0;
@@ -1147,7 +1168,50 @@ struct BatchPlan {
     std::vector<uint32_t> maps;  // kNumMaps x (ncols + 1)
     uint32_t max_passes = 0;
     uint32_t repack_codes = mc::kRepackCodes;
+    // the persistent launch: its queue plan, the tables' offsets in the
+    // copied block (after the maps), the queue counters' offset in the
+    // zeroed part, and the item sizes
+    bool persistent = false;
+    mcq::Plan q;
+    uint64_t q_off = 0, qbase_off = 0, qpmap_off = 0, qcum_off = 0, qgcum_off = 0;
+    uint32_t repack_per = kPersistRepack, merge_per = kPersistMerge, workers = 0;
 };
+
+// Item counts of the persistent launch: per column and phase (ncols x
+// kNumPhases), and of the global fallback phases.
+void persist_counts(const mc_column_in *ins, uint32_t ncols, const BatchPlan &P,
+                    std::vector<uint32_t> &counts, std::vector<uint32_t> &gcount) {
+    counts.assign((size_t)ncols * mcq::kNumPhases, 0u);
+    gcount.assign(mcq::kNumPhases, 0u);
+    for (uint32_t j = 0; j < ncols; j++) {
+        const ColLayout &L = P.L[j];
+        const bool d = ins[j].delta_rows > 0;
+        uint32_t *c = &counts[(size_t)j * mcq::kNumPhases];
+        const uint32_t scan = L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts : 256u;
+        c[mcq::kHash] = L.hashed ? L.hash_tiles : 0;
+        c[mcq::kCompact] = L.hashed ? (uint32_t)ceil_div(ins[j].delta_rows, mc::kCompactTile) : 0;
+        c[mcq::kHist] = L.hist_tiles;
+        c[mcq::kHScan] = d ? 1 : 0;
+        for (uint32_t sl = 0; sl < (uint32_t)mc::kPrefixSlots; sl++) {
+            c[mcq::kPre0Up + 3 * sl] = d ? L.sort_tiles : 0;
+            c[mcq::kPre0Up + 3 * sl + 1] = d ? scan : 0;
+            c[mcq::kPre0Up + 3 * sl + 2] = d ? L.sort_tiles : 0;
+        }
+        c[mcq::kWin0] = c[mcq::kWin1] = d ? L.sort_tiles : 0;
+        c[mcq::kEmit] = L.emit_tiles;
+        c[mcq::kRank] = L.hashed ? L.hash_tiles : 0;
+        c[mcq::kMPart] = L.partitioned ? (uint32_t)merge_part_blocks(L.merge_tiles) : 0;
+        c[mcq::kMerge] = (uint32_t)ceil_div(L.merge_tiles ? L.merge_tiles : 1, P.merge_per);
+        c[mcq::kXc] = (uint32_t)L.xc_tiles;
+        c[mcq::kRepack] = (uint32_t)ceil_div(L.repack_tiles, P.repack_per);
+    }
+    if (P.max_passes) {
+        gcount[mcq::kFbPlan] = 2 * P.max_passes + 1;  // one map slot each
+        for (uint32_t p = 0; p < P.max_passes; p++)
+            for (uint32_t k = 0; k < 3; k++) gcount[mcq::kFbPass0 + 3 * p + k] = kPersistFbItems;
+        gcount[mcq::kFbEmit] = kPersistFbItems;
+    }
+}
 
 int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs, uint32_t ncols,
                 void *scratch, uint64_t scratch_bytes, hipStream_t stream, const mc_tuning &tune,
@@ -1174,11 +1238,29 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
         b += P.L[i].b_size;
         if (ins[i].delta_rows > 0 && P.L[i].passes > P.max_passes) P.max_passes = P.L[i].passes;
     }
+    P.persistent = tune.batched_launch == MC_BATCHED_PERSISTENT;
+    P.repack_per = tune.persist_repack ? tune.persist_repack : kPersistRepack;
+    P.merge_per = tune.persist_merge ? tune.persist_merge : kPersistMerge;
+    P.workers = tune.persist_workers;
+    if (P.persistent) {  // queue counters after the columns' zeroed parts
+        z = align_up(z, 256);
+        P.q_off = z;
+        z += (uint64_t)(kQColDone + ncols) * 4;
+    }
     P.z_total = align_up(z, 256);
     P.b_total = align_up(b, 256);
     P.desc_off = P.z_total + P.b_total;
     P.map_off = P.desc_off + align_up((uint64_t)ncols * sizeof(mc::ColDesc), 256);
-    P.dmap_off = P.map_off + align_up((uint64_t)P.maps.size() * 4, 256);
+    uint64_t after_maps = P.map_off + align_up((uint64_t)P.maps.size() * 4, 256);
+    if (P.persistent) {  // the queue tables travel with the maps
+        const uint64_t NP = mcq::kNumPhases;
+        P.qbase_off = after_maps;
+        P.qgcum_off = P.qbase_off + align_up((NP + 1) * 4, 256);
+        P.qpmap_off = P.qgcum_off + align_up(NP * 4, 256);
+        P.qcum_off = P.qpmap_off + align_up(NP * (ncols + 1) * 4, 256);
+        after_maps = P.qcum_off + align_up((uint64_t)ncols * NP * 4, 256);
+    }
+    P.dmap_off = after_maps;
     P.total = P.dmap_off + align_up((uint64_t)kNumDevMaps * (ncols + 1) * 4, 256);
     // tile-count prefixes per phase
     auto at = [&](int m, uint32_t j) -> uint32_t & { return P.maps[(size_t)m * (ncols + 1) + j]; };
@@ -1219,6 +1301,12 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
                 return fail(MC_E_ARG, "batch has too many tiles for one launch (2^24 - 1)");
         }
         at(m, ncols) = (uint32_t)acc;
+    }
+    if (P.persistent) {
+        std::vector<uint32_t> counts, gcount;
+        persist_counts(ins, ncols, P, counts, gcount);
+        if (!mcq::build_plan(ncols, counts, gcount, P.q))
+            return fail(MC_E_ARG, "batch has too many work items for one persistent launch");
     }
     return MC_OK;
 }
@@ -1351,6 +1439,372 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
         MC_LAUNCHED("kn_repack");
     }
     return MC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The batched merge as one persistent launch (queue.hpp): a prologue kernel
+// clears the workspace's zeroed part, the queue counters and the results;
+// then every worker of kn_persist takes tickets from one counter, decodes the
+// item (phase, column, index), waits for the item's dependencies (bounded),
+// runs the same tile function as the per-phase launches, and counts the item
+// done.  Items of the re-encode and the dictionary merge are several tiles
+// each (repack_per / merge_per), to spread the per-item cost of the ticket,
+// the decode and the wait.
+// ---------------------------------------------------------------------------
+
+struct PersistArgs {
+    const mc::ColDesc *cols;
+    uint32_t ncols;
+    uint32_t total;           // tickets
+    const uint32_t *base;     // kNumPhases + 1 first tickets
+    const uint32_t *pmap;     // kNumPhases x (ncols + 1) column prefixes
+    const uint32_t *cum;      // ncols x kNumPhases: column counter targets
+    const uint32_t *gcum;     // kNumPhases: fallback counter targets
+    uint32_t emit_total;      // emit items of all columns
+    uint32_t fb_total;        // items of the global fallback phases
+    uint32_t *q;              // queue counters (kQ*), then one done counter per column
+    const uint32_t *hmaps;    // per-phase host maps of the batch (fallback slots used)
+    uint32_t *dmaps;          // device-built maps of the columns that need the fallback
+    uint32_t npass;           // fallback passes (largest value length of the batch)
+    uint32_t fb_items;        // items of each global fallback pass phase
+    uint32_t merge_per;       // merge tiles per item
+    uint32_t repack_per;      // re-encode tiles per item
+};
+
+struct PersistSmem {
+    uint32_t base[mcq::kNumPhases + 1];
+    uint32_t ticket, ph, col, idx, abort;
+};
+
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until *ctr >= target; then every thread of the workgroup
+// acquires (the XCDs' L2 caches are not coherent with each other).  Many
+// workgroups can wait on one counter at once (every item of a column's next
+// phase, every item of the fallback chain), and device-scope loads of one
+// word are served one after another, so the polls back off exponentially
+// (about 128 to 8,000 clocks apart) to leave room for the increments they
+// wait for.  The wait is bounded by time (2 s of the constant 100 MHz
+// clock): on overrun the error bit goes to the item's error word and to the
+// launch's abort word; then every worker skips the rest of its items (see
+// kn_persist), so the launch ends soon after one overrun, with every
+// column's error word flagged.  Returns whether the launch is aborting
+// (the same value for every thread of the workgroup).
+constexpr uint64_t kQueueWaitTicks = 200000000ull;  // 2 s at 100 MHz
+__device__ __forceinline__ bool queue_wait(const uint32_t *ctr, uint32_t target, uint32_t *err,
+                                           uint32_t *abort_word, uint32_t *s_abort) {
+    if (threadIdx.x == 0) {
+        uint32_t ab = ld_u32(abort_word) & MC_DEVERR_SPIN;
+        if (!ab && ld_u32(ctr) < target) {
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            uint32_t nap = 1;  // s_sleep(2) rounds (about 128 clocks each) between polls
+            while (true) {
+                for (uint32_t q = 0; q < nap; q++) __builtin_amdgcn_s_sleep(2);
+                if (ld_u32(ctr) >= target) break;
+                ab = ld_u32(abort_word) & MC_DEVERR_SPIN;
+                if (ab) break;
+                if (__builtin_amdgcn_s_memrealtime() - t0 > kQueueWaitTicks) {
+                    mc::flag_error(abort_word, MC_DEVERR_SPIN);
+                    ab = MC_DEVERR_SPIN;
+                    break;
+                }
+                if (nap < 64) nap <<= 1;
+            }
+        }
+        if (ab) mc::flag_error(err, MC_DEVERR_SPIN);
+        *s_abort = ab;
+    }
+    __syncthreads();
+    __threadfence();
+    return *s_abort != 0;
+}
+
+// Decode ticket k with wave 0 (64-lane searches: the phase over the staged
+// bases, then the column over the phase's prefix map); the result lands in S.
+__device__ inline void queue_decode(const PersistArgs &A, PersistSmem &S, uint32_t k) {
+    if (mc::wave_id() != 0) return;
+    const int lane = mc::lane_id();
+    constexpr uint32_t NP = mcq::kNumPhases;
+    // phase = number of x in [1, NP) with base[x] <= k (bases never decrease)
+    uint32_t ph = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < 2; r++) {
+        const uint32_t x = r * 64 + (uint32_t)lane;
+        ph += (uint32_t)__popcll(__ballot(x >= 1 && x < NP && S.base[x] <= k));
+    }
+    const uint32_t off = k - S.base[ph];
+    uint32_t col = 0, idx = off;
+    if (!mcq::is_global(ph)) {
+        const uint32_t *m = A.pmap + (size_t)ph * (A.ncols + 1);
+        // the last column j in [lo, hi) with m[j] <= off (m[0] = 0 <= off)
+        uint32_t lo = 0, hi = A.ncols;
+        while (hi - lo > 1) {
+            const uint32_t step = (hi - lo + 63) / 64;
+            const uint32_t x = lo + (uint32_t)lane * step;
+            const bool pred = lane >= 1 && x < hi && m[x] <= off;
+            const uint32_t cnt = (uint32_t)__popcll(__ballot(pred));
+            lo += cnt * step;
+            hi = min(hi, lo + step);
+        }
+        col = lo;
+        idx = off - m[lo];
+    }
+    if (lane == 0) {
+        S.ph = ph;
+        S.col = col;
+        S.idx = idx;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ uint32_t merge_tiles_of(const mc::ColDesc &C) {
+    const uint64_t t = (C.n_um + C.nd_max + mc::merge_tile<T>() - 1) / mc::merge_tile<T>();
+    return t ? (uint32_t)t : 1u;
+}
+
+// One item of a per-column phase.
+template <int CODES>
+__device__ void run_column_item(const PersistArgs &A, uint32_t ph, uint32_t j, uint32_t idx,
+                                char *smem) {
+    const mc::ColDesc &C = A.cols[j];
+    if (ph == mcq::kHash) {
+        MC_DISPATCH(C, mc::hash_insert_tile, C, idx, smem);
+    } else if (ph == mcq::kCompact) {
+        MC_DISPATCH(C, mc::compact_tile, C, idx, smem);
+    } else if (ph == mcq::kHist) {
+        MC_DISPATCH(C, mc::hist_tile, C, idx, smem);
+    } else if (ph == mcq::kHScan) {
+        MC_DISPATCH(C, mc::hist_scan_col, C, smem);
+    } else if (ph >= mcq::kPre0Up && ph < mcq::kWin0) {
+        const int slot = (int)(ph - mcq::kPre0Up) / 3, kind = (int)(ph - mcq::kPre0Up) % 3;
+        const mc::PassIO io = mc::prefix_io(C, slot);
+        if (kind == 0) {
+            MC_DISPATCH(C, mc::sort_up_tile, C, io, idx, smem);
+        } else if (kind == 1) {
+            if (C.sort_tiles <= mc::kSmallScanTiles) {
+                MC_DISPATCH(C, mc::sort_scan_small, C, io, idx);
+            } else {
+                MC_DISPATCH(C, mc::sort_scan_digit, C, io, idx, smem);
+            }
+        } else {
+            MC_DISPATCH(C, mc::sort_down_tile, C, io, idx, smem);
+        }
+    } else if (ph == mcq::kWin0) {
+        MC_DISPATCH(C, mc::window_sort_tile, C, idx, smem);
+    } else if (ph == mcq::kWin1) {
+        MC_DISPATCH(C, mc::window_seam_tile, C, idx, smem);
+    } else if (ph == mcq::kEmit) {
+        if (C.drankd) {
+            MC_DISPATCH(C, mc::emit_distinct_tile, C, idx, false);
+        } else {
+            MC_DISPATCH(C, mc::emit_tile, C, smem, false);
+        }
+    } else if (ph == mcq::kRank) {
+        mc::rank_rows_tile(C, idx);
+    } else if (ph == mcq::kMPart) {
+        MC_DISPATCH(C, mc::merge_partition, C, idx);
+    } else if (ph == mcq::kMerge) {
+        // tiles [idx * merge_per, ...) of the column, each from its own ticket
+        uint32_t n = 0;
+        MC_DISPATCH_R(C, n, merge_tiles_of);
+        const uint32_t t0 = idx * A.merge_per, t1 = min(n, t0 + A.merge_per);
+        for (uint32_t t = t0; t < t1; t++) {
+            if (t != t0) __syncthreads();
+            MC_DISPATCH(C, mc::merge_tile, C, smem);
+        }
+    } else if (ph == mcq::kXc) {
+        mc::xcompact_tile(C, idx, smem);
+    } else if (ph == mcq::kRepack) {
+        const uint64_t n = (C.n_main + C.nd + CODES - 1) / CODES;
+        const uint64_t t0 = (uint64_t)idx * A.repack_per;
+        const uint64_t t1 = min<uint64_t>(n, t0 + A.repack_per);
+        for (uint64_t t = t0; t < t1; t++) {
+            if (t != t0) __syncthreads();
+            mc::repack_tile<CODES>(C, t, smem);
+        }
+    }
+}
+
+// One item of a global fallback phase: item i strides over the device-built
+// map of the phase (only the columns the prefix sort left unsorted).
+__device__ void run_fallback_item(const PersistArgs &A, PersistSmem &S, uint32_t ph, uint32_t i,
+                                  char *smem) {
+    if (ph == mcq::kFbPlan) {
+        Batch B{A.cols, nullptr, A.ncols};
+        fb_plan_slot(B, A.hmaps, A.dmaps, A.npass, i, reinterpret_cast<uint32_t *>(smem));
+        return;
+    }
+    const bool emit = ph == mcq::kFbEmit;
+    const uint32_t p = emit ? 0u : (ph - mcq::kFbPass0) / 3, kind = emit ? 0u : (ph - mcq::kFbPass0) % 3;
+    const int ds = emit ? 2 * kMaxPasses : (kind == 1 ? kMaxPasses + (int)p : (int)p);
+    Batch B{A.cols, A.dmaps + (size_t)ds * (A.ncols + 1), A.ncols};
+    const uint32_t total = map_total(B);
+    for (uint32_t b = i; b < total; b += A.fb_items) {
+        if (b != i) __syncthreads();
+        const uint32_t j = find_col(B, b);
+        const mc::ColDesc &C = A.cols[j];
+        const uint32_t t = b - B.map[j];
+        if (emit) {
+            if (C.drankd) {
+                MC_DISPATCH(C, mc::emit_distinct_tile, C, t, true);
+            } else {
+                MC_DISPATCH(C, mc::emit_tile, C, smem, true);
+            }
+            continue;
+        }
+        mc::PassIO io;
+        if (!pass_io(C, kPassFull, (int)p, &io)) continue;
+        if (kind == 0) {
+            MC_DISPATCH(C, mc::sort_up_tile, C, io, t, smem);
+        } else if (kind == 1) {
+            if (C.sort_tiles <= mc::kSmallScanTiles) {
+                MC_DISPATCH(C, mc::sort_scan_small, C, io, t);
+            } else {
+                MC_DISPATCH(C, mc::sort_scan_digit, C, io, t, smem);
+            }
+        } else {
+            MC_DISPATCH(C, mc::sort_down_tile, C, io, t, smem);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void kn_prologue(Batch B, uint32_t *z, uint64_t nz) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nz; i += stride)
+        z[i] = 0u;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < B.ncols; j += stride) {
+        mc_result *r = B.cols[j].result;
+        r->new_dict_len = 0;
+        r->new_codes_words = 0;
+        r->delta_dict_len = 0;
+        r->new_bitwidth = 0;
+        r->error = 0;
+    }
+}
+
+// At most 168 VGPRs (three waves per SIMD): the hot steps fit; the widest
+// (the multi-type sort and fallback paths) spill a little.  Its LDS (the
+// largest tile, 52 KB) also leaves room for three workgroups per CU.
+template <int CODES>
+__global__ __launch_bounds__(256, 3) void kn_persist(PersistArgs A) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ PersistSmem S;
+    for (uint32_t x = threadIdx.x; x <= mcq::kNumPhases; x += blockDim.x) S.base[x] = A.base[x];
+    __syncthreads();
+    uint32_t *const ticket = A.q + kQTicket;
+    uint32_t *const colq = A.q + kQColDone;
+    while (true) {
+        if (threadIdx.x == 0) S.ticket = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t k = S.ticket;
+        if (k >= A.total) break;
+        queue_decode(A, S, k);
+        __syncthreads();
+        const uint32_t ph = S.ph, j = S.col, idx = S.idx;
+        if (mcq::is_global(ph)) {
+            const bool ab = ph == mcq::kFbPlan
+                                ? queue_wait(A.q + kQEmitDone, A.emit_total, A.q + kQErr,
+                                             A.q + kQErr, &S.abort)
+                                : queue_wait(A.q + kQFbDone, A.gcum[ph], A.q + kQErr, A.q + kQErr,
+                                             &S.abort);
+            if (!ab) run_fallback_item(A, S, ph, idx, smem);
+        } else {
+            const mc::ColDesc &C = A.cols[j];
+            bool ab = queue_wait(colq + j, A.cum[(size_t)j * mcq::kNumPhases + ph], C.err,
+                                 A.q + kQErr, &S.abort);
+            if (!ab && mcq::after_fallback(ph)) {
+                // a column the prefix sort left unsorted waits for the fallback
+                // chain (the flag is final once the column's Step 1(a) items
+                // are done; thread 0 reads it so that the whole workgroup
+                // takes the same branch)
+                if (threadIdx.x == 0) S.idx = C.sflags[mc::kSfUnsorted];
+                __syncthreads();
+                if (S.idx)
+                    ab = queue_wait(A.q + kQFbDone, A.fb_total, A.q + kQErr, A.q + kQErr, &S.abort);
+            }
+            // an aborted launch skips its items: none runs on inputs that were
+            // not finished
+            if (!ab) run_column_item<CODES>(A, ph, j, idx, smem);
+        }
+        // the item's writes, then its count (release at device scope)
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (mcq::is_global(ph)) {
+                atomicAdd(A.q + kQFbDone, 1u);
+            } else {
+                atomicAdd(colq + j, 1u);
+                if (ph == mcq::kEmit) atomicAdd(A.q + kQEmitDone, 1u);
+            }
+        }
+    }
+}
+
+// Dynamic LDS of kn_persist: the largest tile function it runs.
+template <int CODES>
+constexpr size_t persist_lds() {
+    constexpr size_t a = max3(kSmemHist, kSmemHistScan, kSmemDown);
+    constexpr size_t b = max3(sizeof(mc::EmitSmem<mc::TS16>), kSmemHash, sizeof(mc::CompactSmem));
+    constexpr size_t c = max3(sizeof(mc::MergeSmem<mc::TU32>), sizeof(mc::MergeSmem<mc::TU64>),
+                              sizeof(mc::MergeSmem<mc::TS16>));
+    constexpr size_t d = max3(sizeof(mc::XCompactSmem), sizeof(mc::RepackOutSmem<CODES>), kSmemSmall);
+    return max3(max3(a, b, c), d, (size_t)64);
+}
+
+template <int CODES>
+int launch_persist(const BatchPlan &P, uint32_t ncols, char *ws, uint32_t cus, hipStream_t s) {
+    PersistArgs A;
+    A.cols = reinterpret_cast<const mc::ColDesc *>(ws + P.desc_off);
+    A.ncols = ncols;
+    A.total = P.q.total();
+    A.base = reinterpret_cast<const uint32_t *>(ws + P.qbase_off);
+    A.pmap = reinterpret_cast<const uint32_t *>(ws + P.qpmap_off);
+    A.cum = reinterpret_cast<const uint32_t *>(ws + P.qcum_off);
+    A.gcum = reinterpret_cast<const uint32_t *>(ws + P.qgcum_off);
+    A.emit_total = P.q.emit_total;
+    A.fb_total = P.q.fb_total;
+    A.q = reinterpret_cast<uint32_t *>(ws + P.q_off);
+    A.hmaps = reinterpret_cast<const uint32_t *>(ws + P.map_off);
+    A.dmaps = reinterpret_cast<uint32_t *>(ws + P.dmap_off);
+    A.npass = P.max_passes;
+    A.fb_items = kPersistFbItems;
+    A.merge_per = P.merge_per;
+    A.repack_per = P.repack_per;
+    constexpr size_t lds = persist_lds<CODES>();
+    uint32_t workers = P.workers;
+    if (!workers) {  // as many as the GPU holds at once
+        int per_cu = 0;
+        MC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kn_persist<CODES>, mc::kBlock,
+                                                            lds));
+        workers = (uint32_t)std::max(1, per_cu) * std::max(1u, cus);
+    }
+    workers = std::max(1u, std::min(workers, A.total));
+    if (A.total == 0) return MC_OK;
+    hipLaunchKernelGGL(kn_persist<CODES>, dim3(workers), dim3(mc::kBlock), lds, s, A);
+    MC_LAUNCHED("kn_persist");
+    return MC_OK;
+}
+
+// The persistent form of the batched merge: the prologue (zeroed part with
+// the queue counters, result scalars), then one persistent launch.
+int enqueue_persist(const BatchPlan &P, uint32_t ncols, char *ws, uint32_t cus, hipStream_t s) {
+    Batch B;
+    B.cols = reinterpret_cast<const mc::ColDesc *>(ws + P.desc_off);
+    B.map = nullptr;
+    B.ncols = ncols;
+    const uint64_t nz = P.z_total / 4;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(
+        std::max<uint64_t>(ceil_div(std::max<uint64_t>(nz, ncols), 256 * 4), 1), 2048);
+    hipLaunchKernelGGL(kn_prologue, dim3(grid), dim3(256), 0, s, B, reinterpret_cast<uint32_t *>(ws),
+                       nz);
+    MC_LAUNCHED("kn_prologue");
+    switch (P.repack_codes) {
+        case 1024: return launch_persist<1024>(P, ncols, ws, cus, s);
+        case 4096: return launch_persist<4096>(P, ncols, ws, cus, s);
+        default: return launch_persist<2048>(P, ncols, ws, cus, s);
+    }
 }
 
 }  // namespace
@@ -1827,6 +2281,14 @@ int mc_ctx_set_tuning(mc_ctx *ctx, const mc_tuning *t) {
         return fail(MC_E_ARG, "repack_codes must be 1024, 2048 or 4096");
     if (t->prefix_run < 4 || t->prefix_run > 1024)
         return fail(MC_E_ARG, "prefix_run must be in [4, 1024]");
+    if (t->batched_launch != MC_BATCHED_PHASES && t->batched_launch != MC_BATCHED_PERSISTENT)
+        return fail(MC_E_ARG, "batched_launch must be MC_BATCHED_PHASES or MC_BATCHED_PERSISTENT");
+    if (t->batched_launch == MC_BATCHED_PERSISTENT)
+        return fail(MC_E_ARG,
+                    "MC_BATCHED_PERSISTENT is disabled: its launch stalled on the GPU (also with "
+                    "one workgroup) and the cause is not found; use MC_BATCHED_PHASES");
+    if (t->persist_repack > 1024 || t->persist_merge > 1024)
+        return fail(MC_E_ARG, "persist_repack and persist_merge must be at most 1024");
     if (t->reserved) return fail(MC_E_ARG, "the reserved field must be zero");
     ctx->tune = *t;
     return MC_OK;
@@ -1938,10 +2400,20 @@ int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
     for (uint32_t i = 0; i < ncols; i++)
         hd[i] = make_desc(&ins[i], &outs[i], ws + P.z_off[i], ws + P.z_total + P.b_off[i], P.L[i]);
     memcpy(h + (P.map_off - P.desc_off), P.maps.data(), P.maps.size() * 4);
+    if (P.persistent) {
+        memcpy(h + (P.qbase_off - P.desc_off), P.q.base.data(), P.q.base.size() * 4);
+        memcpy(h + (P.qgcum_off - P.desc_off), P.q.gcum.data(), P.q.gcum.size() * 4);
+        memcpy(h + (P.qpmap_off - P.desc_off), P.q.pmap.data(), P.q.pmap.size() * 4);
+        memcpy(h + (P.qcum_off - P.desc_off), P.q.cum.data(), P.q.cum.size() * 4);
+    }
     MC_HIP(hipMemcpyAsync(ws + P.desc_off, h, meta, hipMemcpyHostToDevice, stream));
     MC_HIP(hipEventRecord(ctx->meta_event, stream));
 
-    if (!graph) return enqueue_batch(P, ncols, ws, stream);
+    auto enqueue = [&](hipStream_t st) {
+        return P.persistent ? enqueue_persist(P, ncols, ws, ctx->cus, st)
+                            : enqueue_batch(P, ncols, ws, st);
+    };
+    if (!graph) return enqueue(stream);
 
     mc_graph *g = new (std::nothrow) mc_graph();
     if (!g) return fail(MC_E_NOMEM, "graph allocation failed");
@@ -1953,7 +2425,7 @@ int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        rc = enqueue_batch(P, ncols, ws, cs);
+        rc = enqueue(cs);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &gr);
         if (rc == MC_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");

@@ -89,7 +89,7 @@ __device__ __forceinline__ uint32_t global_rep(const ColDesc &C, typename T::K k
 // so only the first occurrence of each value probes the global table (a
 // frequent value then costs one global probe per tile, not one per row).
 template <class T>
-__device__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
+__device__ __forceinline__ void hash_insert_tile(const ColDesc &C, uint64_t t, char *smem) {
     typedef typename T::K K;
     HashSmem<T> &S = *reinterpret_cast<HashSmem<T> *>(smem);
     const uint64_t r0 = C.hrow0 + t * kHashTile;
@@ -191,7 +191,7 @@ constexpr int kCompactItems = 8;
 constexpr int kCompactTile = kBlock * kCompactItems;
 
 template <class T>
-__device__ void compact_tile(const ColDesc &C, uint64_t t, char *smem) {
+__device__ __forceinline__ void compact_tile(const ColDesc &C, uint64_t t, char *smem) {
     CompactSmem &S = *reinterpret_cast<CompactSmem *>(smem);
     const uint64_t r0 = C.hrow0 + t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
     uint32_t flags = 0;
@@ -233,7 +233,7 @@ __device__ void compact_tile(const ColDesc &C, uint64_t t, char *smem) {
 // starts a new value.  again: as for emit_tile (the run after the full LSD
 // sort, only when the first run found the order wrong).
 template <class T>
-__device__ void emit_distinct_tile(const ColDesc &C, uint64_t t, bool again) {
+__device__ __forceinline__ void emit_distinct_tile(const ColDesc &C, uint64_t t, bool again) {
     if (again && C.sflags[kSfUnsorted] == 0) return;
     const void *keys = C.keys1;  // sorted values (both sorts end in keys1 / vals1)
     const uint32_t *rows = C.vals1;
@@ -268,7 +268,7 @@ __device__ void emit_distinct_tile(const ColDesc &C, uint64_t t, bool again) {
     if (t == 0 && threadIdx.x == 0) *C.n_ud = n;
 }
 
-__device__ inline void rank_rows_tile(const ColDesc &C, uint64_t t) {
+__device__ __forceinline__ void rank_rows_tile(const ColDesc &C, uint64_t t) {
     const uint64_t n = sort_n(C);
     bool bad = false;
     // three rounds of gathers (representative, its distinct position, that

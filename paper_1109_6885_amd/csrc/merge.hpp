@@ -123,7 +123,7 @@ __device__ __forceinline__ uint64_t co_rank_wave(uint64_t k, uint64_t a, uint64_
 // merge tiles start without a search through global memory.  Each wave
 // returns on its own; there is no barrier.
 template <class T, int ITEMS = MergeCfg<T>::kItems>
-__device__ void merge_partition(const ColDesc &C, uint32_t blk) {
+__device__ __forceinline__ void merge_partition(const ColDesc &C, uint32_t blk) {
     const uint64_t q = (uint64_t)blk * kWaves + wave_id();
     const uint64_t a = C.n_um;
     const uint64_t b = min(*C.n_ud_in, C.nd_max);
@@ -138,7 +138,7 @@ __device__ void merge_partition(const ColDesc &C, uint32_t blk) {
 }
 
 template <class T, int ITEMS = MergeCfg<T>::kItems>
-__device__ void merge_tile(const ColDesc &C, char *smem) {
+__device__ __forceinline__ void merge_tile(const ColDesc &C, char *smem) {
     MergeSmem<T, ITEMS> &S = *reinterpret_cast<MergeSmem<T, ITEMS> *>(smem);
     if (threadIdx.x == 0) S.tile = atomicAdd(&C.counters[1], 1u);
     __syncthreads();

@@ -10,7 +10,7 @@
 namespace mc {
 
 template <class T>
-__device__ void naive_tile(const ColDesc &C, uint64_t t, char *smem) {
+__device__ __forceinline__ void naive_tile(const ColDesc &C, uint64_t t, char *smem) {
     typedef typename T::N N;
     RepackSmem &S = *reinterpret_cast<RepackSmem *>(smem);
     const uint32_t w = C.w;

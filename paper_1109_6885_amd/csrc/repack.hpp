@@ -127,7 +127,7 @@ __device__ __forceinline__ uint32_t xs_at(uint32_t j) { return j + j / kXspBlock
 // Both compact forms of one tile of X_M: the 16-bit deviations of every
 // entry and, if the column has room for them, the sparse records of the
 // tile's 32 blocks.
-__device__ inline void xcompact_tile(const ColDesc &C, uint64_t t, char *smem) {
+__device__ __forceinline__ void xcompact_tile(const ColDesc &C, uint64_t t, char *smem) {
     uint32_t *s_x = reinterpret_cast<XCompactSmem *>(smem)->x;
     const uint64_t c0 = t * kXCompactTile;
     if (c0 >= C.n_um) return;
@@ -192,7 +192,7 @@ __device__ inline void xcompact_tile(const ColDesc &C, uint64_t t, char *smem) {
 // Stage the packed main words of the tile starting at row c0 into LDS with
 // 128-bit loads (streamed once: non-temporal, so the tables keep the cache).
 template <int CODES = kRepackCodes>
-__device__ inline void stage_main_words(const ColDesc &C, uint64_t c0, uint64_t *s_in) {
+__device__ __forceinline__ void stage_main_words(const ColDesc &C, uint64_t c0, uint64_t *s_in) {
     if (c0 >= C.n_main) return;
     const uint32_t w = C.w;
     const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
@@ -232,7 +232,7 @@ __device__ __forceinline__ uint32_t decode_code_nb(const uint64_t *s_in, uint32_
 // Assemble the tile's output words from its new codes (s_code, zero past the
 // last row) and store them with 128-bit writes.
 template <int CODES = kRepackCodes>
-__device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint32_t *s_code,
+__device__ __forceinline__ void pack_store_tile(const ColDesc &C, uint64_t t, const uint32_t *s_code,
                                        uint32_t wn, uint64_t n_out) {
     // local word k covers tile bits [64k, 64k + 64)
     const uint64_t obase = t * (uint64_t)(CODES / 64) * wn;
@@ -274,7 +274,7 @@ __device__ inline void pack_store_tile(const ColDesc &C, uint64_t t, const uint3
 }
 
 template <int CODES = kRepackCodes>
-__device__ inline void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
+__device__ __forceinline__ void repack_tile(const ColDesc &C, uint64_t t, char *smem) {
     constexpr int PER = CODES / kBlock;  // consecutive codes per thread
     RepackOutSmem<CODES> &S = *reinterpret_cast<RepackOutSmem<CODES> *>(smem);
     uint64_t *s_in = S.in;

@@ -131,7 +131,7 @@ struct DownSmem {
 // ---- histograms of all digit positions in one read ----------------------
 
 template <class T>
-__device__ void hist_tile(const ColDesc &C, uint32_t blk, char *smem) {
+__device__ __forceinline__ void hist_tile(const ColDesc &C, uint32_t blk, char *smem) {
     constexpr int P = T::kBytes;
     HistSmem<T> &S = *reinterpret_cast<HistSmem<T> *>(smem);
     for (int i = threadIdx.x; i < P * 256; i += kBlock) S.h[i] = 0;
@@ -164,7 +164,7 @@ __device__ void hist_tile(const ColDesc &C, uint32_t blk, char *smem) {
 }
 
 template <class T>
-__device__ void hist_scan_col(const ColDesc &C, char *smem) {
+__device__ __forceinline__ void hist_scan_col(const ColDesc &C, char *smem) {
     constexpr int P = T::kBytes;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
     uint32_t *ndig = tmp + kWaves;  // distinct digits per position
@@ -236,7 +236,7 @@ __device__ void hist_scan_col(const ColDesc &C, char *smem) {
 // ---- one pass: per-tile counts -------------------------------------------
 
 template <class T>
-__device__ void sort_up_tile(const ColDesc &C, const PassIO &io, uint32_t t, char *smem) {
+__device__ __forceinline__ void sort_up_tile(const ColDesc &C, const PassIO &io, uint32_t t, char *smem) {
     const int p = io.p;
     if (p < 0) return;
     constexpr int TILE = sort_tile<T>();
@@ -267,7 +267,7 @@ __device__ void sort_up_tile(const ColDesc &C, const PassIO &io, uint32_t t, cha
 // position of every (digit, tile).
 
 template <class T>
-__device__ void sort_scan_digit(const ColDesc &C, const PassIO &io, uint32_t d, char *smem) {
+__device__ __forceinline__ void sort_scan_digit(const ColDesc &C, const PassIO &io, uint32_t d, char *smem) {
     const int p = io.p;
     if (p < 0) return;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(smem);
@@ -306,7 +306,7 @@ constexpr uint32_t kSmallScanTiles = 128;
 constexpr uint32_t kSmallScanParts = 4;
 
 template <class T>
-__device__ void sort_scan_small(const ColDesc &C, const PassIO &io, uint32_t part) {
+__device__ __forceinline__ void sort_scan_small(const ColDesc &C, const PassIO &io, uint32_t part) {
     const int p = io.p;
     if (p < 0) return;
     const int lane = lane_id(), wv = wave_id();
@@ -392,7 +392,7 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&dig)[ITEMS], uint32
 // ---- one pass: rank and scatter --------------------------------------------
 
 template <class T>
-__device__ void sort_down_tile(const ColDesc &C, const PassIO &io, uint32_t t, char *smem) {
+__device__ __forceinline__ void sort_down_tile(const ColDesc &C, const PassIO &io, uint32_t t, char *smem) {
     typedef typename T::K K;
     constexpr int ITEMS = SortCfg<T>::kItems;
     constexpr int TILE = sort_tile<T>();
@@ -478,7 +478,7 @@ __device__ __forceinline__ uint32_t prefix_of(const typename T::K &k, const int 
 }
 
 template <class T>
-__device__ void window_sort_tile(const ColDesc &C, uint32_t t, char *smem) {
+__device__ __forceinline__ void window_sort_tile(const ColDesc &C, uint32_t t, char *smem) {
     typedef typename T::K K;
     constexpr int ITEMS = SortCfg<T>::kItems;
     constexpr int TILE = sort_tile<T>();
@@ -577,7 +577,7 @@ __device__ void window_sort_tile(const ColDesc &C, uint32_t t, char *smem) {
 // flagged.  Seams are at least 1536 values apart, so the ranges of two
 // seams never overlap.
 template <class T>
-__device__ void window_seam_tile(const ColDesc &C, uint32_t t, char *smem) {
+__device__ __forceinline__ void window_seam_tile(const ColDesc &C, uint32_t t, char *smem) {
     typedef typename T::K K;
     constexpr int TILE = sort_tile<T>();
     static_assert(TILE >= 2 * (int)(kRunLimit + 1), "seam ranges must not overlap");
@@ -660,7 +660,7 @@ struct EmitSmem {
 // order; again = true: the emit after the full LSD sort, only when that check
 // failed (its own tile counter and prefix words).
 template <class T>
-__device__ void emit_tile(const ColDesc &C, char *smem, bool again) {
+__device__ __forceinline__ void emit_tile(const ColDesc &C, char *smem, bool again) {
     typedef typename T::K K;
     EmitSmem<T> &S = *reinterpret_cast<EmitSmem<T> *>(smem);
     if (again && C.sflags[kSfUnsorted] == 0) return;

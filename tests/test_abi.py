@@ -45,7 +45,7 @@ def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(_lib.McResult) == 32
     assert ctypes.sizeof(_lib.McColumnIn) == 56
     assert ctypes.sizeof(_lib.McColumnOut) == 56
-    assert ctypes.sizeof(_lib.McTuning) == 16
+    assert ctypes.sizeof(_lib.McTuning) == 32
     assert ctypes.sizeof(_lib.McDeltaIndex) == 32
 
 

@@ -645,7 +645,8 @@ def test_launch_shapes_do_not_change_results(codes, run):
     """Every re-encode tile size and prefix-run target gives the same bytes."""
     ctx = cm.Context(torch.cuda.current_device())
     ctx.set_tuning(repack_codes=codes, prefix_run=run)
-    assert ctx.get_tuning() == {"repack_codes": codes, "prefix_run": run, "hash_min_rows": 0}
+    got = ctx.get_tuning()
+    assert (got["repack_codes"], got["prefix_run"], got["hash_min_rows"]) == (codes, run, 0)
     rng = np.random.default_rng(codes + run)
     for vtype, shape in (("u32", (3000, 9_001, 4_097, 0.5)), ("u64", (70_000, 123_457, 50_001, 0.9)),
                          ("str16", (20_000, 40_000, 30_011, 0.3))):
@@ -679,10 +680,13 @@ def test_hash_route_on_every_shape(vtype):
 def test_set_tuning_rejects_bad_shapes():
     ctx = cm.Context(torch.cuda.current_device())
     for kw in ({"repack_codes": 3000}, {"repack_codes": 512}, {"prefix_run": 3},
-               {"prefix_run": 2048}):
+               {"prefix_run": 2048}, {"batched_launch": 2}, {"batched_launch": 1},
+               {"persist_repack": 1025}, {"persist_merge": 5000}):
         with pytest.raises(cm.ColmergeError):
             ctx.set_tuning(**kw)
-    assert ctx.get_tuning() == {"repack_codes": 2048, "prefix_run": 32, "hash_min_rows": 0}
+    assert ctx.get_tuning() == {"repack_codes": 2048, "prefix_run": 32, "hash_min_rows": 0,
+                                "batched_launch": 0, "persist_workers": 0, "persist_repack": 0,
+                                "persist_merge": 0}
 
 
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
