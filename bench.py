@@ -239,11 +239,15 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
             "autotuned": tune, "autotune_candidate_ms": tune_ms}
 
 
-def bench_serve(args):
+def bench_serve(args, plain=False):
     """Served merge stream: 64 resident tables (10-200 columns each, column
     shapes as in the batched workload) built in HBM, appends every 10 ms from
-    pinned pools on an append stream, merge requests arriving as a Poisson
-    process, admission under the memory budget.  Prints one JSON line."""
+    pinned pools on an append stream (from a host thread of their own),
+    merge requests arriving as a Poisson process, admission under the memory
+    budget.  plain: every merge as one mc_merge_column call per column
+    instead of one batched launch sequence.  Returns a dict (one JSON line
+    with --serve)."""
+    import threading
     import numpy as np
     import torch
 
@@ -255,7 +259,7 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     t = time.time()
     shapes = gpu_gen.served_shapes(64, scale)
-    ex = serve.GpuExecutor(n_streams=4)
+    ex = serve.GpuExecutor(n_streams=4, plain=plain)
     budget = int(args.serve_budget_gb * 1e9)
     srv = serve.Server(ex, budget_bytes=budget, max_inflight=4, merge_trigger=args.serve_trigger)
     tick = 0.01
@@ -310,29 +314,55 @@ def bench_serve(args):
         arrivals.append((tt, int(arr_rng.integers(0, 64))))
     srv.t0 = srv.clock()
     t0 = srv.t0
-    next_tick, ticks, late_ticks, ai = t0, 0, 0, 0
+    ex.start_clock(t0)
+    sys.setswitchinterval(0.0005)  # the append thread and the merge loop share the interpreter
+    stop = threading.Event()
+    tick_stats = {"ticks": 0, "late": 0, "offered_rows": 0}
+
+    def appender():
+        # every 10 ms, one batch per table (from its pinned pool), each append
+        # under the server's lock; a tick that starts after its time is late
+        next_tick = t0
+        while not stop.is_set():
+            now = srv.clock()
+            if now - t0 >= horizon:
+                break
+            if now < next_tick:
+                time.sleep(min(0.001, next_tick - now))
+                continue
+            k = tick_stats["ticks"]
+            for tid, pool in pools.items():
+                b = pool[k % 4]
+                srv.append(tid, b)
+                tick_stats["offered_rows"] += b["n"]
+            tick_stats["ticks"] += 1
+            next_tick += tick
+            if srv.clock() > next_tick:
+                tick_stats["late"] += 1
+
+    th = threading.Thread(target=appender, daemon=True)
+    th.start()
+    ai = 0
     next_log = t0 + 1.0
     reqs = []
     while True:
         now = srv.clock()
         if now - t0 >= horizon:
             break
-        if now >= next_tick:
-            for tid, pool in pools.items():
-                srv.append(tid, pool[ticks % 4])
-            ticks += 1
-            next_tick += tick
-            if srv.clock() > next_tick:
-                late_ticks += 1
         while ai < len(arrivals) and arrivals[ai][0] <= now - t0:
             reqs.append(srv.submit_merge(arrivals[ai][1]))
             ai += 1
-        srv.poll()
+        if not srv.poll():
+            time.sleep(0.0002)
         if now >= next_log:
             next_log += 1.0
-            log(f"t={now - t0:.1f}s: {len(srv.done)} committed, {len(srv.queue)} queued, "
-                f"{len(srv.running)} running, {srv.in_use() / 1e9:.1f} GB in use, "
-                f"backpressure {srv.backpressure}")
+            with srv.lock:
+                log(f"t={now - t0:.1f}s{' plain' if plain else ''}: {len(srv.done)} committed, "
+                    f"{len(srv.queue)} queued, {len(srv.running)} running, "
+                    f"{srv.in_use() / 1e9:.1f} GB in use, backpressure {srv.backpressure}")
+    stop.set()
+    th.join()
+    ticks, late_ticks = tick_stats["ticks"], tick_stats["late"]
     t_end = srv.clock()
     log(f"arrivals done: {len(reqs)} requests, {len(srv.done)} committed, "
         f"{len(srv.queue)} queued, {len(srv.running)} running")
@@ -344,6 +374,7 @@ def bench_serve(args):
         reqs = list(srv.done)
     counted = [r for r in reqs if r.arrival - t0 >= args.serve_warmup and r.committed is not None]
     lat = np.array([r.latency for r in counted]) if counted else np.zeros(0)
+    dlat = np.array([r.device_latency for r in counted if r.device_latency is not None])
     window = t_end - (t0 + args.serve_warmup)
     st = srv.stats()
     out = {
@@ -359,8 +390,14 @@ def bench_serve(args):
         "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
         "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
         "max_ms": float(lat.max() * 1e3) if lat.size else None,
+        "latency": "arrival to commit (the merge loop's host thread observes completion)",
+        "device_p50_ms": float(np.percentile(dlat, 50) * 1e3) if dlat.size else None,
+        "device_p99_ms": float(np.percentile(dlat, 99) * 1e3) if dlat.size else None,
+        "device_latency": "arrival to the end of the merge's last kernel (device clock)",
+        "merge_launch": "plain (mc_merge_column per column)" if plain else "batched",
         "merged_tuples_s": sum(r.rows for r in counted) / window if window > 0 else None,
         "appended_rows_s": st["appended_rows"] / (t_end - t0),
+        "offered_rows_s": tick_stats["offered_rows"] / (t_end - t0),
         "admission_waits": st["admission_waits"], "backpressure": st["backpressure"],
         "rejected": st["rejected"], "auto_requests": st["auto_requests"],
         "late_ticks": late_ticks, "ticks": ticks,
@@ -615,6 +652,8 @@ def main():
                     help="run only the served merge stream and print its JSON line")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served merge stream in the default run")
+    ap.add_argument("--serve-plain", action="store_true",
+                    help="with --serve: merges as one mc_merge_column call per column")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="row and append-rate scale of the served tables")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -632,7 +671,7 @@ def main():
               "which is not built)", file=sys.stderr)
         sys.exit(2)
     if args.serve:
-        print(json.dumps(bench_serve(args)), flush=True)
+        print(json.dumps(bench_serve(args, plain=args.serve_plain)), flush=True)
         return
     if args.sweep:
         fn = {"fig7": bench_sweep_fig7, "fig8": bench_sweep_fig8, "fig9": bench_sweep_fig9,
@@ -842,6 +881,18 @@ def main():
         del main_leg
         torch.cuda.empty_cache()
         line["served"] = bench_serve(args)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        plain = bench_serve(args, plain=True)
+        line["served_plain"] = plain
+        b = line["served"]
+        if b["merged_tuples_s"] and plain["merged_tuples_s"] and b["p50_ms"] and plain["p50_ms"]:
+            line["served_vs_plain"] = {
+                "tuples_s_ratio": b["merged_tuples_s"] / plain["merged_tuples_s"],
+                "p50_ratio": plain["p50_ms"] / b["p50_ms"],
+                "p99_ratio": plain["p99_ms"] / b["p99_ms"],
+                "device_p50_ratio": (plain["device_p50_ms"] / b["device_p50_ms"]
+                                     if b["device_p50_ms"] and plain["device_p50_ms"] else None)}
     print(json.dumps(line), flush=True)
     if not all(v is not False for v in parity.values()):
         log(f"PARITY FAILURE: {parity}")

@@ -33,6 +33,7 @@ a GPU.
 from __future__ import annotations
 
 import collections
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -50,10 +51,17 @@ class MergeRequest:
     status: str = "queued"      # queued | running | committed | cancelled | rejected
     job: object = None
     snapshot: object = None     # the frozen delta (executor object)
+    completed: float | None = None  # when the merge's last kernel ended (device clock, if known)
 
     @property
     def latency(self):
         return None if self.committed is None else self.committed - self.arrival
+
+    @property
+    def device_latency(self):
+        """Arrival to the merge's results in HBM, on the device's clock (the
+        commit itself waits for the host's next poll)."""
+        return None if self.completed is None else self.completed - self.arrival
 
 
 @dataclass
@@ -90,6 +98,9 @@ class Server:
         self.reserve = 0            # headroom kept for merges: largest merge need seen
         self.waiting_for_memory = False
         self.t0 = self.clock()
+        # appends may come from another host thread than the one that polls:
+        # every public call holds this lock
+        self.lock = threading.RLock()
 
     # ---- tables and appends -------------------------------------------------
 
@@ -114,6 +125,10 @@ class Server:
         so a request can always be admitted once nothing else runs; appends
         cannot starve the merges that would free their memory.  While a
         request waits for memory no delta grows at all."""
+        with self.lock:
+            return self._append(tid, rows)
+
+    def _append(self, tid: int, rows) -> bool:
         t = self.tables[tid]
         n = self.ex.batch_rows(rows)
         grow, new_cap = self.ex.grow_plan(t.active, n)
@@ -150,17 +165,19 @@ class Server:
     # ---- requests -----------------------------------------------------------
 
     def submit_merge(self, tid: int) -> MergeRequest:
-        r = MergeRequest(tid, self.clock())
-        self.queue.append(r)
-        return r
+        with self.lock:
+            r = MergeRequest(tid, self.clock())
+            self.queue.append(r)
+            return r
 
     def cancel(self, r: MergeRequest) -> bool:
         """Cancel a request that has not been admitted (nothing changes)."""
-        if r.status == "queued" and r in self.queue:
-            self.queue.remove(r)
-            r.status = "cancelled"
-            return True
-        return False
+        with self.lock:
+            if r.status == "queued" and r in self.queue:
+                self.queue.remove(r)
+                r.status = "cancelled"
+                return True
+            return False
 
     def resident_bytes(self) -> int:
         # while a table merges, its second buffer is the merge's snapshot
@@ -182,6 +199,10 @@ class Server:
     def poll(self) -> int:
         """Commit finished merges, then admit what fits.  Returns the number
         of commits."""
+        with self.lock:
+            return self._poll()
+
+    def _poll(self) -> int:
         commits = 0
         still = []
         for r in self.running:
@@ -236,6 +257,8 @@ class Server:
 
     def _commit(self, r: MergeRequest):
         t = self.tables[r.table]
+        done = getattr(self.ex, "completion_time", None)
+        r.completed = done(r.job) if done is not None else None
         new_main = self.ex.result(r.job)
         old = t.main
         t.main = new_main                       # atomic swap of the table's main
@@ -267,6 +290,10 @@ class Server:
     # ---- statistics ------------------------------------------------------------
 
     def stats(self) -> dict:
+        with self.lock:
+            return self._stats()
+
+    def _stats(self) -> dict:
         lat = np.array([r.latency for r in self.done], dtype=np.float64)
         wall = self.clock() - self.t0
         rows = sum(r.rows for r in self.done)
@@ -320,11 +347,16 @@ class GpuExecutor:
     previous launch's copy on another stream); commit reads the result scalars
     once per merge."""
 
-    def __init__(self, n_streams: int = 4, device: int = 0):
+    def __init__(self, n_streams: int = 4, device: int = 0, plain: bool = False):
         import torch
         import paper_1109_6885_amd as cm
         self.torch, self.cm = torch, cm
         self.device = device
+        # plain: each merge is one mc_merge_column call per column, in order
+        # on the merge's stream with one workspace sized for its largest
+        # column (the comparison of the batched form with the plain one)
+        self.plain = plain
+        self.t0_event = None  # device-clock origin for completion times
         self.append_stream = torch.cuda.Stream(device=device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self.ctxs = [cm.Context(device) for _ in range(n_streams)]
@@ -430,6 +462,7 @@ class GpuExecutor:
         cm = self.cm
         ins = []
         total = 0
+        plain_scratch = 0
         for c in m.cols:
             d = cm.McColumnIn()
             d.type = cm.TYPE_CODES[c.vtype]
@@ -441,9 +474,12 @@ class GpuExecutor:
             d.delta_values = 256 if rows else None
             d.delta_rows = rows
             ins.append(d)
-            dc, words, _ = cm.bounds_of(d)
+            dc, words, sb = cm.bounds_of(d)
             total += dc * cm.VALUE_LEN[c.vtype] + max(words, 2) * 8 + cm.RESULT_BYTES
-        total += cm.batched_bounds_of(ins, self.ctx)
+            plain_scratch = max(plain_scratch, sb)
+        # the workspace each route really needs: one column at a time (plain)
+        # or every column at once (batched)
+        total += plain_scratch if self.plain else cm.batched_bounds_of(ins, self.ctx)
         if len(cache) > 64:
             cache.clear()
         cache[key] = total
@@ -481,10 +517,15 @@ class GpuExecutor:
                     torch.empty(max(words, 2), dtype=torch.int64, device=f"cuda:{self.device}"),
                     None, None, res[j * cm.RESULT_BYTES:(j + 1) * cm.RESULT_BYTES],
                     col.n_main + int(col.delta.shape[0])))
-            scratch = cm.alloc_scratch(cm.batched_bounds_of(descs, self.ctx))
-            cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s,
-                                     ctx=self.ctxs[si], descs=descs)
-            done = torch.cuda.Event()
+            if self.plain:
+                scratch = cm.alloc_scratch(max(cm.bounds_of(dd)[2] for dd in descs))
+                for col, out in zip(cols, outs):
+                    cm.merge_column(col, out=out, scratch=scratch, stream=s, ctx=self.ctxs[si])
+            else:
+                scratch = cm.alloc_scratch(cm.batched_bounds_of(descs, self.ctx))
+                cm.merge_columns_batched(cols, outs=outs, scratch=scratch, stream=s,
+                                         ctx=self.ctxs[si], descs=descs)
+            done = torch.cuda.Event(enable_timing=self.t0_event is not None)
             done.record(s)
             self.last_done[si] = done
         return {"cols": cols, "outs": outs, "res": res, "scratch": scratch, "done": done,
@@ -492,6 +533,22 @@ class GpuExecutor:
 
     def finished(self, job) -> bool:
         return job["done"].query()
+
+    def start_clock(self, host_now: float):
+        """Record the device-clock origin (after a synchronize) matching the
+        host clock reading host_now: completion times are then host-clock
+        seconds of the merges' last kernels."""
+        torch = self.torch
+        torch.cuda.synchronize(self.device)
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0_event.record(torch.cuda.current_stream(self.device))
+        self.t0_event.synchronize()
+        self.t0_host = host_now
+
+    def completion_time(self, job):
+        if self.t0_event is None:
+            return None
+        return self.t0_host + self.t0_event.elapsed_time(job["done"]) / 1e3
 
     def result(self, job) -> GpuMain:
         cm = self.cm

@@ -359,3 +359,56 @@ def test_merge_trigger_fraction_of_main():
                for b in batches for v in b["cols"][j]]
         assert decode(c) == expected[j] + add
     assert s.stats()["auto_requests"] == 2
+
+
+def test_appends_from_another_thread():
+    """Appends from a host thread of their own while the merge loop polls
+    (the served benchmark's arrangement): every public call holds the
+    server's lock, so the two threads never see a table half-updated; every
+    row that was accepted is in the final tables, in order, and the budget
+    holds throughout."""
+    import threading
+    import time
+
+    rng = np.random.default_rng(23)
+    ex = CpuExecutor(polls_to_finish=3)
+    s = Server(ex, budget_bytes=10 ** 12, max_inflight=3)
+    tables = {t: make_table(rng, 2, 40) for t in range(3)}
+    expected = {t: [decode(c) for c in m.cols] for t, m in tables.items()}
+    for t, m in tables.items():
+        s.add_table(t, m, delta_capacity=500)
+    batches = {t: [batch(rng, tables[t], 5) for _ in range(40)] for t in tables}
+    accepted = {t: [] for t in tables}
+    errors = []
+
+    def appender():
+        try:
+            for k in range(40):
+                for t in tables:
+                    if s.append(t, batches[t][k]):
+                        accepted[t].append(batches[t][k])
+                time.sleep(0.0005)
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    th = threading.Thread(target=appender)
+    th.start()
+    reqs = []
+    while th.is_alive():
+        reqs.append(s.submit_merge(int(rng.integers(0, 3))))
+        s.poll()
+        with s.lock:
+            assert s.in_use() <= s.budget
+        time.sleep(0.0003)
+    th.join()
+    assert not errors, errors
+    for t in tables:
+        reqs.append(s.submit_merge(t))
+    s.drain()
+    assert all(r.status == "committed" for r in reqs)
+    for t, m in tables.items():
+        for j, c in enumerate(s.tables[t].main.cols):
+            vt = c["vtype"]
+            add = [(bytes(np.asarray(v, np.uint8)) if vt == "str16" else int(v))
+                   for b in accepted[t] for v in b["cols"][j]]
+            assert decode(c) == expected[t][j] + add
