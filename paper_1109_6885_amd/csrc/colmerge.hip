@@ -144,16 +144,18 @@ struct Carver {
 struct ColLayout {
     // part Z
     uint64_t counters = 0, sflags = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0,
-             emit_status = 0, emit_status2 = 0,
+             pgsum = 0, egsum = 0, emit_status = 0, emit_status2 = 0,
              merge_status = 0, mbound = 0, dcount = 0, htab = 0, z_size = 0;
     // part B
-    uint64_t base = 0, tcount = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
+    uint64_t base = 0, tcount = 0, ecnt = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
              drank = 0, x_d = 0, x_m = 0, xdev = 0, xsp = 0, rep = 0, dindex = 0, dkeys = 0,
              drankd = 0, b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
     uint32_t repack_codes = mc::kRepackCodes, prefix_run = 0;  // launch shapes
     bool partitioned = false;  // merge tile boundaries come from merge_partition
+    bool two_launch_pass = false;  // prefix passes in two launches each (no waits)
+    bool single = false;           // a single-column call (emit in two launches)
     bool hashed = false;       // Step 1(a) deduplicates by hashing first
     bool indexed = false;      // ... with the hashing done by a delta index (mc_delta_index)
     uint64_t hmask = 0;
@@ -216,6 +218,13 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.xflag = z.take(8);
     L.gh = z.take((uint64_t)mc::kGhCopies * L.passes * 256 * 4);
     L.trivial = z.take(16 * 4);
+    // single-column calls: the emit in two launches, and so the prefix passes
+    // when there are at most kP2MaxTiles sort tiles
+    L.single = !batched;
+    L.two_launch_pass = L.single && nd > 0 && L.sort_tiles <= mc::kP2MaxTiles;
+    if (L.two_launch_pass)
+        L.pgsum = z.take((uint64_t)mc::kPrefixSlots * ceil_div(L.sort_tiles, mc::kP2Group) * 256 * 4);
+    if (L.single) L.egsum = z.take(ceil_div(L.emit_tiles, mc::kEmitGroup) * 4);
     L.emit_status = z.take((uint64_t)L.emit_tiles * 8);
     L.emit_status2 = z.take((uint64_t)L.emit_tiles * 8);
     L.merge_status = z.take(L.merge_tiles * 8);
@@ -229,6 +238,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     Carver b;
     L.base = b.take((uint64_t)L.passes * 256 * 4);
     L.tcount = b.take((uint64_t)256 * L.sort_tiles * 4);
+    if (L.single) L.ecnt = b.take((uint64_t)L.emit_tiles * 4);
     L.keys0 = b.take(nd * E);
     L.keys1 = b.take(nd * E);
     L.vals0 = b.take(nd * 4);
@@ -305,6 +315,11 @@ mc::ColDesc make_desc(const mc_column_in *in, const mc_column_out *out, char *za
     C.base = reinterpret_cast<uint32_t *>(zb + L.base);
     C.trivial = reinterpret_cast<uint32_t *>(za + L.trivial);
     C.tcount = reinterpret_cast<uint32_t *>(zb + L.tcount);
+    C.pgsum = L.two_launch_pass ? reinterpret_cast<uint32_t *>(za + L.pgsum) : nullptr;
+    if (L.single) {
+        C.egsum = reinterpret_cast<uint32_t *>(za + L.egsum);
+        C.ecnt = reinterpret_cast<uint32_t *>(zb + L.ecnt);
+    }
     C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
     C.sflags = reinterpret_cast<uint32_t *>(za + L.sflags);
     C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);
@@ -477,10 +492,16 @@ __global__ __launch_bounds__(256) void k1_sort_down(mc::ColDesc C, int kind, int
 // the same kernel of other merges; they stride over the tiles (or digits) of
 // each phase, with a grid-wide barrier between phases.  Every pass reads
 // what the previous pass wrote, exactly as the per-phase launches do.
+//
+// The second emit follows in the same launch, after one more barrier: the
+// workgroups take emit tiles by ticket until none is left (a tile's
+// look-back waits only for lower tickets, held by running workgroups), or,
+// on the hashing route, stride over the tiles of the distinct values.
 template <class T>
 __global__ __launch_bounds__(256) void k1_full_sort(mc::ColDesc C) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
-    __shared__ uint32_t s_ok;
+    __shared__ __attribute__((aligned(16)))
+    char smem[std::max(sizeof(mc::DownSmem<T>), sizeof(mc::EmitSmem<T>))];
+    __shared__ uint32_t s_ok, s_tile;
     if (C.sflags[mc::kSfUnsorted] == 0) return;
     const uint32_t G = gridDim.x;
     const bool small = C.sort_tiles <= mc::kSmallScanTiles;
@@ -508,25 +529,54 @@ __global__ __launch_bounds__(256) void k1_full_sort(mc::ColDesc C) {
             mc::sort_down_tile<T>(C, io, t, smem);
             __syncthreads();
         }
-        if (p + 1 < T::kBytes) {
-            target += G;
-            if (!mc::grid_barrier(bar, target, C.err, &s_ok)) return;
+        target += G;
+        if (!mc::grid_barrier(bar, target, C.err, &s_ok)) return;
+    }
+    const uint32_t emit_tiles = (C.nd + mc::kEmitTile - 1) / mc::kEmitTile;
+    if (C.sort_n) {  // the hashing route: every sorted position is a distinct value
+        for (uint32_t t = blockIdx.x; t < emit_tiles; t += G) {
+            mc::emit_distinct_tile<T>(C, t, true);
+            __syncthreads();
         }
+        return;
+    }
+    while (true) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&C.sflags[mc::kSfEmitTicket2], 1u);
+        __syncthreads();
+        const uint32_t t = s_tile;
+        __syncthreads();  // everyone has the ticket before thread 0 takes the next
+        if (t >= emit_tiles) break;
+        mc::emit_tile_at<T>(C, smem, true, t);
+        __syncthreads();
     }
 }
-// round 0: every tile sorted in LDS; round 1: the runs crossing tile seams
+// One prefix pass (slot) in two launches.
 template <class T>
-__global__ __launch_bounds__(256) void k1_window(mc::ColDesc C, int round) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
-    if (round == 0)
-        mc::window_sort_tile<T>(C, blockIdx.x, smem);
-    else
-        mc::window_seam_tile<T>(C, blockIdx.x, smem);
+__global__ __launch_bounds__(256) void k1_sort_up2(mc::ColDesc C, int slot) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
+    mc::sort_up2_tile<T>(C, mc::prefix_io(C, slot), slot, blockIdx.x, smem);
 }
 template <class T>
-__global__ __launch_bounds__(256) void k1_emit(mc::ColDesc C, int again) {
+__global__ __launch_bounds__(256) void k1_sort_down2(mc::ColDesc C, int slot) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::DownSmem<T>)];
+    mc::sort_down2_tile<T>(C, mc::prefix_io(C, slot), slot, blockIdx.x, smem);
+}
+// The emit after the prefix sort in two launches: the windows and the run
+// heads' counts, then the numbering.
+template <class T>
+__global__ __launch_bounds__(256) void k1_emit_count(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitWinSmem<T>)];
+    mc::emit_count_tile<T>(C, blockIdx.x, smem);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_emit_write(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<T>)];
-    mc::emit_tile<T>(C, smem, again != 0);
+    mc::emit_tile_at<T, true>(C, smem, false, blockIdx.x);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k1_emit_distinct_win(mc::ColDesc C) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitWinSmem<T>)];
+    mc::emit_distinct_window_tile<T>(C, blockIdx.x, smem);
 }
 template <class T>
 __global__ __launch_bounds__(256) void k1_hash_insert(mc::ColDesc C) {
@@ -537,10 +587,6 @@ template <class T>
 __global__ __launch_bounds__(256) void k1_compact(mc::ColDesc C) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::CompactSmem)];
     mc::compact_tile<T>(C, blockIdx.x, smem);
-}
-template <class T>
-__global__ __launch_bounds__(256) void k1_emit_distinct(mc::ColDesc C, int again) {
-    mc::emit_distinct_tile<T>(C, blockIdx.x, again != 0);
 }
 __global__ __launch_bounds__(256) void k1_rank_rows(mc::ColDesc C) {
     mc::rank_rows_tile(C, blockIdx.x);
@@ -819,33 +865,37 @@ int launch_delta_dictionary(const mc::ColDesc &C, const ColLayout &L, uint32_t c
     MC_LAUNCHED("k1_hist");
     hipLaunchKernelGGL(k1_hist_scan<T>, dim3(1), dim3(mc::kBlock), 0, s, C);
     MC_LAUNCHED("k1_hist_scan");
-    // prefix sort: up to three passes, then windows sorted in LDS
-    rc = launch_passes<T>(C, L, kPassPrefix, mc::kPrefixSlots, s);
-    if (rc) return rc;
-    for (int round = 0; round < 2; round++) {
-        hipLaunchKernelGGL(k1_window<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, round);
-        MC_LAUNCHED("k1_window");
+    // prefix sort: up to three passes (two launches each, or three), then the
+    // windows sorted in LDS, folded into the emit (which checks the order)
+    if (L.two_launch_pass) {
+        for (int slot = 0; slot < mc::kPrefixSlots; slot++) {
+            hipLaunchKernelGGL(k1_sort_up2<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, slot);
+            MC_LAUNCHED("k1_sort_up2");
+            hipLaunchKernelGGL(k1_sort_down2<T>, dim3(L.sort_tiles), dim3(mc::kBlock), 0, s, C, slot);
+            MC_LAUNCHED("k1_sort_down2");
+        }
+    } else {
+        rc = launch_passes<T>(C, L, kPassPrefix, mc::kPrefixSlots, s);
+        if (rc) return rc;
     }
     if (after_sort) MC_HIP(hipEventRecord(after_sort, s));
-    // emit (checks the order), then the full sort and a second emit, which
-    // return at once unless the check failed
-    for (int again = 0; again < 2; again++) {
-        if (again && L.sort_tiles) {
-            // at most half the CUs: a CU holds at least 3 of its workgroups
-            // (VGPRs), so the launches of up to 6 concurrent merges on other
-            // streams are resident together
-            const uint32_t grid = std::min<uint32_t>(L.sort_tiles, cus > 1 ? cus / 2 : 1u);
-            hipLaunchKernelGGL(k1_full_sort<T>, dim3(grid), dim3(mc::kBlock), 0, s, C);
-            MC_LAUNCHED("k1_full_sort");
-        }
-        if (L.hashed) {
-            hipLaunchKernelGGL(k1_emit_distinct<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C,
-                               again);
-            MC_LAUNCHED("k1_emit_distinct");
-        } else {
-            hipLaunchKernelGGL(k1_emit<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C, again);
-            MC_LAUNCHED("k1_emit");
-        }
+    if (L.hashed) {
+        hipLaunchKernelGGL(k1_emit_distinct_win<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_emit_distinct_win");
+    } else {
+        hipLaunchKernelGGL(k1_emit_count<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_emit_count");
+        hipLaunchKernelGGL(k1_emit_write<T>, dim3(L.emit_tiles), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_emit_write");
+    }
+    // the full sort and the second emit in one launch, which returns at once
+    // unless the order check failed.  At most half the CUs: a CU holds at
+    // least 3 of its workgroups (VGPRs), so the launches of up to 6
+    // concurrent merges on other streams are resident together.
+    {
+        const uint32_t grid = std::min<uint32_t>(L.sort_tiles, cus > 1 ? cus / 2 : 1u);
+        hipLaunchKernelGGL(k1_full_sort<T>, dim3(grid), dim3(mc::kBlock), 0, s, C);
+        MC_LAUNCHED("k1_full_sort");
     }
     if (L.hashed) {
         hipLaunchKernelGGL(k1_rank_rows, dim3(L.hash_tiles), dim3(mc::kBlock), 0, s, C);
@@ -1968,6 +2018,11 @@ int mc_delta_dictionary(mc_ctx *ctx, int32_t type, const void *delta_values, uin
     C.base = reinterpret_cast<uint32_t *>(zb + L.base);
     C.trivial = reinterpret_cast<uint32_t *>(za + L.trivial);
     C.tcount = reinterpret_cast<uint32_t *>(zb + L.tcount);
+    C.pgsum = L.two_launch_pass ? reinterpret_cast<uint32_t *>(za + L.pgsum) : nullptr;
+    if (L.single) {
+        C.egsum = reinterpret_cast<uint32_t *>(za + L.egsum);
+        C.ecnt = reinterpret_cast<uint32_t *>(zb + L.ecnt);
+    }
     C.counters = reinterpret_cast<uint32_t *>(za + L.counters);
     C.sflags = reinterpret_cast<uint32_t *>(za + L.sflags);
     C.emit_status = reinterpret_cast<uint64_t *>(za + L.emit_status);

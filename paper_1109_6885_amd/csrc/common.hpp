@@ -43,6 +43,7 @@ struct TU32 {
     __device__ static void store(void *p, uint64_t i, K k) { static_cast<K *>(p)[i] = k; }
     // radix digit `d` (0 = least significant byte of the order)
     __device__ static uint32_t digit(K k, int d) { return (k >> (8 * d)) & 0xffu; }
+    __device__ static uint32_t ndigit(N k, int d) { return (k >> (8 * d)) & 0xffu; }  // of norm(k)
     __device__ static N norm(K k) { return k; }
     __device__ static K denorm(N n) { return n; }
     __device__ static bool lt(N a, N b) { return a < b; }
@@ -58,6 +59,7 @@ struct TU64 {
     __device__ static K load(const void *p, uint64_t i) { return static_cast<const K *>(p)[i]; }
     __device__ static void store(void *p, uint64_t i, K k) { static_cast<K *>(p)[i] = k; }
     __device__ static uint32_t digit(K k, int d) { return (uint32_t)(k >> (8 * d)) & 0xffu; }
+    __device__ static uint32_t ndigit(N k, int d) { return (uint32_t)(k >> (8 * d)) & 0xffu; }
     __device__ static N norm(K k) { return k; }
     __device__ static K denorm(N n) { return n; }
     __device__ static bool lt(N a, N b) { return a < b; }
@@ -77,6 +79,10 @@ struct TS16 {
         int byte = 15 - d;
         uint64_t w = byte >= 8 ? k.b : k.a;
         return (uint32_t)(w >> (8 * (byte & 7))) & 0xffu;
+    }
+    // digit d of norm(k): byte d of the 128-bit number (lo: bytes 0-7)
+    __device__ static uint32_t ndigit(const N &n, int d) {
+        return (uint32_t)((d >= 8 ? n.hi >> (8 * (d - 8)) : n.lo >> (8 * d)) & 0xffu);
     }
     __device__ static N norm(K k) {
         N n;
@@ -203,6 +209,11 @@ struct ColDesc {
     uint32_t *base;            // [passes][256] digit offsets
     uint32_t *trivial;         // [passes] single-digit flags (zeroed)
     uint32_t *tcount;          // [256][sort_tiles] tile counts / offsets
+    uint32_t *pgsum;           // [slot][tile group][256] digit counts of the tile groups of
+                               // the two-launch prefix passes (zeroed), or null: three
+                               // launches per pass
+    uint32_t *ecnt;            // run heads of every emit tile (two-launch emit)
+    uint32_t *egsum;           // run heads of every group of emit tiles (zeroed)
     uint32_t *counters;        // [1] merge tile counter (zeroed)
     uint32_t *sflags;          // Step 1(a) words, slots kSf* below (zeroed)
     uint64_t *emit_status;     // emit prefix words (zeroed)
@@ -233,11 +244,12 @@ struct ColDesc {
 };
 
 // Decoupled look-back over the tiles' status words.  One wave looks back:
-// each round its 64 lanes read the statuses of the 64 nearest unvisited
-// predecessors at once, waits only for the lanes up to the nearest one that
-// holds an inclusive prefix (the others are not needed), and sums the
-// aggregates up to that one; a tile far from the last published inclusive
-// prefix needs (distance / 64) rounds.  (All 256 threads polling, each
+// each round its 64 lanes read the statuses of the 256 nearest unvisited
+// predecessors at once (four per lane), then, 64 at a time and nearest
+// first, wait only for the lanes up to the nearest one that holds an
+// inclusive prefix (the others are not needed) and sum the aggregates up to
+// that one; a tile far from the last published inclusive prefix needs
+// (distance / 256) memory round trips.  (All 256 threads polling, each
 // waiting for its own predecessor, put four times the agent-scope loads on
 // the same few status lines.)  Every thread of the block must call it; every
 // thread gets the exclusive prefix (the sum of the aggregates of tiles
@@ -252,32 +264,46 @@ __device__ inline uint64_t lookback_resolve(uint64_t *status, uint32_t tile, uin
                                             uint32_t *err, uint64_t *s_prefix) {
     if (tile == 0) return 0;
     if (wave_id() == 0) {
+        // each round reads kLbGroups groups of 64 predecessors at once (one
+        // memory round trip for 256 tiles), then consumes them nearest first
+        constexpr int kLbGroups = 4;
         const int lane = lane_id();
         uint64_t prefix = 0;
         int64_t base = (int64_t)tile - 1;
         uint32_t spins = 0;
-        while (true) {
-            const int64_t t = base - lane;  // lane 0: nearest predecessor
-            uint64_t s = t >= 0 ? ld_relaxed(&status[t]) : kFlagPre;  // before tile 0: zero prefix
-            while (true) {
-                const uint64_t pre = __ballot((s & kFlagPre) != 0);
-                // lanes up to and including the nearest inclusive prefix
-                const uint64_t need = pre ? ((pre & (~pre + 1)) << 1) - 1 : ~0ull;
-                const uint64_t wait = __ballot((s >> 62) == 0) & need;
-                if (!wait) break;
-                if (++spins > kSpinLimit) {  // give up: unpublished statuses count as zero
-                    if (lane == 0) flag_error(err, MC_DEVERR_SPIN);
-                    if ((s >> 62) == 0) s = kFlagPre;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                if ((wait >> lane) & 1ull) s = ld_relaxed(&status[t]);
+        bool done = false;
+        while (!done) {
+            uint64_t sg[kLbGroups];
+#pragma unroll
+            for (int g = 0; g < kLbGroups; g++) {
+                const int64_t t = base - 64 * g - lane;  // lane 0: nearest predecessor of the group
+                sg[g] = t >= 0 ? ld_relaxed(&status[t]) : kFlagPre;  // before tile 0: zero prefix
             }
-            const uint64_t pre = __ballot((s & kFlagPre) != 0);
-            const int stop = pre ? __ffsll((long long)pre) - 1 : 64;
-            prefix += wave_sum(lane <= stop ? (s & kValMask) : 0ull);
-            if (stop < 64) break;
-            base -= 64;
+#pragma unroll
+            for (int g = 0; g < kLbGroups; g++) {
+                if (done) break;
+                const int64_t t = base - 64 * g - lane;
+                uint64_t s = sg[g];
+                while (true) {
+                    const uint64_t pre = __ballot((s & kFlagPre) != 0);
+                    // lanes up to and including the nearest inclusive prefix
+                    const uint64_t need = pre ? ((pre & (~pre + 1)) << 1) - 1 : ~0ull;
+                    const uint64_t wait = __ballot((s >> 62) == 0) & need;
+                    if (!wait) break;
+                    if (++spins > kSpinLimit) {  // give up: unpublished statuses count as zero
+                        if (lane == 0) flag_error(err, MC_DEVERR_SPIN);
+                        if ((s >> 62) == 0) s = kFlagPre;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((wait >> lane) & 1ull) s = ld_relaxed(&status[t]);
+                }
+                const uint64_t pre = __ballot((s & kFlagPre) != 0);
+                const int stop = pre ? __ffsll((long long)pre) - 1 : 64;
+                prefix += wave_sum(lane <= stop ? (s & kValMask) : 0ull);
+                if (stop < 64) done = true;
+            }
+            base -= 64 * kLbGroups;
         }
         if (lane == 0) {
             st_relaxed(&status[tile], kFlagPre | (prefix + agg));

@@ -268,6 +268,37 @@ __device__ __forceinline__ void emit_distinct_tile(const ColDesc &C, uint64_t t,
     if (t == 0 && threadIdx.x == 0) *C.n_ud = n;
 }
 
+// emit_distinct_tile with the windows folded in (window_view): the
+// view of tile t is ordered inside its runs of equal prefix in LDS.
+template <class T>
+__device__ __forceinline__ void emit_distinct_window_tile(const ColDesc &C, uint64_t t, char *smem) {
+    typedef typename T::N N;
+    EmitWinSmem<T> &S = *reinterpret_cast<EmitWinSmem<T> *>(smem);
+    const uint64_t n = sort_n(C);
+    const uint64_t tb = t * kEmitTile;
+    if (tb >= n) return;  // the launch is sized for every delta row; fewer values are distinct
+    const uint64_t vb = tb ? tb - 1 : 0, ve = min<uint64_t>(n, tb + kEmitTile);
+    window_view<T>(C, n, vb, ve, S);
+    const uint32_t off = tb ? 1u : 0u;  // view index of position tb
+    bool bad = false, unsorted = false;
+    for (uint32_t r = threadIdx.x; r < (uint32_t)(ve - tb); r += kBlock) {
+        const uint64_t i = tb + r;
+        const uint32_t v = off + r;
+        const N k = S.keys[S.perm[v]];
+        // distinct values: strictly increasing
+        if (i > 0 && !T::lt(S.keys[S.perm[v - 1]], k)) unsorted = true;
+        T::store(C.u_d, i, T::denorm(k));
+        const uint32_t d = S.vals[S.perm[v]];
+        if (d < n)
+            C.drankd[d] = (uint32_t)i;
+        else
+            bad = true;
+    }
+    if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+    if (unsorted) C.sflags[kSfUnsorted] = 1u;
+    if (t == 0 && threadIdx.x == 0) *C.n_ud = n;
+}
+
 __device__ __forceinline__ void rank_rows_tile(const ColDesc &C, uint64_t t) {
     const uint64_t n = sort_n(C);
     bool bad = false;

@@ -455,6 +455,133 @@ __device__ __forceinline__ void sort_down_tile(const ColDesc &C, const PassIO &i
     if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
 }
 
+// ---- one pass in two launches ------------------------------------------------
+// For a single column of at most kP2MaxTiles tiles, a prefix pass runs as
+// two launches and no workgroup waits for another: sort_up2_tile writes its
+// tile's digit counts (tile-major) and adds them into its group's sums
+// (kP2Group consecutive tiles); sort_down2_tile finds every digit's first
+// output position from the digit's global offset, the sums of the groups
+// before its tile's group and the counts of the group's earlier tiles, then
+// ranks and scatters as sort_down_tile.  (The three-launch form scans the
+// counts in a launch of its own; the one-launch form chained the tiles by a
+// look-back, whose cross-workgroup round trips measured slower than the
+// extra launch.)
+constexpr uint32_t kP2Group = 32;
+constexpr uint32_t kP2MaxTiles = 4096;
+
+__device__ __forceinline__ uint32_t *p2_gsum(const ColDesc &C, int slot) {
+    return C.pgsum + (uint64_t)slot * ((C.sort_tiles + kP2Group - 1) / kP2Group) * 256;
+}
+
+template <class T>
+__device__ __forceinline__ void sort_up2_tile(const ColDesc &C, const PassIO &io, int slot, uint32_t t,
+                                              char *smem) {
+    const int p = io.p;
+    if (p < 0) return;
+    constexpr int TILE = sort_tile<T>();
+    const uint64_t n = sort_n(C);
+    if ((uint64_t)t * TILE >= n) return;  // past the values: never read
+    uint32_t *h = reinterpret_cast<uint32_t *>(smem);
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t b0 = (uint64_t)t * TILE;
+    uint32_t dg[SortCfg<T>::kItems];
+#pragma unroll
+    for (int j = 0; j < SortCfg<T>::kItems; j++) {
+        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
+        dg[j] = i < n ? T::digit(T::load(io.src, i), p) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < SortCfg<T>::kItems; j++) {
+        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[dg[j]], 1u);
+    }
+    __syncthreads();
+    const uint32_t c = h[threadIdx.x];
+    C.tcount[(uint64_t)t * 256 + threadIdx.x] = c;
+    if (c) atomicAdd(&p2_gsum(C, slot)[(t / kP2Group) * 256 + threadIdx.x], c);
+}
+
+template <class T>
+__device__ __forceinline__ void sort_down2_tile(const ColDesc &C, const PassIO &io, int slot, uint32_t t,
+                                                char *smem) {
+    typedef typename T::K K;
+    constexpr int ITEMS = SortCfg<T>::kItems;
+    constexpr int TILE = sort_tile<T>();
+    constexpr int WCHUNK = 64 * ITEMS;
+    DownSmem<T> &S = *reinterpret_cast<DownSmem<T> *>(smem);
+    const int p = io.p;
+    if (p < 0) {  // no digit varies (copy) or an unused slot
+        sort_down_tile<T>(C, io, t, smem);
+        return;
+    }
+    const uint64_t b0 = (uint64_t)t * TILE;
+    const uint64_t n = sort_n(C);
+    if (b0 >= n) return;
+    const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - b0);
+    const int lane = lane_id(), wv = wave_id();
+    K key[ITEMS];
+    uint32_t val[ITEMS], dig[ITEMS], slotv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t li = wv * WCHUNK + j * 64 + lane;
+        dig[j] = 0;
+        if (li < tn) {
+            key[j] = T::load(io.src, b0 + li);
+            val[j] = io.vsrc ? io.vsrc[b0 + li] : (uint32_t)(b0 + li);
+            dig[j] = T::digit(key[j], p);
+        }
+    }
+    {
+        // digit d's first position: its global offset, the groups before
+        // this tile's group, the group's tiles before this one
+        // (eight loads in flight per round: a plain loop would wait for each)
+        const uint32_t d = threadIdx.x;
+        const uint32_t g = t / kP2Group;
+        const uint32_t *gs = p2_gsum(C, slot) + d;
+        const uint32_t *tc = C.tcount + (uint64_t)g * kP2Group * 256 + d;
+        const uint32_t nt = t - g * kP2Group;  // the group's tiles before t
+        uint32_t pos = C.base[p * 256 + d];
+        for (uint32_t x0 = 0; x0 < g; x0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) v[k] = x0 + k < g ? gs[(x0 + k) * 256] : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) pos += v[k];
+        }
+        for (uint32_t x0 = 0; x0 < nt; x0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) v[k] = x0 + k < nt ? tc[(x0 + k) * 256] : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) pos += v[k];
+        }
+        S.gpos[d] = pos;
+    }
+    rank_digits<ITEMS>(dig, tn, S.wcnt, S.dex, S.tmp, slotv);
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        if ((uint32_t)(wv * WCHUNK + j * 64 + lane) < tn) {
+            S.keys[slotv[j]] = key[j];
+            S.vals[slotv[j]] = val[j];
+        }
+    }
+    __syncthreads();
+    bool bad = false;
+    for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
+        const K k = S.keys[i];
+        const uint32_t d = T::digit(k, p);
+        const uint64_t pos = (uint64_t)S.gpos[d] + (i - S.dex[d]);
+        if (pos < n) {
+            T::store(io.kdst, pos, k);
+            io.vdst[pos] = S.vals[i];
+        } else {
+            bad = true;
+        }
+    }
+    if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+}
+
 // ---- windows sorted in LDS after the prefix passes --------------------------
 // window_sort_tile sorts [t*TILE, (t+1)*TILE) in place in keys1 / vals1.  The
 // tile is already ordered by prefix, so only runs of equal prefix need
@@ -659,17 +786,49 @@ struct EmitSmem {
 // again = false: the emit after the prefix sort, which also checks the
 // order; again = true: the emit after the full LSD sort, only when that check
 // failed (its own tile counter and prefix words).
+template <class T, bool DIRECT = false>
+__device__ __forceinline__ void emit_tile_at(const ColDesc &C, char *smem, bool again, uint32_t t);
+
 template <class T>
 __device__ __forceinline__ void emit_tile(const ColDesc &C, char *smem, bool again) {
-    typedef typename T::K K;
     EmitSmem<T> &S = *reinterpret_cast<EmitSmem<T> *>(smem);
     if (again && C.sflags[kSfUnsorted] == 0) return;
-    const void *keys = C.keys1;  // sorted values (both sorts end in keys1 / vals1)
-    const uint32_t *rows = C.vals1;
-    uint64_t *status = again ? C.emit_status2 : C.emit_status;
     if (threadIdx.x == 0) S.tile = atomicAdd(&C.sflags[again ? kSfEmitTicket2 : kSfEmitTicket], 1u);
     __syncthreads();
-    const uint32_t t = S.tile;
+    emit_tile_at<T>(C, smem, again, S.tile);
+}
+
+// Emit groups: emit_count_tile adds every tile's count of run heads into
+// the sum of its group of kEmitGroup tiles.
+constexpr uint32_t kEmitGroup = 64;
+
+// Exclusive prefix of tile t over the per-tile counts cnt, from the sums of
+// the groups before t's group (gsum) and the counts of the group's earlier
+// tiles, all written by an earlier launch.  Wave 0 computes it into *out.
+__device__ __forceinline__ void group_prefix(const uint32_t *cnt, const uint32_t *gsum, uint32_t t,
+                                             uint32_t group, uint64_t *out) {
+    if (wave_id() != 0) return;
+    const uint32_t lane = lane_id(), g = t / group;
+    uint64_t v = 0;
+    for (uint32_t x = lane; x < g; x += 64) v += gsum[x];
+    for (uint32_t j = g * group + lane; j < t; j += 64) v += cnt[j];
+    v = wave_sum(v);
+    if (lane == 0) *out = v;
+}
+
+// Emit tile t.  DIRECT = false: the sorted values are in keys1 / vals1 and t
+// is a ticket below the number of emit tiles, taken in order (the tile's
+// prefix comes from a look-back).  DIRECT = true: emit_count_tile has
+// written the sorted values to keys0 / vals0 and the tiles' run-head counts
+// and group sums, and t is the workgroup index.
+template <class T, bool DIRECT>
+__device__ __forceinline__ void emit_tile_at(const ColDesc &C, char *smem, bool again, uint32_t t) {
+    typedef typename T::K K;
+    EmitSmem<T> &S = *reinterpret_cast<EmitSmem<T> *>(smem);
+    const void *keys = DIRECT ? C.keys0 : C.keys1;
+    const uint32_t *rows = DIRECT ? C.vals0 : C.vals1;
+    uint64_t *status = again ? C.emit_status2 : C.emit_status;
+    if (DIRECT) group_prefix(C.ecnt, C.egsum, t, kEmitGroup, &S.lb);
     const uint64_t tb = (uint64_t)t * kEmitTile;
     // coalesced staging of the tile (and its predecessor value) in LDS: slot
     // x holds sorted position tb + x - 1 (zero where there is none; such
@@ -698,18 +857,18 @@ __device__ __forceinline__ void emit_tile(const ColDesc &C, char *smem, bool aga
             if (i > 0 && T::lt(T::norm(k), T::norm(prev))) unsorted = true;
         }
     }
-    if (unsorted && !again) C.sflags[kSfUnsorted] = 1u;
+    if (unsorted && !again && !DIRECT) C.sflags[kSfUnsorted] = 1u;
     const uint32_t cnt = __popc(head);
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);
-    lookback_publish(status, t, tot);
+    const uint32_t ex = block_excl_scan(cnt, S.tmp, &tot);  // its barriers also publish S.lb
+    if (!DIRECT) lookback_publish(status, t, tot);
     {
         uint32_t lo = ex;
 #pragma unroll
         for (int j = 0; j < kEmitItems; j++)
             if ((head >> j) & 1u) S.head[lo++] = (uint16_t)(l0 + j + 1);
     }
-    const uint64_t tile_prefix = lookback_resolve(status, t, tot, C.err, &S.lb);
+    const uint64_t tile_prefix = DIRECT ? S.lb : lookback_resolve(status, t, tot, C.err, &S.lb);
     __syncthreads();  // head slots complete
     for (uint32_t r = threadIdx.x; r < tot; r += kBlock) {
         const uint64_t idx = tile_prefix + r;
@@ -736,6 +895,151 @@ __device__ __forceinline__ void emit_tile(const ColDesc &C, char *smem, bool aga
     const uint64_t tile_end = (uint64_t)(t + 1) * kEmitTile;
     if (threadIdx.x == 0 && tile_end >= C.nd && (uint64_t)t * kEmitTile < C.nd)
         *C.n_ud = tile_prefix + tot;
+}
+
+// ---- the windows folded into the emit ----------------------------------------
+// The emit after the prefix sort does what window_sort_tile,
+// window_seam_tile and emit_tile do one after the other, without a pass of
+// its own for the windows.  Emit tile t needs the sorted values at its view,
+// positions [tb - 1, tb + kEmitTile) (tb = t * kEmitTile; the first one for
+// the run-head test at tb).  It stages the prefix-sorted values of the view
+// and kWinPad more on each side, finds the runs of equal prefix among them
+// and orders the view: a run of at most kRunLimit + 1 values that meets the
+// view lies wholly inside the staged range and is ranked there; a longer run
+// (also every run cut off by the staged range's ends, which are then longer
+// than that) keeps its place, and the check of adjacent pairs finds it if it
+// is out of order (the full sort then takes over).  Neighbouring tiles see
+// the same runs around their common position, so they agree on the value
+// there.  emit_count_tile (radix route) and emit_distinct_window_tile
+// (hashing route) build on window_view.
+constexpr int kWinPad = kRunLimit + 1;
+constexpr int kEmitView = kEmitTile + 1;
+constexpr int kEmitWin = kEmitView + 2 * kWinPad;  // values staged per tile
+constexpr int kEmitWinWords = (kEmitWin + 63) / 64 + 1;  // run-head mask (+1: all heads past the end)
+static_assert(kEmitWin <= 65536, "staged indices are 16-bit");
+
+template <class T>
+struct EmitWinSmem {
+    typename T::N keys[kEmitWin];  // normalized: compared without conversion
+    uint32_t vals[kEmitWin];
+    uint64_t heads[kEmitWinWords];
+    uint16_t perm[kEmitView];  // view position -> staged index of the value sorted there
+    uint32_t tmp[kWaves];
+};
+
+// The prefix of a normalized value (as prefix_of).
+template <class T>
+__device__ __forceinline__ uint32_t nprefix_of(const typename T::N &k, const int (&pp)[kPrefixSlots]) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int s = 0; s < kPrefixSlots; s++)
+        if (pp[s] >= 0) v = (v << 8) | T::ndigit(k, pp[s]);
+    return v;
+}
+
+// Stage [lo, hi) = [vb - kWinPad, ve + kWinPad) clipped to [0, n) of the
+// prefix-sorted values (keys1 / vals1) and order the view [vb, ve) inside
+// its runs of equal prefix: perm[v] = staged index of the value at sorted
+// position vb + v.  Returns lo.  Ends with a barrier.
+template <class T>
+__device__ __forceinline__ uint64_t window_view(const ColDesc &C, uint64_t n, uint64_t vb, uint64_t ve,
+                                                EmitWinSmem<T> &S) {
+    typedef typename T::N N;
+    const uint64_t lo = vb > (uint64_t)kWinPad ? vb - kWinPad : 0;
+    const uint32_t m = (uint32_t)(min<uint64_t>(n, ve + kWinPad) - lo);
+    const uint32_t v0 = (uint32_t)(vb - lo), v1 = (uint32_t)(ve - lo);  // the view, staged indices
+    struct KV {
+        N k;
+        uint32_t v;
+    };
+    constexpr int kSlots = (kEmitWin + kBlock - 1) / kBlock;
+    stage_all<kSlots>(
+        m, [&](uint32_t x) { return KV{T::norm(T::load(C.keys1, lo + x)), C.vals1[lo + x]}; },
+        [&](uint32_t x, const KV &e) {
+            S.keys[x] = e.k;
+            S.vals[x] = e.v;
+        });
+    int pp[kPrefixSlots];
+#pragma unroll
+    for (int s = 0; s < kPrefixSlots; s++) pp[s] = (int)C.sflags[kSfPrefix + s] - 1;
+    // no digit varies: every value is the same, each one a run of its own
+    const bool varies = pp[kPrefixSlots - 1] >= 0;
+    __syncthreads();
+    const int lane = lane_id();
+    for (int w = wave_id(); w < kEmitWinWords; w += kWaves) {
+        const uint32_t x = (uint32_t)w * 64 + lane;
+        bool h = true;  // staged index 0 and everything past the staged values count as heads
+        if (varies && x > 0 && x < m) h = nprefix_of<T>(S.keys[x], pp) != nprefix_of<T>(S.keys[x - 1], pp);
+        const uint64_t bal = __ballot(h);
+        if (lane == 0) S.heads[w] = bal;
+    }
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < m; x += kBlock) {
+        uint32_t w = x / 64;
+        const uint32_t bit = x & 63u;
+        uint64_t hm = S.heads[w] & (bit == 63 ? ~0ull : ((2ull << bit) - 1ull));
+        while (hm == 0) hm = S.heads[--w];  // staged index 0 is a head
+        const uint32_t s = w * 64 + 63 - (uint32_t)__clzll((long long)hm);
+        w = x / 64;
+        hm = bit == 63 ? 0ull : (S.heads[w] & ~((2ull << bit) - 1ull));
+        while (hm == 0) hm = S.heads[++w];  // the last word is all heads
+        const uint32_t e = min<uint32_t>(w * 64 + (uint32_t)(__ffsll((long long)hm) - 1), m);
+        if (e <= v0 || s >= v1) continue;  // the run misses the view
+        uint32_t dest = x;
+        if (e - s - 1 <= kRunLimit) {
+            // stable rank in the run: the members before x that are <= it
+            // and those after it that are < it, in one loop over the run
+            // (its lanes then step through the run together)
+            const N kn = S.keys[x];
+            uint32_t rank = 0;
+#pragma unroll 4
+            for (uint32_t q = s; q < e; q++)
+                rank += (q < x ? T::le(S.keys[q], kn) : T::lt(S.keys[q], kn)) ? 1u : 0u;
+            dest = s + rank;
+        }
+        if (dest >= v0 && dest < v1) S.perm[dest - v0] = (uint16_t)x;
+    }
+    __syncthreads();
+    return lo;
+}
+
+// The first half of the emit after the prefix sort: tile t orders its view
+// (window_view), writes its positions' sorted values to keys0 / vals0,
+// checks the order of adjacent pairs, counts its run heads and adds the
+// count into its group's sum; emit_tile_at<T, true> then numbers the heads.
+template <class T>
+__device__ __forceinline__ void emit_count_tile(const ColDesc &C, uint32_t t, char *smem) {
+    typedef typename T::N N;
+    EmitWinSmem<T> &S = *reinterpret_cast<EmitWinSmem<T> *>(smem);
+    const uint64_t n = C.nd;
+    const uint64_t tb = (uint64_t)t * kEmitTile;
+    if (tb >= n) return;  // the launch has one tile per kEmitTile values
+    const uint64_t vb = tb ? tb - 1 : 0, ve = min<uint64_t>(n, tb + kEmitTile);
+    window_view<T>(C, n, vb, ve, S);
+    const uint32_t off = tb ? 1u : 0u;  // view index of position tb
+    uint32_t cnt = 0;
+    bool unsorted = false;
+    for (uint32_t r = threadIdx.x; r < (uint32_t)(ve - tb); r += kBlock) {
+        const uint64_t i = tb + r;
+        const uint32_t v = off + r;
+        const N k = S.keys[S.perm[v]];
+        T::store(C.keys0, i, T::denorm(k));
+        C.vals0[i] = S.vals[S.perm[v]];
+        bool h = true;
+        if (i > 0) {
+            const N prev = S.keys[S.perm[v - 1]];
+            h = !T::eq(k, prev);
+            if (T::lt(k, prev)) unsorted = true;
+        }
+        cnt += h ? 1u : 0u;
+    }
+    if (unsorted) C.sflags[kSfUnsorted] = 1u;
+    uint32_t tot;
+    block_excl_scan(cnt, S.tmp, &tot);
+    if (threadIdx.x == 0) {
+        C.ecnt[t] = tot;
+        if (tot) atomicAdd(&C.egsum[t / kEmitGroup], tot);
+    }
 }
 
 }  // namespace mc
