@@ -145,11 +145,11 @@ struct ColLayout {
     // part Z
     uint64_t counters = 0, sflags = 0, n_ud = 0, err = 0, xflag = 0, gh = 0, trivial = 0,
              pgsum = 0, egsum = 0, emit_status = 0, emit_status2 = 0,
-             merge_status = 0, mbound = 0, dcount = 0, htab = 0, z_size = 0;
+             merge_status = 0, mbound = 0, dcount = 0, htab = 0, hgsum = 0, z_size = 0;
     // part B
     uint64_t base = 0, tcount = 0, ecnt = 0, keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, u_d = 0,
              drank = 0, x_d = 0, x_m = 0, xdev = 0, xsp = 0, rep = 0, dindex = 0, dkeys = 0,
-             drankd = 0, b_size = 0;
+             drankd = 0, hcnt = 0, drow = 0, b_size = 0;
     uint32_t sort_tiles = 0, emit_tiles = 0, hist_tiles = 0, passes = 0;
     uint64_t merge_tiles = 0, repack_tiles = 0, xc_tiles = 0;
     uint32_t repack_codes = mc::kRepackCodes, prefix_run = 0;  // launch shapes
@@ -233,6 +233,7 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     if (L.hashed && !L.indexed) {
         L.dcount = z.take(8);
         L.htab = z.take((L.hmask + 1) * 4);
+        if (L.single) L.hgsum = z.take(ceil_div(L.hash_tiles, mc::kEmitGroup) * 4);
     }
     L.z_size = z.size();
     Carver b;
@@ -251,8 +252,13 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.xsp = b.take(ceil_div(n_um, mc::kXspBlock) * 16);
     if (L.hashed && !L.indexed) {
         L.rep = b.take(nd * 4);
-        L.dindex = b.take(nd * 4);
         L.dkeys = b.take(nd * E);
+        if (L.single) {
+            L.hcnt = b.take((uint64_t)L.hash_tiles * 4);
+            L.drow = b.take(nd * 4);
+        } else {
+            L.dindex = b.take(nd * 4);
+        }
     }
     if (L.hashed) L.drankd = b.take(nd * 4);
     L.b_size = b.size();
@@ -277,9 +283,15 @@ void set_hash_fields(mc::ColDesc &C, char *za, char *zb, const ColLayout &L) {
     C.htab = reinterpret_cast<uint32_t *>(za + L.htab);
     C.hmask = L.hmask;
     C.rep = reinterpret_cast<uint32_t *>(zb + L.rep);
-    C.dindex = reinterpret_cast<uint32_t *>(zb + L.dindex);
     C.dkeys = zb + L.dkeys;
     C.dcount = reinterpret_cast<uint64_t *>(za + L.dcount);
+    if (L.single) {  // positions from per-tile counts; the sort carries representative rows
+        C.hcnt = reinterpret_cast<uint32_t *>(zb + L.hcnt);
+        C.hgsum = reinterpret_cast<uint32_t *>(za + L.hgsum);
+        C.drow = reinterpret_cast<uint32_t *>(zb + L.drow);
+    } else {
+        C.dindex = reinterpret_cast<uint32_t *>(zb + L.dindex);
+    }
     C.sort_src = C.dkeys;
     C.sort_n = C.dcount;
 }

@@ -241,6 +241,12 @@ struct ColDesc {
     uint32_t *drankd;          // rank in U_D of every distinct value (by distinct position)
     uint64_t *dcount;          // number of distinct values listed (zeroed in a merge)
     uint64_t hrow0;            // first delta row of this hashing launch (0 in a merge)
+    // single-column merges (else null): the compaction takes its positions
+    // from per-tile counts instead of one shared atomic counter, and the
+    // sort carries each distinct value's representative row
+    uint32_t *hcnt;            // representatives found by every hashing tile
+    uint32_t *hgsum;           // ... by every group of kEmitGroup hashing tiles (zeroed)
+    uint32_t *drow;            // representative row of every distinct value (sort payload)
 };
 
 // Decoupled look-back over the tiles' status words.  One wave looks back:

@@ -172,27 +172,54 @@ __device__ __forceinline__ void hash_insert_tile(const ColDesc &C, uint64_t t, c
     }
     __syncthreads();  // every thread is done reading the values
     uint32_t *grep = reinterpret_cast<uint32_t *>(S.keys);
+    uint32_t nrep = 0;  // rows of this thread that became representatives
 #pragma unroll
     for (int j = 0; j < kHashItems; j++) {
         const uint32_t i = j * kBlock + threadIdx.x;
-        if (i < tn && S.lrep[i] == i) grep[i] = res[j];
+        if (i < tn && S.lrep[i] == i) {
+            grep[i] = res[j];
+            nrep += res[j] == (uint32_t)(r0 + i) ? 1u : 0u;
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < tn; i += kBlock) C.rep[r0 + i] = grep[S.lrep[i]];
     if (!ok) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+    if (C.hcnt) {  // the tile's count of representatives, for the compaction's positions
+        nrep = wave_sum(nrep);
+        uint32_t *wsum = S.slot;  // the local table is no longer read
+        __syncthreads();
+        if (lane_id() == 0) wsum[wave_id()] = nrep;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; w++) tot += wsum[w];
+            C.hcnt[t] = tot;
+            if (tot) atomicAdd(&C.hgsum[t / kEmitGroup], tot);
+        }
+    }
 }
 
 struct CompactSmem {
     uint32_t tmp[kWaves];
     uint64_t base;  // the tile's first position in the distinct list
+    uint64_t pre;   // representatives of the tiles before it (per-tile counts)
 };
 
 constexpr int kCompactItems = 8;
 constexpr int kCompactTile = kBlock * kCompactItems;
 
+// With per-tile counts (C.hcnt, a merge's own hashing) the tile's range
+// starts after the representatives of the tiles before it, so the list is
+// in row order and no workgroup waits on a shared counter (one atomic add
+// per tile on a single word serializes the tiles); the last tile writes the
+// count.  A delta index appends its batches' values at *dcount with one
+// atomic add per tile.  With C.drow the list's payload is each value's
+// representative row; else dindex[rep] holds the value's position.
 template <class T>
 __device__ __forceinline__ void compact_tile(const ColDesc &C, uint64_t t, char *smem) {
     CompactSmem &S = *reinterpret_cast<CompactSmem *>(smem);
+    if (C.hcnt) group_prefix(C.hcnt, C.hgsum, (uint32_t)t, kEmitGroup, &S.pre);
     const uint64_t r0 = C.hrow0 + t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
     uint32_t flags = 0;
 #pragma unroll
@@ -201,11 +228,17 @@ __device__ __forceinline__ void compact_tile(const ColDesc &C, uint64_t t, char 
         if (row < C.nd && C.rep[row] == (uint32_t)row) flags |= 1u << j;
     }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan((uint32_t)__popc(flags), S.tmp, &tot);
-    if (threadIdx.x == 0)
-        S.base = tot ? atomicAdd(reinterpret_cast<unsigned long long *>(C.dcount),
-                                 (unsigned long long)tot)
-                     : 0;
+    const uint32_t ex = block_excl_scan((uint32_t)__popc(flags), S.tmp, &tot);  // also publishes S.pre
+    if (threadIdx.x == 0) {
+        if (C.hcnt) {
+            S.base = S.pre;
+            if ((t + 1) * kCompactTile >= C.nd - C.hrow0) *C.dcount = S.pre + tot;  // the last tile
+        } else {
+            S.base = tot ? atomicAdd(reinterpret_cast<unsigned long long *>(C.dcount),
+                                     (unsigned long long)tot)
+                         : 0;
+        }
+    }
     __syncthreads();
     uint64_t pos = S.base + ex;
     bool full = false;
@@ -219,7 +252,10 @@ __device__ __forceinline__ void compact_tile(const ColDesc &C, uint64_t t, char 
             const uint64_t row = r0 + j;
             if (pos < C.nd_max) {  // the distinct list's capacity
                 T::store(C.dkeys, pos, kv[j]);
-                C.dindex[row] = (uint32_t)pos;
+                if (C.drow)
+                    C.drow[pos] = (uint32_t)row;
+                else
+                    C.dindex[row] = (uint32_t)pos;
             } else {
                 full = true;
             }
@@ -238,6 +274,7 @@ __device__ __forceinline__ void emit_distinct_tile(const ColDesc &C, uint64_t t,
     const void *keys = C.keys1;  // sorted values (both sorts end in keys1 / vals1)
     const uint32_t *rows = C.vals1;
     const uint64_t n = sort_n(C);
+    const uint64_t dlim = C.drow ? C.nd : n;  // payload: a representative row, or a list position
     bool bad = false, unsorted = false;
     typedef typename T::K K;
     K k[kEmitItems], kp[kEmitItems];
@@ -258,7 +295,7 @@ __device__ __forceinline__ void emit_distinct_tile(const ColDesc &C, uint64_t t,
         // distinct values: strictly increasing
         if (i > 0 && !T::lt(T::norm(kp[j]), T::norm(k[j]))) unsorted = true;
         T::store(C.u_d, i, k[j]);
-        if (d[j] < n)
+        if (d[j] < dlim)
             C.drankd[d[j]] = (uint32_t)i;
         else
             bad = true;
@@ -289,7 +326,7 @@ __device__ __forceinline__ void emit_distinct_window_tile(const ColDesc &C, uint
         if (i > 0 && !T::lt(S.keys[S.perm[v - 1]], k)) unsorted = true;
         T::store(C.u_d, i, T::denorm(k));
         const uint32_t d = S.vals[S.perm[v]];
-        if (d < n)
+        if (d < (C.drow ? C.nd : n))  // payload: a representative row, or a list position
             C.drankd[d] = (uint32_t)i;
         else
             bad = true;
@@ -302,6 +339,29 @@ __device__ __forceinline__ void emit_distinct_window_tile(const ColDesc &C, uint
 __device__ __forceinline__ void rank_rows_tile(const ColDesc &C, uint64_t t) {
     const uint64_t n = sort_n(C);
     bool bad = false;
+    if (C.drow) {
+        // the emit wrote every distinct value's rank at its representative
+        // row: two rounds of gathers (representative, its rank)
+        uint32_t v[kHashItems];
+#pragma unroll
+        for (int j = 0; j < kHashItems; j++) {
+            const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+            v[j] = row < C.nd ? C.rep[row] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int j = 0; j < kHashItems; j++) {
+            const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+            if (row < C.nd && v[j] >= C.nd) bad = true;
+            v[j] = v[j] < C.nd ? C.drankd[v[j]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kHashItems; j++) {
+            const uint64_t row = t * kHashTile + (uint64_t)j * kBlock + threadIdx.x;
+            if (row < C.nd) C.drank[row] = v[j];
+        }
+        if (bad) flag_error(C.err, MC_DEVERR_DELTA_RANGE);
+        return;
+    }
     // three rounds of gathers (representative, its distinct position, that
     // position's rank), each with all of the thread's loads in flight
     uint32_t v[kHashItems];

@@ -90,7 +90,7 @@ __device__ __forceinline__ PassIO lsd_io(const ColDesc &C, int p) {
     PassIO io;
     io.p = C.trivial[p] ? -1 : p;
     io.src = pass_src(C, p);
-    io.vsrc = p == 0 ? nullptr : vbuf(C, p - 1);
+    io.vsrc = p == 0 ? C.drow : vbuf(C, p - 1);  // pass 0: the payload (null: the position)
     io.kdst = kbuf(C, p);
     io.vdst = vbuf(C, p);
     return io;
@@ -107,7 +107,7 @@ __device__ __forceinline__ PassIO prefix_io(const ColDesc &C, int s) {
     const bool to1 = ((kPrefixSlots - 1 - s) & 1) == 0;  // slots alternate, the last into keys1
     io.p = p >= 0 ? p : (s == kPrefixSlots - 1 ? kPassCopy : kPassSkip);
     io.src = first ? C.sort_src : (to1 ? C.keys0 : C.keys1);
-    io.vsrc = first ? nullptr : (to1 ? C.vals0 : C.vals1);
+    io.vsrc = first ? C.drow : (to1 ? C.vals0 : C.vals1);
     io.kdst = to1 ? C.keys1 : C.keys0;
     io.vdst = to1 ? C.vals1 : C.vals0;
     return io;
