@@ -209,6 +209,30 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
     torch.cuda.synchronize()
     t_b = (_t.perf_counter() - t0) / steps
 
+    # shapes per column class (type, width class, size class), tuned on the
+    # batch's columns of each class and cached in the context, against the
+    # one global shape above; the results must be identical
+    n_cls, couts = cm.autotune_batched_classes(dcols, stream=stream, ctx=ctx)
+    del couts
+    class_cache = ctx.class_tuning_cache()
+    log(f"per-class shapes for {n_cls} classes: {class_cache}")
+    couts, cgraph = cm.merge_columns_batched(dcols, graph=True, stream=stream, ctx=ctx)
+    for _ in range(warmup):
+        cgraph.launch(stream)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        cgraph.launch(stream)
+    torch.cuda.synchronize()
+    t_c = (_t.perf_counter() - t0) / steps
+    class_same = all(
+        b.scalars() == s and torch.equal(a.new_codes[: s["words"]], b.new_codes[: s["words"]])
+        and torch.equal(a.new_dict[: s["n_new"]], b.new_dict[: s["n_new"]])
+        for a, b, s in zip(outs, couts, scal))
+    del cgraph, couts
+    for c in list(class_cache):  # the per-column runs below use the global shapes
+        ctx.set_class_tuning(c)
+
     # plain: one call per column, reusing one scratch sized for the largest
     scratch = cm.alloc_scratch(max(cm.merge_bounds(d)[2] for d in dcols))
     pouts = [cm.alloc_output(d) for d in dcols]
@@ -236,7 +260,11 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
             "batched_tuples_s": rows / t_b, "plain_tuples_s": rows / t_p,
             "batched_gbs_alg": b_alg / t_b / 1e9, "plain_gbs_alg": b_alg / t_p / 1e9,
             "speedup": t_p / t_b, "batched_equals_plain": bool(same),
-            "autotuned": tune, "autotune_candidate_ms": tune_ms}
+            "autotuned": tune, "autotune_candidate_ms": tune_ms,
+            "per_class": {"classes_tuned": n_cls, "graph_ms": t_c * 1e3,
+                          "global_over_class": t_b / t_c, "equals_global": bool(class_same),
+                          "shapes": {str(k): [v["repack_codes"], v["prefix_run"]]
+                                     for k, v in sorted(class_cache.items())}}}
 
 
 def bench_serve(args, plain=False):

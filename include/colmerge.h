@@ -389,6 +389,46 @@ int mc_autotune_batched(mc_ctx *ctx, const mc_column_in *ins,
                         struct ihipStream_t *stream, mc_tuning *chosen,
                         float *times_ms);
 
+/* ---- launch shapes per column class ------------------------------------ */
+
+/* Columns of a batch fall into tuning classes by value type, input code
+ * width (1-8, 9-16, 17-24, 25-32 bits) and size (main + delta rows below
+ * 2^21, below 2^24, or more): class = (type * 4 + width class) * 3 + size
+ * class, 3 x 4 x 3 = MC_TUNE_CLASSES classes.  A context caches shapes per
+ * class; in a batched merge a column of a class with cached shapes uses
+ * their repack_codes and prefix_run (one re-encode launch per tile size in
+ * use), every other column the context's tuning.  The persistent batched
+ * launch, with one tile size, ignores the cache. */
+#define MC_TUNE_CLASSES 36u
+
+/* *cls = the class of column `in`.  MC_E_ARG for a null argument or a
+ * column descriptor that mc_merge_column would refuse. */
+int mc_tune_class(const mc_column_in *in, uint32_t *cls);
+
+/* Cache the shapes of class `cls` (< MC_TUNE_CLASSES); tuning null removes
+ * them.  MC_E_ARG for a null context, a class out of range, or
+ * repack_codes / prefix_run outside the ranges of mc_tuning. */
+int mc_ctx_set_class_tuning(mc_ctx *ctx, uint32_t cls, const mc_tuning *tuning);
+
+/* The shapes a column of class `cls` gets: the context's tuning with the
+ * class's cached repack_codes and prefix_run, if any (*is_set, nullable, is
+ * 1 then, else 0). */
+int mc_ctx_get_class_tuning(const mc_ctx *ctx, uint32_t cls, mc_tuning *tuning,
+                            int *is_set);
+
+/* Autotuner per class: for every class present in the batch (arguments as
+ * for mc_merge_columns_batched, no graph), runs the batch's columns of that
+ * class alone with each candidate shape -- repack_codes in {1024, 2048,
+ * 4096}, then prefix_run in {16, 32, 64} with the best of those -- timing
+ * each with HIP events on `stream` (best of three runs after one warm-up
+ * run), and caches the fastest for the class in the context.  *classes
+ * (nullable) receives the number of classes tuned.  It synchronizes the
+ * stream; the outputs hold the batch's merge result afterwards. */
+int mc_autotune_batched_classes(mc_ctx *ctx, const mc_column_in *ins,
+                                const mc_column_out *outs, uint32_t ncols,
+                                void *scratch, uint64_t scratch_bytes,
+                                struct ihipStream_t *stream, uint32_t *classes);
+
 /* ---- step timing (for measurement) ------------------------------------ */
 
 /* Enabling (or re-enabling) timing starts a new measurement: from then on

@@ -13,6 +13,7 @@ Tensor conventions (all on the GPU):
 from __future__ import annotations
 
 import ctypes
+import json
 from dataclasses import dataclass
 
 import numpy as np
@@ -72,6 +73,51 @@ class Context:
         t = McTuning()
         check(load().mc_ctx_get_tuning(self.handle, ctypes.byref(t)), "mc_ctx_get_tuning")
         return {f: getattr(t, f) for f in self.TUNING_FIELDS}
+
+    # ---- per-class shapes of the batched merge (a cache in the context) ----
+
+    CLASS_FIELDS = ("repack_codes", "prefix_run")
+
+    def set_class_tuning(self, cls: int, repack_codes: int | None = None,
+                         prefix_run: int | None = None):
+        """mc_ctx_set_class_tuning: cache shapes for class `cls`; with both
+        shapes None the class's entry is removed."""
+        if repack_codes is None and prefix_run is None:
+            check(load().mc_ctx_set_class_tuning(self.handle, cls, None),
+                  "mc_ctx_set_class_tuning")
+            return
+        cur = self.get_class_tuning(cls)[0]
+        t = McTuning(repack_codes or cur["repack_codes"], prefix_run or cur["prefix_run"])
+        check(load().mc_ctx_set_class_tuning(self.handle, cls, ctypes.byref(t)),
+              "mc_ctx_set_class_tuning")
+
+    def get_class_tuning(self, cls: int):
+        """mc_ctx_get_class_tuning: (shapes a column of class `cls` gets, cached?)."""
+        t, is_set = McTuning(), ctypes.c_int()
+        check(load().mc_ctx_get_class_tuning(self.handle, cls, ctypes.byref(t),
+                                             ctypes.byref(is_set)), "mc_ctx_get_class_tuning")
+        return {f: getattr(t, f) for f in self.CLASS_FIELDS}, bool(is_set.value)
+
+    def class_tuning_cache(self) -> dict:
+        """The cached classes: {class: {"repack_codes": ..., "prefix_run": ...}}."""
+        out = {}
+        for c in range(_lib.TUNE_CLASSES):
+            shapes, is_set = self.get_class_tuning(c)
+            if is_set:
+                out[c] = shapes
+        return out
+
+    def save_class_tuning(self, path: str):
+        """Write the cache as JSON (keys: class numbers)."""
+        with open(path, "w") as f:
+            json.dump({str(c): v for c, v in self.class_tuning_cache().items()}, f, indent=1)
+
+    def load_class_tuning(self, path: str):
+        """Load a cache written by save_class_tuning into this context."""
+        with open(path) as f:
+            data = json.load(f)
+        for c, v in data.items():
+            self.set_class_tuning(int(c), int(v["repack_codes"]), int(v["prefix_run"]))
 
     def __del__(self):
         try:
@@ -492,6 +538,32 @@ def autotune_batched(cols, outs=None, scratch=None, stream=None, ctx=None):
                                      scratch.numel(), _stream(stream), ctypes.byref(t), times),
           "mc_autotune_batched")
     return ({f: getattr(t, f) for f in Context.TUNING_FIELDS}, list(times), outs)
+
+
+def tune_class(col) -> int:
+    """mc_tune_class: the tuning class of a column (ColumnInput)."""
+    c = ctypes.c_uint32()
+    d = col.descriptor()
+    check(load().mc_tune_class(ctypes.byref(d), ctypes.byref(c)), "mc_tune_class")
+    return c.value
+
+
+def autotune_batched_classes(cols, outs=None, scratch=None, stream=None, ctx=None):
+    """mc_autotune_batched_classes: time the candidate shapes per class of
+    this batch and cache the fastest per class in the context.  Returns
+    (classes tuned, outs); the outputs hold the batch's merge result."""
+    ctx = ctx or context()
+    if outs is None:
+        outs = [alloc_output(c) for c in cols]
+    if scratch is None:
+        scratch = alloc_scratch(batched_bounds(cols, ctx))
+    ins = (McColumnIn * len(cols))(*[c.descriptor() for c in cols])
+    os_ = (McColumnOut * len(cols))(*[o.descriptor() for o in outs])
+    n = ctypes.c_uint32()
+    check(load().mc_autotune_batched_classes(ctx.handle, ins, os_, len(cols), _ptr(scratch),
+                                             scratch.numel(), _stream(stream), ctypes.byref(n)),
+          "mc_autotune_batched_classes")
+    return n.value, outs
 
 
 def merge_columns_batched(cols, outs=None, scratch=None, graph: bool = False, stream=None,

@@ -33,8 +33,12 @@ EXPORTS = [
     "mc_ctx_set_tuning", "mc_ctx_get_tuning", "mc_autotune_batched", "mc_merge_bounds_ctx",
     "mc_delta_index_bytes", "mc_delta_index_reset", "mc_delta_index_append",
     "mc_merge_indexed_bounds", "mc_merge_column_indexed", "mc_merge_batched_bounds_ctx",
-    "mc_merge_column_noalloc", "mc_ctx_set_validate",
+    "mc_merge_column_noalloc", "mc_ctx_set_validate", "mc_tune_class", "mc_ctx_set_class_tuning",
+    "mc_ctx_get_class_tuning", "mc_autotune_batched_classes",
 ]
+
+# Tuning classes of the batched merge (MC_TUNE_CLASSES in colmerge.h).
+TUNE_CLASSES = 36
 
 # Entries of mc_ctx_step_times (MC_STEP_TIMES in colmerge.h).
 STEP_TIMES = 6
@@ -137,6 +141,12 @@ def load():
         "mc_autotune_batched": (ctypes.c_int, [p, pin, pout, u32, p, u64, p,
                                                ctypes.POINTER(McTuning),
                                                ctypes.POINTER(ctypes.c_float)]),
+        "mc_tune_class": (ctypes.c_int, [pin, ctypes.POINTER(u32)]),
+        "mc_ctx_set_class_tuning": (ctypes.c_int, [p, u32, ctypes.POINTER(McTuning)]),
+        "mc_ctx_get_class_tuning": (ctypes.c_int, [p, u32, ctypes.POINTER(McTuning),
+                                                   ctypes.POINTER(ctypes.c_int)]),
+        "mc_autotune_batched_classes": (ctypes.c_int, [p, pin, pout, u32, p, u64, p,
+                                                       ctypes.POINTER(u32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

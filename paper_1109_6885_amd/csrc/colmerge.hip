@@ -36,6 +36,11 @@ struct mc_ctx {
     hipEvent_t meta_event = nullptr;
     // launch shapes (mc_ctx_set_tuning / mc_autotune_batched)
     mc_tuning tune = {2048u, 32u, 0u, MC_BATCHED_PHASES, 0u, 0u, 0u, 0u};
+    // per-class shapes of the batched merge (mc_ctx_set_class_tuning /
+    // mc_autotune_batched_classes): repack_codes and prefix_run of the
+    // classes that have them
+    mc_tuning class_tune[MC_TUNE_CLASSES] = {};
+    uint8_t class_set[MC_TUNE_CLASSES] = {};
     // device address of this device's allocation-free workspace
     void *noalloc_scratch = nullptr;
     // validate mode (mc_ctx_set_validate)
@@ -435,18 +440,24 @@ __global__ __launch_bounds__(256) void k_check_order(const void *u, uint64_t n, 
     if (bad) atomicOr(err, MC_DEVERR_ORDER);
 }
 
-// Plain 128-bit copy: the achievable streaming bandwidth on this GPU, and
-// the kernel of known traffic that calibrates hardware byte counters.
 // err |= *src (an index's error word into a merge's result)
 __global__ void k_or_word(uint32_t *err, const uint32_t *src) {
     if (threadIdx.x == 0 && *src) atomicOr(err, *src);
 }
 
-__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
-                                                uint4 *__restrict__ dst, uint64_t n16) {
+// Plain 128-bit copy: the achievable streaming bandwidth on this GPU, and
+// the kernel of known traffic that calibrates hardware byte counters.
+// One 16-byte non-temporal load and store per thread and one workgroup per
+// 4 KiB (measured on a 1 GiB copy: 6.57 TB/s; a grid-stride loop capped at
+// 16 workgroups per CU reached 4.6, with 2 to 16 loads per thread in flight
+// 5.4 to 6.3).  Past 2^32 work-items a launch cannot be one-shot: then each
+// thread strides.
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy16(const v4u32 *__restrict__ src,
+                                                v4u32 *__restrict__ dst, uint64_t n16) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        dst[i] = src[i];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 template <class T>
@@ -1175,11 +1186,14 @@ constexpr uint32_t kFbGrid = 2048;
 // per-column counts of every column with a delta, from which kn_fb_plan builds
 // the device maps of the columns that need the full sort (device slot p: pass
 // p, kMaxPasses + p: scan p, 2 kMaxPasses: emit)
+// kMapRepack + 0, 1, 2: the re-encode tiles of the columns whose tile is
+// 1024, 2048 or 4096 codes (one launch each; per-class shapes may mix them)
 constexpr int kMapHist = 0, kMapHistScan = 1, kMapPass = 2, kMapScan = 3, kMapEmit = 4,
-              kMapMerge = 5, kMapRepack = 8, kMapXc = 9, kMapMergePart = 10, kMapHash = 11,
-              kMapCompact = 12, kMapRank = 13, kMapFbPass = 14,
+              kMapMerge = 5, kMapRepack = 8, kMapXc = 11, kMapMergePart = 12, kMapHash = 13,
+              kMapCompact = 14, kMapRank = 15, kMapFbPass = 16,
               kMapFbScan = kMapFbPass + kMaxPasses, kMapFbEmit = kMapFbScan + kMaxPasses,
               kNumMaps = kMapFbEmit + 1;
+int repack_slot(uint32_t codes) { return codes == 1024u ? 0 : codes == 4096u ? 2 : 1; }
 constexpr int kNumDevMaps = 2 * kMaxPasses + 1;
 
 // The fallback's maps, one workgroup per device slot s: column j keeps its
@@ -1277,11 +1291,25 @@ void persist_counts(const mc_column_in *ins, uint32_t ncols, const BatchPlan &P,
 
 int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs, uint32_t ncols,
                 void *scratch, uint64_t scratch_bytes, hipStream_t stream, const mc_tuning &tune,
-                mc_graph **graph);
+                mc_graph **graph, bool use_classes = true);
 
+// Tuning class of a column: value type, input code width class (1-8, 9-16,
+// 17-24, 25-32) and size class (main + delta rows below 2^21, below 2^24,
+// or more).
+uint32_t tune_class_of(const mc_column_in &in) {
+    const uint32_t w = in.bitwidth;
+    const uint64_t n = in.main_rows + in.delta_rows;
+    const uint32_t wc = w <= 8 ? 0u : w <= 16 ? 1u : w <= 24 ? 2u : 3u;
+    const uint32_t sc = n < (1ull << 21) ? 0u : n < (1ull << 24) ? 1u : 2u;
+    return ((uint32_t)in.type * 4u + wc) * 3u + sc;
+}
+
+// classes: the context whose per-class shapes apply, or null (every column
+// takes `tune`; also the persistent launch, which has one tile size).
 int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
-               const mc_tuning &tune = kDefaultTuning) {
+               const mc_tuning &tune = kDefaultTuning, const mc_ctx *classes = nullptr) {
     P.repack_codes = tune.repack_codes;
+    if (tune.batched_launch == MC_BATCHED_PERSISTENT) classes = nullptr;
     P.z_off.resize(ncols);
     P.b_off.resize(ncols);
     P.L.resize(ncols);
@@ -1290,9 +1318,18 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
     for (uint32_t i = 0; i < ncols; i++) {
         int rc = check_in(&ins[i]);
         if (rc) return rc;
-        // each column takes the Step 1(a) route it would take alone
+        // each column takes the Step 1(a) route it would take alone, with
+        // its class's shapes if the context has them
+        mc_tuning ti = tune;
+        if (classes) {
+            const uint32_t c = tune_class_of(ins[i]);
+            if (classes->class_set[c]) {
+                ti.repack_codes = classes->class_tune[c].repack_codes;
+                ti.prefix_run = classes->class_tune[c].prefix_run;
+            }
+        }
         P.L[i] = col_layout(ins[i].type, ins[i].main_dict_len, ins[i].delta_rows,
-                            ins[i].main_rows, /*allow_hash=*/true, tune, /*indexed=*/false,
+                            ins[i].main_rows, /*allow_hash=*/true, ti, /*indexed=*/false,
                             /*batched=*/true);
         P.z_off[i] = z;
         z += P.L[i].z_size;
@@ -1351,7 +1388,8 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
             else if (m == kMapFbEmit) n = has_delta ? L.emit_tiles : 0;
             else if (m >= kMapMerge && m < kMapMerge + 3)
                 n = (int)ins[j].type == m - kMapMerge ? (L.merge_tiles ? L.merge_tiles : 1) : 0;
-            else if (m == kMapRepack) n = L.repack_tiles;
+            else if (m >= kMapRepack && m < kMapRepack + 3)
+                n = repack_slot(L.repack_codes) == m - kMapRepack ? L.repack_tiles : 0;
             else if (m == kMapXc) n = L.xc_tiles;
             else if (m == kMapMergePart) n = L.partitioned ? merge_part_blocks(L.merge_tiles) : 0;
             else if (m == kMapHash || m == kMapRank) n = L.hashed ? L.hash_tiles : 0;
@@ -1491,14 +1529,18 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
         hipLaunchKernelGGL(kn_xcompact, dim3(tiles(kMapXc)), dim3(mc::kBlock), 0, s, batch(kMapXc));
         MC_LAUNCHED("kn_xcompact");
     }
+    const dim3 rb(mc::kBlock);
+    if (tiles(kMapRepack + 1)) {
+        hipLaunchKernelGGL(kn_repack<2048>, dim3(tiles(kMapRepack + 1)), rb, 0, s, batch(kMapRepack + 1));
+        MC_LAUNCHED("kn_repack<2048>");
+    }
     if (tiles(kMapRepack)) {
-        const dim3 g(tiles(kMapRepack)), b(mc::kBlock);
-        switch (P.repack_codes) {
-            case 1024: hipLaunchKernelGGL(kn_repack<1024>, g, b, 0, s, batch(kMapRepack)); break;
-            case 4096: hipLaunchKernelGGL(kn_repack<4096>, g, b, 0, s, batch(kMapRepack)); break;
-            default: hipLaunchKernelGGL(kn_repack<2048>, g, b, 0, s, batch(kMapRepack)); break;
-        }
-        MC_LAUNCHED("kn_repack");
+        hipLaunchKernelGGL(kn_repack<1024>, dim3(tiles(kMapRepack)), rb, 0, s, batch(kMapRepack));
+        MC_LAUNCHED("kn_repack<1024>");
+    }
+    if (tiles(kMapRepack + 2)) {
+        hipLaunchKernelGGL(kn_repack<4096>, dim3(tiles(kMapRepack + 2)), rb, 0, s, batch(kMapRepack + 2));
+        MC_LAUNCHED("kn_repack<4096>");
     }
     return MC_OK;
 }
@@ -2175,13 +2217,10 @@ int mc_copy_bytes(mc_ctx *ctx, const void *src, void *dst, uint64_t bytes, hipSt
         return fail(MC_E_ARG, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
     if (bytes && (!src || !dst)) return fail(MC_E_ARG, "null buffer");
     if (bytes == 0) return MC_OK;
-    int dev = 0, cus = 256;
-    MC_HIP(hipGetDevice(&dev));
-    MC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    uint64_t grid = ceil_div(bytes / 16, 256);
-    if (grid > (uint64_t)cus * 16) grid = (uint64_t)cus * 16;
+    // one thread per 16 bytes, within a launch's 2^32 work-items
+    const uint64_t grid = std::min<uint64_t>(ceil_div(bytes / 16, 256), (1ull << 24) - 1);
     hipLaunchKernelGGL(k_copy16, dim3((uint32_t)grid), dim3(256), 0, s,
-                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), bytes / 16);
+                       static_cast<const v4u32 *>(src), static_cast<v4u32 *>(dst), bytes / 16);
     MC_LAUNCHED("k_copy16");
     return MC_OK;
 }
@@ -2380,12 +2419,14 @@ int mc_autotune_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_column_ou
     }
     // one warm-up run, then the best of two timed runs
     auto time_one = [&](const mc_tuning &t, float *ms) -> int {
-        int rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, t, nullptr);
+        int rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, t, nullptr,
+                             false);
         if (rc) return rc;
         float best = 0.0f;
         for (int r = 0; r < 2; r++) {
             MC_HIP(hipEventRecord(e0, stream));
-            rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, t, nullptr);
+            rc = batched_run(ctx, ins, outs, ncols, scratch, scratch_bytes, stream, t, nullptr,
+                             false);
             if (rc) return rc;
             MC_HIP(hipEventRecord(e1, stream));
             MC_HIP(hipEventSynchronize(e1));
@@ -2429,17 +2470,142 @@ int mc_autotune_batched(mc_ctx *ctx, const mc_column_in *ins, const mc_column_ou
     return MC_OK;
 }
 
+int mc_tune_class(const mc_column_in *in, uint32_t *cls) {
+    if (!in || !cls) return fail(MC_E_ARG, "null argument");
+    int rc = check_in(in);
+    if (rc) return rc;
+    *cls = tune_class_of(*in);
+    return MC_OK;
+}
+
+int mc_ctx_set_class_tuning(mc_ctx *ctx, uint32_t cls, const mc_tuning *t) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    if (cls >= MC_TUNE_CLASSES) return fail(MC_E_ARG, "class out of range");
+    if (!t) {
+        ctx->class_set[cls] = 0;
+        return MC_OK;
+    }
+    if (t->repack_codes != 1024 && t->repack_codes != 2048 && t->repack_codes != 4096)
+        return fail(MC_E_ARG, "repack_codes must be 1024, 2048 or 4096");
+    if (t->prefix_run < 4 || t->prefix_run > 1024)
+        return fail(MC_E_ARG, "prefix_run must be in [4, 1024]");
+    ctx->class_tune[cls] = ctx->tune;
+    ctx->class_tune[cls].repack_codes = t->repack_codes;
+    ctx->class_tune[cls].prefix_run = t->prefix_run;
+    ctx->class_set[cls] = 1;
+    return MC_OK;
+}
+
+int mc_ctx_get_class_tuning(const mc_ctx *ctx, uint32_t cls, mc_tuning *t, int *is_set) {
+    if (!ctx || !t) return fail(MC_E_ARG, "null argument");
+    if (cls >= MC_TUNE_CLASSES) return fail(MC_E_ARG, "class out of range");
+    *t = ctx->tune;
+    if (ctx->class_set[cls]) {
+        t->repack_codes = ctx->class_tune[cls].repack_codes;
+        t->prefix_run = ctx->class_tune[cls].prefix_run;
+    }
+    if (is_set) *is_set = ctx->class_set[cls];
+    return MC_OK;
+}
+
+int mc_autotune_batched_classes(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
+                                uint32_t ncols, void *scratch, uint64_t scratch_bytes,
+                                hipStream_t stream, uint32_t *classes) {
+    if (!ctx) return fail(MC_E_ARG, "null context");
+    if (ncols && (!ins || !outs)) return fail(MC_E_ARG, "null descriptors");
+    std::vector<std::vector<uint32_t>> members(MC_TUNE_CLASSES);
+    for (uint32_t j = 0; j < ncols; j++) {
+        int rc = check_in(&ins[j]);
+        if (rc) return rc;
+        members[tune_class_of(ins[j])].push_back(j);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MC_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    std::vector<mc_column_in> sub_in;
+    std::vector<mc_column_out> sub_out;
+    // one warm-up run, then the best of three timed runs of the class's columns
+    auto time_one = [&](const mc_tuning &t, float *ms) -> int {
+        const uint32_t n = (uint32_t)sub_in.size();
+        int rc = batched_run(ctx, sub_in.data(), sub_out.data(), n, scratch, scratch_bytes, stream,
+                             t, nullptr, false);
+        if (rc) return rc;
+        float best = 0.0f;
+        for (int r = 0; r < 3; r++) {
+            MC_HIP(hipEventRecord(e0, stream));
+            rc = batched_run(ctx, sub_in.data(), sub_out.data(), n, scratch, scratch_bytes, stream,
+                             t, nullptr, false);
+            if (rc) return rc;
+            MC_HIP(hipEventRecord(e1, stream));
+            MC_HIP(hipEventSynchronize(e1));
+            float x = 0.0f;
+            MC_HIP(hipEventElapsedTime(&x, e0, e1));
+            best = r == 0 ? x : std::min(best, x);
+        }
+        *ms = best;
+        return MC_OK;
+    };
+    int rc = MC_OK;
+    uint32_t tuned = 0;
+    const uint32_t codes[3] = {1024u, 2048u, 4096u}, runs[3] = {16u, 32u, 64u};
+    for (uint32_t c = 0; c < MC_TUNE_CLASSES && rc == MC_OK; c++) {
+        if (members[c].empty()) continue;
+        sub_in.clear();
+        sub_out.clear();
+        for (uint32_t j : members[c]) {
+            sub_in.push_back(ins[j]);
+            sub_out.push_back(outs[j]);
+        }
+        mc_tuning best = ctx->tune;
+        float best_ms = 0.0f, x = 0.0f;
+        for (int i = 0; i < 3 && rc == MC_OK; i++) {
+            mc_tuning t = ctx->tune;
+            t.repack_codes = codes[i];
+            rc = time_one(t, &x);
+            if (rc == MC_OK && (i == 0 || x < best_ms)) {
+                best = t;
+                best_ms = x;
+            }
+        }
+        const mc_tuning by_codes = best;
+        for (int i = 0; i < 3 && rc == MC_OK; i++) {
+            mc_tuning t = by_codes;
+            t.prefix_run = runs[i];
+            if (t.prefix_run == by_codes.prefix_run) continue;  // timed above
+            rc = time_one(t, &x);
+            if (rc == MC_OK && x < best_ms) {
+                best = t;
+                best_ms = x;
+            }
+        }
+        if (rc == MC_OK) {
+            ctx->class_tune[c] = best;
+            ctx->class_set[c] = 1;
+            tuned++;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (classes) *classes = tuned;
+    return MC_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
 int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs, uint32_t ncols,
                 void *scratch, uint64_t scratch_bytes, hipStream_t stream, const mc_tuning &tune,
-                mc_graph **graph) {
+                mc_graph **graph, bool use_classes) {
     if (ncols == 0) return MC_OK;
     if (!ins || !outs) return fail(MC_E_ARG, "null descriptors");
     BatchPlan P;
-    int rc = plan_batch(ins, ncols, P, tune);
+    int rc = plan_batch(ins, ncols, P, tune, use_classes ? ctx : nullptr);
     if (rc) return rc;
     for (uint32_t i = 0; i < ncols; i++) {
         rc = check_out(&ins[i], &outs[i]);

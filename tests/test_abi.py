@@ -167,3 +167,27 @@ def test_row_limit_matches_launch_limit(lib):
     rc, *_ = _bounds(lib, _in(n_main=(1 << 34) - 1024 - 1_000_000 + 1))
     assert rc == -1
     assert b"2^34" in lib.mc_last_error()
+
+
+def test_tune_class(lib):
+    """mc_tune_class: class = (type * 4 + width class) * 3 + size class, with
+    width classes 1-8, 9-16, 17-24, 25-32 bits and size classes below 2^21,
+    below 2^24 and from 2^24 main + delta rows; refused descriptors."""
+    c = ctypes.c_uint32()
+    cases = [((0, 4, 10, 100, 5), 0), ((0, 8, 200, 1 << 20, 1 << 20), 1),
+             ((1, 9, 300, (1 << 24) - 1, 1), (1 * 4 + 1) * 3 + 2),
+             ((1, 20, 1_048_000, 100_000_000, 1_000_000), (1 * 4 + 2) * 3 + 2),
+             ((2, 24, 10_000_000, 100_000_000, 10_000_000), (2 * 4 + 2) * 3 + 2),
+             ((2, 32, 1 << 31, 10, 10), (2 * 4 + 3) * 3 + 0),
+             ((2, 17, 70_000, (1 << 21) - 11, 10), (2 * 4 + 2) * 3 + 0),
+             ((2, 17, 70_000, (1 << 21) - 10, 10), (2 * 4 + 2) * 3 + 1)]
+    for (t, w, n_um, n_main, nd), want in cases:
+        assert lib.mc_tune_class(ctypes.byref(_in(t, w, n_um, n_main, nd)), ctypes.byref(c)) == 0
+        assert c.value == want, (t, w, n_main, nd, c.value, want)
+        assert c.value < _lib.TUNE_CLASSES
+    assert lib.mc_tune_class(ctypes.byref(_in(w=0)), ctypes.byref(c)) == -1
+    assert lib.mc_tune_class(None, ctypes.byref(c)) == -1
+    t = _lib.McTuning(2048, 32)
+    assert lib.mc_ctx_set_class_tuning(None, 0, ctypes.byref(t)) == -1
+    assert lib.mc_ctx_get_class_tuning(None, 0, ctypes.byref(t), None) == -1
+    assert lib.mc_autotune_batched_classes(None, None, None, 0, None, 0, None, None) == -1

@@ -185,6 +185,63 @@ def test_batched_full_sort_many_columns():
         check_col(c, o.fetch())
 
 
+def test_class_shapes_mixed():
+    """Per-class shapes: every class of the batch gets a different re-encode
+    tile (1024, 2048, 4096 in turn) and prefix run, so one batch runs the
+    three re-encode launches side by side; every column still matches the
+    oracle, also from a graph, and clearing the cache restores the context's
+    shapes."""
+    cols = small_batch(30, 0.002)
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    ctx = cm.Context(torch.cuda.current_device())
+    classes = sorted({cm.tune_class(d) for d in dcols})
+    say(f"case mixed class shapes, {len(cols)} columns, classes {classes}")
+    codes, runs = (1024, 2048, 4096), (16, 32, 64)
+    for i, c in enumerate(classes):
+        ctx.set_class_tuning(c, codes[i % 3], runs[(i // 3) % 3])
+    assert set(ctx.class_tuning_cache()) == set(classes)
+    assert len({ctx.get_class_tuning(c)[0]["repack_codes"] for c in classes}) == min(3, len(classes))
+    for graph in (False, True):
+        outs, g = cm.merge_columns_batched(dcols, ctx=ctx, graph=graph)
+        torch.cuda.synchronize()
+        for c, o in zip(cols, outs):
+            check_col(c, o.fetch())
+    for c in classes:
+        ctx.set_class_tuning(c)
+    assert ctx.class_tuning_cache() == {}
+    assert ctx.get_class_tuning(classes[0]) == ({"repack_codes": 2048, "prefix_run": 32}, False)
+
+
+def test_autotune_batched_classes(tmp_path):
+    """The per-class autotuner caches one of its candidates for every class of
+    the batch, leaves the batch's result in the outputs, and the cache
+    survives a JSON round trip into a fresh context whose merges agree with
+    the oracle."""
+    cols = small_batch(24, 0.002)
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    ctx = cm.Context(torch.cuda.current_device())
+    classes = {cm.tune_class(d) for d in dcols}
+    say(f"case class autotune, {len(cols)} columns, {len(classes)} classes")
+    n, outs = cm.autotune_batched_classes(dcols, ctx=ctx)
+    torch.cuda.synchronize()
+    assert n == len(classes)
+    cache = ctx.class_tuning_cache()
+    assert set(cache) == classes
+    for v in cache.values():
+        assert v["repack_codes"] in (1024, 2048, 4096) and v["prefix_run"] in (16, 32, 64)
+    for c, o in zip(cols, outs):
+        check_col(c, o.fetch())
+    path = str(tmp_path / "classes.json")
+    ctx.save_class_tuning(path)
+    ctx2 = cm.Context(torch.cuda.current_device())
+    ctx2.load_class_tuning(path)
+    assert ctx2.class_tuning_cache() == cache
+    outs2, _ = cm.merge_columns_batched(dcols, ctx=ctx2)
+    torch.cuda.synchronize()
+    for c, o in zip(cols, outs2):
+        check_col(c, o.fetch())
+
+
 def test_autotune_batched():
     """The autotuner picks one of its candidates, leaves the batch's result
     in the outputs, and later batched merges with the chosen shapes agree
