@@ -267,6 +267,36 @@ def bench_batched(cm, torch, cols, steps, warmup, stream, ctx):
                                      for k, v in sorted(class_cache.items())}}}
 
 
+def bench_batched_only(args):
+    """The 300-column batch alone with the default launch shapes: one graph,
+    `warmup` untimed replays, `steps` timed ones (a clean run for kernel
+    traces and counters of the batched kernels)."""
+    import torch
+
+    import paper_1109_6885_amd as cm
+    from workloads import gen
+    t = time.time()
+    cols = gen.batched_columns(300, workers=args.gen_workers)
+    log(f"generated the 300-column workload in {time.time() - t:.1f}s")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    outs, graph = cm.merge_columns_batched(dcols, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    assert all(o.scalars()["error"] == 0 for o in outs)
+    for _ in range(args.warmup):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / max(args.steps, 1)
+    rows = sum(c.n_main + c.n_delta for c in cols)
+    return {"workload": "300 columns (batched only)", "rows": rows, "graph_ms": ms,
+            "tuples_s": rows / (ms / 1000.0), "steps": args.steps, "warmup": args.warmup}
+
+
 def bench_serve(args, plain=False):
     """Served merge stream: 64 resident tables (10-200 columns each, column
     shapes as in the batched workload) built in HBM, appends every 10 ms from
@@ -692,6 +722,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=5.0, help="merge requests per second")
     ap.add_argument("--sweep", choices=["fig7", "fig8", "fig9", "index"],
                     help="run a sweep instead and print its JSON line")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 300-column batch with the default shapes, replayed from a "
+                         "graph (--warmup untimed, --steps timed; for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -705,6 +738,9 @@ def main():
         fn = {"fig7": bench_sweep_fig7, "fig8": bench_sweep_fig8, "fig9": bench_sweep_fig9,
               "index": bench_index}
         print(json.dumps(fn[args.sweep](args)), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(bench_batched_only(args)), flush=True)
         return
 
     import concurrent.futures as cf
