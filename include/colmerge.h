@@ -355,7 +355,12 @@ void mc_graph_destroy(mc_graph *graph);
  *   persist_repack: Step 2(b) tiles per work item of the persistent launch
  *                 (0: default 4; at most 1024);
  *   persist_merge: dictionary-merge tiles per work item (0: default 2; at
- *                 most 1024).
+ *                 most 1024);
+ *   hash_dict_ratio: a delta of at least 4096 rows also hashes first when
+ *                 it has at least this many times as many rows as U_M has
+ *                 entries (0: the default, 64; 0xFFFFFFFF: never): most
+ *                 of its rows then repeat a few values, whose runs of equal
+ *                 prefix the prefix sort cannot order in place.
  * The results do not depend on them. */
 #define MC_BATCHED_PHASES 0u
 #define MC_BATCHED_PERSISTENT 1u
@@ -367,7 +372,7 @@ typedef struct mc_tuning {
     uint32_t persist_workers;
     uint32_t persist_repack;
     uint32_t persist_merge;
-    uint32_t reserved; /* zero */
+    uint32_t hash_dict_ratio;
 } mc_tuning;
 
 /* MC_E_ARG if a value is outside the ranges above (the context keeps its

@@ -58,15 +58,16 @@ class Context:
         check(load().mc_ctx_set_validate(self.handle, int(bool(on))), "mc_ctx_set_validate")
 
     TUNING_FIELDS = ("repack_codes", "prefix_run", "hash_min_rows", "batched_launch",
-                     "persist_workers", "persist_repack", "persist_merge")
+                     "persist_workers", "persist_repack", "persist_merge", "hash_dict_ratio")
 
     def set_tuning(self, repack_codes: int = 2048, prefix_run: int = 32, hash_min_rows: int = 0,
                    batched_launch: int = 0, persist_workers: int = 0, persist_repack: int = 0,
-                   persist_merge: int = 0):
+                   persist_merge: int = 0, hash_dict_ratio: int = 0):
         """mc_ctx_set_tuning: launch shapes for every later merge on this context
-        (batched_launch: 0 one launch per phase, 1 one persistent launch)."""
+        (batched_launch: 0 one launch per phase, 1 one persistent launch;
+        hash_dict_ratio: 0 default 64, 0xFFFFFFFF never)."""
         t = McTuning(repack_codes, prefix_run, hash_min_rows, batched_launch, persist_workers,
-                     persist_repack, persist_merge, 0)
+                     persist_repack, persist_merge, hash_dict_ratio)
         check(load().mc_ctx_set_tuning(self.handle, ctypes.byref(t)), "mc_ctx_set_tuning")
 
     def get_tuning(self) -> dict:

@@ -74,7 +74,7 @@ class McTuning(ctypes.Structure):
     _fields_ = [("repack_codes", ctypes.c_uint32), ("prefix_run", ctypes.c_uint32),
                 ("hash_min_rows", ctypes.c_uint32), ("batched_launch", ctypes.c_uint32),
                 ("persist_workers", ctypes.c_uint32), ("persist_repack", ctypes.c_uint32),
-                ("persist_merge", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("persist_merge", ctypes.c_uint32), ("hash_dict_ratio", ctypes.c_uint32)]
 
 
 class McDeltaIndex(ctypes.Structure):

@@ -171,6 +171,21 @@ struct ColLayout {
 // the radix passes then only see distinct values.  Smaller deltas sort
 // directly (their passes are latency-bound, and hashing would add work).
 constexpr uint64_t kHashMinRows = 1ull << 21;
+// A delta of at least kHashMinRowsDict rows with at least hash_dict_ratio
+// (default kHashDictRatio) times as many rows as U_M has entries hashes
+// first too: if a good share of its rows repeat main values, each of those
+// values fills a run of equal prefix thousands of values long, and one
+// other value sharing the prefix leaves the run out of order, which costs
+// the full LSD sort (16 passes for strings).  Hashing leaves the radix
+// passes only the distinct values.  (On the 300-column batch: every one of
+// the 16 columns that took the full sort has 6 to 738 dictionary entries
+// and 29K to 197K delta rows.)
+constexpr uint64_t kHashMinRowsDict = 4096;
+constexpr uint64_t kHashDictRatio = 64;
+bool many_repeats(uint64_t nd, uint64_t n_um, uint32_t ratio) {
+    if (ratio == 0xFFFFFFFFu || n_um == 0 || nd < kHashMinRowsDict) return false;
+    return nd >= (ratio ? ratio : kHashDictRatio) * n_um;
+}
 
 // Merges of at least this many tiles find the tile boundaries in a launch of
 // their own (one wave per boundary, all at once) instead of at the start of
@@ -201,7 +216,8 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     const uint32_t E = value_len(type);
     L.indexed = indexed;
     L.hashed = indexed ||
-               (allow_hash && nd >= (tune.hash_min_rows ? tune.hash_min_rows : kHashMinRows));
+               (allow_hash && (nd >= (tune.hash_min_rows ? tune.hash_min_rows : kHashMinRows) ||
+                               many_repeats(nd, n_um, tune.hash_dict_ratio)));
     if (L.hashed) L.hash_tiles = (uint32_t)ceil_div(nd, mc::kHashTile);  // also rank_rows' grid
     if (L.hashed && !L.indexed) {
         uint64_t h = 1024;
@@ -2395,7 +2411,6 @@ int mc_ctx_set_tuning(mc_ctx *ctx, const mc_tuning *t) {
                     "one workgroup) and the cause is not found; use MC_BATCHED_PHASES");
     if (t->persist_repack > 1024 || t->persist_merge > 1024)
         return fail(MC_E_ARG, "persist_repack and persist_merge must be at most 1024");
-    if (t->reserved) return fail(MC_E_ARG, "the reserved field must be zero");
     ctx->tune = *t;
     return MC_OK;
 }

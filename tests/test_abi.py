@@ -191,3 +191,16 @@ def test_tune_class(lib):
     assert lib.mc_ctx_set_class_tuning(None, 0, ctypes.byref(t)) == -1
     assert lib.mc_ctx_get_class_tuning(None, 0, ctypes.byref(t), None) == -1
     assert lib.mc_autotune_batched_classes(None, None, None, 0, None, 0, None, None) == -1
+
+
+def test_few_main_values_take_the_hashing_route(lib):
+    """A delta of at least 4096 rows with at least 64 times as many rows as
+    the dictionary has entries hashes first: its workspace then holds the
+    hash table (a power of two of at least twice the rows, 4 bytes a
+    slot); 63 times as many rows, or 4095 rows, keep the radix route."""
+    def scratch(n_um, nd):
+        return _bounds(lib, _in(type_=0, w=12, n_um=n_um, n_main=10_000, nd=nd))[3]
+    table = lambda nd: 4 * (1 << max(10, (2 * nd - 1).bit_length()))
+    assert scratch(100, 6_400) - scratch(101, 6_400) >= table(6_400)
+    assert scratch(1, 4_096) - scratch(1, 4_095) >= table(4_096)
+    assert scratch(100, 6_400) - scratch(100, 6_300) >= table(6_400)

@@ -172,7 +172,10 @@ def test_batched_full_sort_many_columns():
             cols.append(gen.random_column(rng, vt, 4000, 30_000, 9_000, 0.5))
     say(f"case batched full sort, {len(cols)} columns")
     dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
-    outs, graph = cm.merge_columns_batched(dcols, graph=True)
+    # the radix route (600,000 rows over 3,000 entries would hash by default)
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(hash_dict_ratio=0xFFFFFFFF)
+    outs, graph = cm.merge_columns_batched(dcols, graph=True, ctx=ctx)
     torch.cuda.synchronize()
     for c, o in zip(cols, outs):
         check_col(c, o.fetch())
@@ -183,6 +186,28 @@ def test_batched_full_sort_many_columns():
     torch.cuda.synchronize()
     for c, o in zip(cols, outs):
         check_col(c, o.fetch())
+
+
+def test_batched_few_main_values_repeated():
+    """Columns whose deltas repeat a few main values (the shapes of the
+    300-column batch that needed the full sort) beside ordinary ones: by
+    default they hash first; with the rule off they take the radix route and
+    the full sort; both agree with the oracle."""
+    rng = np.random.default_rng(23)
+    cols = []
+    for vt, kd, nd in (("str16", 6, 63_400), ("u32", 119, 197_246), ("str16", 738, 168_887),
+                       ("u64", 66, 155_927), ("str16", 50, 28_997)):
+        cols.append(gen.random_column(rng, vt, kd, 30_000, nd, 0.5))
+        cols.append(gen.random_column(rng, vt, 20_000, 30_000, 5_000, 0.5))
+    dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
+    for ratio in (0, 0xFFFFFFFF):
+        say(f"case batched few main values repeated, {len(cols)} columns, ratio {ratio:#x}")
+        ctx = cm.Context(torch.cuda.current_device())
+        ctx.set_tuning(hash_dict_ratio=ratio)
+        outs, _ = cm.merge_columns_batched(dcols, ctx=ctx)
+        torch.cuda.synchronize()
+        for c, o in zip(cols, outs):
+            check_col(c, o.fetch())
 
 
 def test_class_shapes_mixed():

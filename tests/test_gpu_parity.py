@@ -26,10 +26,20 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_merge(col, tables=True):
-    out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=tables)
+def gpu_merge(col, tables=True, ctx=None):
+    out = cm.merge_column(cm.ColumnInput.from_numpy(col), tables=tables, ctx=ctx)
     torch.cuda.synchronize()
     return out.fetch()
+
+
+NEVER_HASH = 0xFFFFFFFF  # hash_dict_ratio: no delta hashes for repeating few main values
+
+
+def radix_ctx():
+    """A context whose deltas below 2^21 rows always take the radix route."""
+    ctx = cm.Context(torch.cuda.current_device())
+    ctx.set_tuning(hash_dict_ratio=NEVER_HASH)
+    return ctx
 
 
 def ora_merge(col):
@@ -514,7 +524,9 @@ def test_full_sort_grid_shapes(vtype, nd):
     """The full sort runs as one launch of at most one workgroup per compute
     unit that strides over tiles and digits: deltas of 147-977 sort tiles
     (fewer tiles than digits, more tiles than workgroups), almost all values
-    behind one 2-byte prefix so that the full sort must run."""
+    behind one 2-byte prefix so that the full sort must run (radix route:
+    these deltas have over 64 times as many rows as the dictionary has
+    entries, which would send them through the hashing route by default)."""
     rng = np.random.default_rng(93)
     base = gen.random_column(rng, vtype, 2000, 10_000, 0)
     if vtype == "str16":
@@ -528,7 +540,7 @@ def test_full_sort_grid_shapes(vtype, nd):
     d = d[rng.permutation(d.shape[0])]
     col = gen.Column(vtype, base.u_m, base.main_packed, base.n_main, base.w, d)
     say(f"case full sort grid shapes {vtype} nd={col.n_delta}")
-    assert_same(gpu_merge(col), ora_merge(col))
+    assert_same(gpu_merge(col, ctx=radix_ctx()), ora_merge(col))
 
 
 def test_full_sort_concurrent_streams():
@@ -550,7 +562,7 @@ def test_full_sort_concurrent_streams():
     say("case full sort on six streams at once, str16, 1M delta rows each")
     dev = torch.cuda.current_device()
     streams = [torch.cuda.Stream() for _ in cols]
-    ctxs = [cm.Context(dev) for _ in cols]
+    ctxs = [radix_ctx() for _ in cols]  # the radix route's one-launch full sort
     dcols = [cm.ColumnInput.from_numpy(c) for c in cols]
     outs = [cm.alloc_output(d, tables=True) for d in dcols]
     scratch = [cm.alloc_scratch(cm.merge_bounds(d, x)[2]) for d, x in zip(dcols, ctxs)]
@@ -686,7 +698,7 @@ def test_set_tuning_rejects_bad_shapes():
             ctx.set_tuning(**kw)
     assert ctx.get_tuning() == {"repack_codes": 2048, "prefix_run": 32, "hash_min_rows": 0,
                                 "batched_launch": 0, "persist_workers": 0, "persist_repack": 0,
-                                "persist_merge": 0}
+                                "persist_merge": 0, "hash_dict_ratio": 0}
 
 
 @pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
@@ -726,3 +738,21 @@ def test_hash_route_step_entry():
     assert n == ref_ud.shape[0]
     assert np.array_equal(u_d[:n].cpu().numpy().view(np.uint64), ref_ud)
     assert np.array_equal(drank.cpu().numpy().view(np.uint32), ref_drank)
+
+
+@pytest.mark.parametrize("vtype", ["u32", "u64", "str16"])
+@pytest.mark.parametrize("kd,nd", [(6, 63_400), (119, 197_246), (738, 168_887), (3, 4_095),
+                                   (64, 4_096)])
+def test_few_main_values_repeated(vtype, kd, nd):
+    """Deltas with at least 64 times as many rows as the dictionary has
+    entries (and at least 4096 rows) hash first: half their rows repeat the
+    few main values, half are new.  The same merge through the radix route
+    (the rule switched off), where such deltas usually need the full sort,
+    and the oracle agree byte for byte.  (4,095 rows stay on the radix
+    route; 4,096 rows over 64 entries is the first to hash.)"""
+    rng = np.random.default_rng(kd * 7 + nd)
+    col = gen.random_column(rng, vtype, kd, 40_000, nd, 0.5)
+    say(f"case few main values repeated {vtype} kd={kd} nd={nd}")
+    ref = ora_merge(col)
+    assert_same(gpu_merge(col), ref)
+    assert_same(gpu_merge(col, ctx=radix_ctx()), ref)
