@@ -720,11 +720,13 @@ __global__ __launch_bounds__(256) void kn_hist_scan(Batch B) {
 // unsorted, so an unneeded pass is a launch of workgroups that return).
 __device__ __forceinline__ uint32_t map_total(const Batch &B) { return B.map[B.ncols]; }
 
-__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p) {
-    __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
+// The bodies stride: workgroup `first` of `count` takes units first,
+// first + count, ... of the map (a launch, or the one-launch fallback below).
+__device__ __forceinline__ void sort_up_units(const Batch &B, int kind, int p, uint32_t first,
+                                              uint32_t count, char *smem) {
     const uint32_t total = map_total(B);
-    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-        if (b != blockIdx.x) __syncthreads();  // the tile before is done with the LDS
+    for (uint32_t b = first; b < total; b += count) {
+        if (b != first) __syncthreads();  // the tile before is done with the LDS
         const uint32_t j = find_col(B, b);
         const mc::ColDesc &C = B.cols[j];
         mc::PassIO io;
@@ -732,11 +734,11 @@ __global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p) {
         MC_DISPATCH(C, mc::sort_up_tile, C, io, b - B.map[j], smem);
     }
 }
-__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p) {
-    __shared__ __attribute__((aligned(16))) char smem[64];
+__device__ __forceinline__ void sort_scan_units(const Batch &B, int kind, int p, uint32_t first,
+                                                uint32_t count, char *smem) {
     const uint32_t total = map_total(B);
-    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-        if (b != blockIdx.x) __syncthreads();
+    for (uint32_t b = first; b < total; b += count) {
+        if (b != first) __syncthreads();
         const uint32_t j = find_col(B, b);
         const mc::ColDesc &C = B.cols[j];
         mc::PassIO io;
@@ -748,17 +750,47 @@ __global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p) {
         }
     }
 }
-__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p) {
-    __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
+__device__ __forceinline__ void sort_down_units(const Batch &B, int kind, int p, uint32_t first,
+                                                uint32_t count, char *smem) {
     const uint32_t total = map_total(B);
-    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-        if (b != blockIdx.x) __syncthreads();
+    for (uint32_t b = first; b < total; b += count) {
+        if (b != first) __syncthreads();
         const uint32_t j = find_col(B, b);
         const mc::ColDesc &C = B.cols[j];
         mc::PassIO io;
         if (!pass_io(C, kind, p, &io)) continue;
         MC_DISPATCH(C, mc::sort_down_tile, C, io, b - B.map[j], smem);
     }
+}
+// emit_tile takes its tile from a per-column ticket (a workgroup holds one
+// ticket at a time and waits only on lower ones, all held by running
+// workgroups), emit_distinct_tile waits on no other tile.
+__device__ __forceinline__ void emit_units(const Batch &B, bool again, uint32_t first,
+                                           uint32_t count, char *smem) {
+    const uint32_t total = map_total(B);
+    for (uint32_t b = first; b < total; b += count) {
+        if (b != first) __syncthreads();
+        const uint32_t j = find_col(B, b);
+        const mc::ColDesc &C = B.cols[j];
+        if (C.drankd) {  // hashing route: the sorted values are distinct
+            MC_DISPATCH(C, mc::emit_distinct_tile, C, b - B.map[j], again);
+        } else {
+            MC_DISPATCH(C, mc::emit_tile, C, smem, again);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void kn_sort_up(Batch B, int kind, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemSmall];
+    sort_up_units(B, kind, p, blockIdx.x, gridDim.x, smem);
+}
+__global__ __launch_bounds__(256) void kn_sort_scan(Batch B, int kind, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[64];
+    sort_scan_units(B, kind, p, blockIdx.x, gridDim.x, smem);
+}
+__global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
+    sort_down_units(B, kind, p, blockIdx.x, gridDim.x, smem);
 }
 __global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
@@ -770,22 +802,9 @@ __global__ __launch_bounds__(256) void kn_window(Batch B, int round) {
         MC_DISPATCH(C, mc::window_seam_tile, C, blockIdx.x - B.map[j], smem);
     }
 }
-// Strides like the passes: emit_tile takes its tile from a per-column ticket
-// (a workgroup holds one ticket at a time and waits only on lower ones, all
-// held by running workgroups), emit_distinct_tile waits on no other tile.
 __global__ __launch_bounds__(256) void kn_emit(Batch B, int again) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];
-    const uint32_t total = map_total(B);
-    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-        if (b != blockIdx.x) __syncthreads();
-        const uint32_t j = find_col(B, b);
-        const mc::ColDesc &C = B.cols[j];
-        if (C.drankd) {  // hashing route: the sorted values are distinct
-            MC_DISPATCH(C, mc::emit_distinct_tile, C, b - B.map[j], again != 0);
-        } else {
-            MC_DISPATCH(C, mc::emit_tile, C, smem, again != 0);
-        }
-    }
+    emit_units(B, again != 0, blockIdx.x, gridDim.x, smem);
 }
 // Step 1(a)'s hashing route for the columns whose deltas take it
 __global__ __launch_bounds__(256) void kn_hash_insert(Batch B) {
@@ -1190,16 +1209,13 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxPasses = 16;
-// Workgroups of each batched fallback launch (they stride over the device-built
-// map of the columns that need the full sort).
-constexpr uint32_t kFbGrid = 2048;
 // map slots: 0 hist, 1 hist_scan, 2 sort tiles (prefix pass up/down,
 // windows), 3 prefix pass scan, 4 emit, 5..7 merge of the u32 / u64 / str16
 // columns, 8 repack, 9 X_M compaction, 10 merge tile boundaries, 11 hash
 // insert, 12 compaction of the distinct values, 13 row ranks, 14..29
 // fallback pass p up/down (tiles) and 30..45 fallback pass p scan (digits or
 // parts), columns with at least p + 1 digit positions, 46 fallback emit: the
-// per-column counts of every column with a delta, from which kn_fb_plan builds
+// per-column counts of every column with a delta, from which kn_full_sort builds
 // the device maps of the columns that need the full sort (device slot p: pass
 // p, kMaxPasses + p: scan p, 2 kMaxPasses: emit)
 // kMapRepack + 0, 1, 2: the re-encode tiles of the columns whose tile is
@@ -1247,10 +1263,62 @@ __device__ void fb_plan_slot(const Batch &B, const uint32_t *hmaps, uint32_t *dm
     }
     if (threadIdx.x == 255) dst[n] = part[255];
 }
-__global__ __launch_bounds__(256) void kn_fb_plan(Batch B, const uint32_t *hmaps,
-                                                  uint32_t *dmaps, uint32_t npass) {
-    __shared__ uint32_t part[256];
-    fb_plan_slot(B, hmaps, dmaps, npass, blockIdx.x, part);
+
+// The batched fallback in one launch (as k1_full_sort for one column): it
+// returns at once when every column's order check passed, where the launch
+// per phase it replaces cost 3 launches per digit position (48 for 16-byte
+// values) plus the plan and the second emit, about 160 us per batch of
+// launches that returned at once.  Otherwise its workgroups (at most one
+// per two compute units, so all are resident; see k1_full_sort) build the
+// device maps of the unsorted columns, run every pass's phases striding over
+// them, and the second emit, with a grid-wide barrier between phases.  A
+// barrier that overruns its bounded wait marks every unsorted column's
+// error word.
+constexpr size_t kSmemFull = std::max(std::max(kSmemDown, sizeof(mc::EmitSmem<mc::TS16>)),
+                                      (size_t)256 * 4);
+__device__ void fb_spin_error(const Batch &B) {
+    for (uint32_t j = threadIdx.x; j < B.ncols; j += blockDim.x)
+        if (B.cols[j].sflags[mc::kSfUnsorted]) mc::flag_error(B.cols[j].err, MC_DEVERR_SPIN);
+}
+__global__ __launch_bounds__(256) void kn_full_sort(Batch B, const uint32_t *hmaps, uint32_t *dmaps,
+                                                    uint32_t npass, uint32_t *bar) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemFull];
+    __shared__ uint32_t s_first, s_ok;
+    const uint32_t n = B.ncols;
+    if (threadIdx.x == 0) s_first = n;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
+        if (B.cols[j].sflags[mc::kSfUnsorted]) atomicMin(&s_first, j);
+    __syncthreads();
+    if (s_first == n) return;
+    uint32_t *err = B.cols[s_first].err;  // the first unsorted column's
+    const uint32_t G = gridDim.x;
+    uint32_t target = 0;
+    auto barrier = [&]() -> bool {
+        target += G;
+        if (mc::grid_barrier(bar, target, err, &s_ok)) return true;
+        fb_spin_error(B);
+        return false;
+    };
+    for (uint32_t sl = blockIdx.x; sl < 2 * npass + 1; sl += G) {
+        fb_plan_slot(B, hmaps, dmaps, npass, sl, reinterpret_cast<uint32_t *>(smem));
+        __syncthreads();
+    }
+    if (!barrier()) return;
+    auto dmap = [&](uint32_t ds) {
+        Batch D = B;
+        D.map = dmaps + (size_t)ds * (n + 1);
+        return D;
+    };
+    for (uint32_t p = 0; p < npass; p++) {
+        sort_up_units(dmap(p), kPassFull, (int)p, blockIdx.x, G, smem);
+        if (!barrier()) return;
+        sort_scan_units(dmap(kMaxPasses + p), kPassFull, (int)p, blockIdx.x, G, smem);
+        if (!barrier()) return;
+        sort_down_units(dmap(p), kPassFull, (int)p, blockIdx.x, G, smem);
+        if (!barrier()) return;
+    }
+    emit_units(dmap(2 * kMaxPasses), true, blockIdx.x, G, smem);
 }
 
 struct BatchPlan {
@@ -1266,6 +1334,7 @@ struct BatchPlan {
     bool persistent = false;
     mcq::Plan q;
     uint64_t q_off = 0, qbase_off = 0, qpmap_off = 0, qcum_off = 0, qgcum_off = 0;
+    uint64_t fb_bar_off = 0;  // the one-launch fallback's barrier counter (zeroed part)
     uint32_t repack_per = kPersistRepack, merge_per = kPersistMerge, workers = 0;
 };
 
@@ -1357,6 +1426,11 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
     P.repack_per = tune.persist_repack ? tune.persist_repack : kPersistRepack;
     P.merge_per = tune.persist_merge ? tune.persist_merge : kPersistMerge;
     P.workers = tune.persist_workers;
+    if (P.max_passes && !P.persistent) {  // the fallback's barrier counter
+        z = align_up(z, 256);
+        P.fb_bar_off = z;
+        z += 4;
+    }
     if (P.persistent) {  // queue counters after the columns' zeroed parts
         z = align_up(z, 256);
         P.q_off = z;
@@ -1428,7 +1502,7 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
 }
 
 // Enqueue the batched launch sequence (descriptors and maps already on the device).
-int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
+int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, uint32_t cus, hipStream_t s) {
     const mc::ColDesc *d_cols = reinterpret_cast<const mc::ColDesc *>(ws + P.desc_off);
     const uint32_t *d_maps = reinterpret_cast<const uint32_t *>(ws + P.map_off);
     uint32_t *d_dmaps = reinterpret_cast<uint32_t *>(ws + P.dmap_off);
@@ -1436,13 +1510,6 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
         Batch B;
         B.cols = d_cols;
         B.map = d_maps + (size_t)m * (ncols + 1);
-        B.ncols = ncols;
-        return B;
-    };
-    auto dbatch = [&](int ds) {  // a device-built fallback map
-        Batch B;
-        B.cols = d_cols;
-        B.map = d_dmaps + (size_t)ds * (ncols + 1);
         B.ncols = ncols;
         return B;
     };
@@ -1467,31 +1534,20 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
                            batch(kMapHistScan));
         MC_LAUNCHED("kn_hist_scan");
     }
-    // passes of kind `kind`: the prefix passes take one workgroup per tile of
-    // every column with a delta; the fallback passes a fixed grid striding over
-    // the device-built maps (upper bound: the host slot's total)
-    auto passes = [&](int kind, uint32_t n) -> int {
-        for (uint32_t p = 0; p < n; p++) {
-            const bool fb = kind != kPassPrefix;
-            const uint32_t tp = tiles(fb ? kMapFbPass + (int)p : kMapPass);
-            const uint32_t ts = tiles(fb ? kMapFbScan + (int)p : kMapScan);
-            if (!tp) continue;
-            const Batch bp = fb ? dbatch((int)p) : batch(kMapPass);
-            const Batch bs = fb ? dbatch(kMaxPasses + (int)p) : batch(kMapScan);
-            const uint32_t gp = fb ? std::min(tp, kFbGrid) : tp;
-            const uint32_t gs = fb ? std::min(ts, kFbGrid) : ts;
-            hipLaunchKernelGGL(kn_sort_up, dim3(gp), dim3(mc::kBlock), 0, s, bp, kind, (int)p);
+    if (P.max_passes) {
+        // the prefix passes: one workgroup per tile of every column with a delta
+        for (int p = 0; p < mc::kPrefixSlots; p++) {
+            const uint32_t tp = tiles(kMapPass), ts = tiles(kMapScan);
+            hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass),
+                               kPassPrefix, p);
             MC_LAUNCHED("kn_sort_up");
-            hipLaunchKernelGGL(kn_sort_scan, dim3(gs), dim3(mc::kBlock), 0, s, bs, kind, (int)p);
+            hipLaunchKernelGGL(kn_sort_scan, dim3(ts), dim3(mc::kBlock), 0, s, batch(kMapScan),
+                               kPassPrefix, p);
             MC_LAUNCHED("kn_sort_scan");
-            hipLaunchKernelGGL(kn_sort_down, dim3(gp), dim3(mc::kBlock), 0, s, bp, kind, (int)p);
+            hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass),
+                               kPassPrefix, p);
             MC_LAUNCHED("kn_sort_down");
         }
-        return MC_OK;
-    };
-    if (P.max_passes) {
-        rc = passes(kPassPrefix, mc::kPrefixSlots);
-        if (rc) return rc;
         for (int round = 0; round < 2; round++) {
             hipLaunchKernelGGL(kn_window, dim3(tiles(kMapPass)), dim3(mc::kBlock), 0, s,
                                batch(kMapPass), round);
@@ -1503,17 +1559,12 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, hipStream_t s) {
                            batch(kMapEmit), 0);
         MC_LAUNCHED("kn_emit");
         if (P.max_passes) {  // the full sort of the columns found unsorted, and their emit
-            hipLaunchKernelGGL(kn_fb_plan, dim3(2 * P.max_passes + 1), dim3(256), 0, s,
-                               batch(0), d_maps, d_dmaps, P.max_passes);
-            MC_LAUNCHED("kn_fb_plan");
-            rc = passes(kPassFull, P.max_passes);
-            if (rc) return rc;
-            const uint32_t te = tiles(kMapFbEmit);
-            if (te) {
-                hipLaunchKernelGGL(kn_emit, dim3(std::min(te, kFbGrid)), dim3(mc::kBlock), 0, s,
-                                   dbatch(2 * kMaxPasses), 1);
-                MC_LAUNCHED("kn_emit");
-            }
+            const uint32_t grid =
+                std::max(1u, std::min(tiles(kMapFbPass), cus > 1 ? cus / 2 : 1u));
+            hipLaunchKernelGGL(kn_full_sort, dim3(grid), dim3(mc::kBlock), 0, s, batch(0), d_maps,
+                               d_dmaps, P.max_passes,
+                               reinterpret_cast<uint32_t *>(ws + P.fb_bar_off));
+            MC_LAUNCHED("kn_full_sort");
         }
     }
     if (tiles(kMapRank)) {
@@ -2659,7 +2710,7 @@ int batched_run(mc_ctx *ctx, const mc_column_in *ins, const mc_column_out *outs,
 
     auto enqueue = [&](hipStream_t st) {
         return P.persistent ? enqueue_persist(P, ncols, ws, ctx->cus, st)
-                            : enqueue_batch(P, ncols, ws, st);
+                            : enqueue_batch(P, ncols, ws, ctx->cus, st);
     };
     if (!graph) return enqueue(stream);
 
