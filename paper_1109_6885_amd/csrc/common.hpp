@@ -355,15 +355,19 @@ __device__ inline bool grid_barrier(uint32_t *ctr, uint32_t target, uint32_t *er
 // store(x, value).  Every load of a thread is issued before its first
 // store, so the loads are in flight together; a strided load-then-store
 // loop would wait for each load in turn (the compiler keeps the order
-// because the store may alias the next load).
+// because the store may alias the next load).  The loads are not guarded:
+// slots past n load element n - 1 again and store nothing.  (With a guard
+// per load, the compiler moves work of the store, such as a normalization,
+// into the guarded block, and then waits for each load before the next.)
 template <int SLOTS, class LoadF, class StoreF>
 __device__ __forceinline__ void stage_all(uint32_t n, LoadF load, StoreF store) {
+    if (n == 0) return;
     typedef decltype(load(0u)) V;
     V r[SLOTS];
 #pragma unroll
     for (int j = 0; j < SLOTS; j++) {
         const uint32_t x = j * kBlock + threadIdx.x;
-        if (x < n) r[j] = load(x);
+        r[j] = load(x < n ? x : n - 1);
     }
 #pragma unroll
     for (int j = 0; j < SLOTS; j++) {

@@ -218,17 +218,22 @@ __device__ __forceinline__ void merge_tile(const ColDesc &C, char *smem) {
         return;
     }
     // stage a[0] = U_M[i0 - 1] (if any), a[1 + x] = U_M[i0 + x] and
-    // b[y] = U_D[j0 + y] as one range of na + 1 + nb loads
+    // b[y] = U_D[j0 + y]: the predecessor by thread 0, the rest as one range
+    // of na + nb loads, all in flight before any value is normalized (a
+    // normalization or select inside each load's guard makes the compiler
+    // wait for that load before it issues the next)
     typedef typename T::N N;
+    typedef typename T::K K;
     N *const sa = S.ab, *const sb = S.ab + na + 1;
-    constexpr int kStageSlots = (merge_tile<T, ITEMS>() + 1 + kBlock - 1) / kBlock;
-    stage_all<kStageSlots>(
-        na + 1 + nb,
-        [&](uint32_t q) -> N {
-            if (q <= na) return (q > 0 || i0 > 0) ? gA(i0 + q - 1) : N{};
-            return gB(j0 + (q - na - 1));
-        },
-        [&](uint32_t q, const N &v) { S.ab[q] = v; });
+    // every thread loads the predecessor's address (one request per wave),
+    // unguarded so that nothing waits for it here; without a predecessor it
+    // reads some valid entry and stores zero
+    const K pred = T::load((i0 > 0 || a > 0) ? C.u_m : C.u_d, i0 > 0 ? i0 - 1 : 0);
+    stage_all<merge_tile<T, ITEMS>() / kBlock>(
+        na + nb,
+        [&](uint32_t q) -> K { return q < na ? T::load(C.u_m, i0 + q) : T::load(C.u_d, j0 + (q - na)); },
+        [&](uint32_t q, const K &v) { S.ab[q + 1] = T::norm(v); });
+    if (threadIdx.x == 0) S.ab[0] = i0 > 0 ? T::norm(pred) : N{};
     __syncthreads();
 
     // this thread's slice of the tile's merged range

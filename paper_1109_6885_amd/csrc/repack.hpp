@@ -191,17 +191,21 @@ __device__ __forceinline__ void xcompact_tile(const ColDesc &C, uint64_t t, char
 
 // Stage the packed main words of the tile starting at row c0 into LDS with
 // 128-bit loads (streamed once: non-temporal, so the tables keep the cache).
+// A thread's loads (up to CODES / 1024 pairs, at w = 32) are all issued
+// before the first LDS store: a strided load-then-store loop waits for each.
 template <int CODES = kRepackCodes>
 __device__ __forceinline__ void stage_main_words(const ColDesc &C, uint64_t c0, uint64_t *s_in) {
     if (c0 >= C.n_main) return;
     const uint32_t w = C.w;
     const uint64_t win = (C.n_main * w + 63) / 64;  // readable input words
-    const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 32
+    const uint64_t wbase = (c0 / 64) * w;           // even: c0/64 is a multiple of 16
     const uint32_t nw = (uint32_t)min<uint64_t>(CODES / 64 * (uint64_t)w, win - wbase);
-    const uint32_t npair = nw / 2;
+    const uint32_t npair = nw / 2;  // <= CODES / 4 (w <= 32)
     const u64x2 *src2 = reinterpret_cast<const u64x2 *>(C.main_codes + wbase);
     u64x2 *dst2 = reinterpret_cast<u64x2 *>(s_in);
-    for (uint32_t x = threadIdx.x; x < npair; x += kBlock) dst2[x] = __builtin_nontemporal_load(src2 + x);
+    stage_all<CODES / 1024>(
+        npair, [&](uint32_t x) { return __builtin_nontemporal_load(src2 + x); },
+        [&](uint32_t x, const u64x2 &v) { dst2[x] = v; });
     if ((nw & 1u) && threadIdx.x == 0)
         s_in[nw - 1] = __builtin_nontemporal_load(C.main_codes + wbase + nw - 1);
 }

@@ -233,6 +233,60 @@ __device__ __forceinline__ void hist_scan_col(const ColDesc &C, char *smem) {
     }
 }
 
+// ---- loads of a tile's keys ---------------------------------------------
+// Every load of a thread is issued before any loaded value is used: a digit
+// or a select computed inside the guard of each load makes the compiler wait
+// for that load before it issues the next, one memory round trip per item.
+
+template <class K>
+struct KeyVal {
+    K k;
+    uint32_t v;
+};
+
+// Keys (and their payloads) at tile positions base + 64 j, j < ITEMS, of the
+// tile starting at b0 with tn values; entries past tn are zero.
+template <class T, int ITEMS>
+__device__ __forceinline__ void load_keys(const PassIO &io, uint64_t b0, uint32_t tn, uint32_t base,
+                                          typename T::K (&key)[ITEMS], uint32_t (&val)[ITEMS]) {
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t li = base + j * 64;
+        key[j] = typename T::K{};
+        if (li < tn) key[j] = T::load(io.src, b0 + li);
+    }
+    if (io.vsrc) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            const uint32_t li = base + j * 64;
+            val[j] = 0;
+            if (li < tn) val[j] = io.vsrc[b0 + li];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) val[j] = (uint32_t)(b0 + base + j * 64);
+    }
+}
+
+// Count the digits p of the tile's values (positions b0 + j * kBlock +
+// thread, below n) into the 256 LDS counters h.
+template <class T>
+__device__ __forceinline__ void count_digits(const PassIO &io, uint64_t b0, uint64_t n, int p, uint32_t *h) {
+    constexpr int ITEMS = SortCfg<T>::kItems;
+    typename T::K key[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
+        key[j] = typename T::K{};
+        if (i < n) key[j] = T::load(io.src, i);
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[T::digit(key[j], p)], 1u);
+    }
+}
+
 // ---- one pass: per-tile counts -------------------------------------------
 
 template <class T>
@@ -245,19 +299,8 @@ __device__ __forceinline__ void sort_up_tile(const ColDesc &C, const PassIO &io,
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t b0 = (uint64_t)t * TILE;
-    const void *src = io.src;
     const uint64_t n = sort_n(C);
-    uint32_t dg[SortCfg<T>::kItems];
-#pragma unroll
-    for (int j = 0; j < SortCfg<T>::kItems; j++) {  // every load first
-        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
-        dg[j] = i < n ? T::digit(T::load(src, i), p) : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < SortCfg<T>::kItems; j++) {
-        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[dg[j]], 1u);
-    }
+    count_digits<T>(io, b0, n, p, h);
     __syncthreads();
     C.tcount[(uint64_t)threadIdx.x * C.sort_tiles + t] = h[threadIdx.x];
 }
@@ -408,26 +451,27 @@ __device__ __forceinline__ void sort_down_tile(const ColDesc &C, const PassIO &i
 
     if (p < 0) {
         // every value has the same digit here: the stable order is unchanged
-        for (uint32_t i = threadIdx.x; i < tn; i += kBlock) {
-            T::store(io.kdst, b0 + i, T::load(io.src, b0 + i));
-            io.vdst[b0 + i] = io.vsrc ? io.vsrc[b0 + i] : (uint32_t)(b0 + i);
-        }
+        // (every load of the thread first, then the stores)
+        stage_all<ITEMS>(
+            tn,
+            [&](uint32_t i) {
+                return KeyVal<K>{T::load(io.src, b0 + i),
+                                 io.vsrc ? io.vsrc[b0 + i] : (uint32_t)(b0 + i)};
+            },
+            [&](uint32_t i, const KeyVal<K> &e) {
+                T::store(io.kdst, b0 + i, e.k);
+                io.vdst[b0 + i] = e.v;
+            });
         return;
     }
 
     const int lane = lane_id(), wv = wave_id();
     K key[ITEMS];
     uint32_t val[ITEMS], dig[ITEMS], slot[ITEMS];
+    load_keys<T, ITEMS>(io, b0, tn, wv * WCHUNK + lane, key, val);
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        const uint32_t li = wv * WCHUNK + j * 64 + lane;  // index inside the tile
-        dig[j] = 0;
-        if (li < tn) {
-            key[j] = T::load(io.src, b0 + li);
-            val[j] = io.vsrc ? io.vsrc[b0 + li] : (uint32_t)(b0 + li);
-            dig[j] = T::digit(key[j], p);
-        }
-    }
+    for (int j = 0; j < ITEMS; j++)
+        dig[j] = wv * WCHUNK + j * 64 + lane < tn ? T::digit(key[j], p) : 0u;
     S.gpos[threadIdx.x] = C.tcount[(uint64_t)threadIdx.x * C.sort_tiles + t];
     rank_digits<ITEMS>(dig, tn, S.wcnt, S.dex, S.tmp, slot);
 
@@ -485,17 +529,7 @@ __device__ __forceinline__ void sort_up2_tile(const ColDesc &C, const PassIO &io
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t b0 = (uint64_t)t * TILE;
-    uint32_t dg[SortCfg<T>::kItems];
-#pragma unroll
-    for (int j = 0; j < SortCfg<T>::kItems; j++) {
-        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
-        dg[j] = i < n ? T::digit(T::load(io.src, i), p) : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < SortCfg<T>::kItems; j++) {
-        const uint64_t i = b0 + (uint64_t)j * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[dg[j]], 1u);
-    }
+    count_digits<T>(io, b0, n, p, h);
     __syncthreads();
     const uint32_t c = h[threadIdx.x];
     C.tcount[(uint64_t)t * 256 + threadIdx.x] = c;
@@ -522,16 +556,10 @@ __device__ __forceinline__ void sort_down2_tile(const ColDesc &C, const PassIO &
     const int lane = lane_id(), wv = wave_id();
     K key[ITEMS];
     uint32_t val[ITEMS], dig[ITEMS], slotv[ITEMS];
+    load_keys<T, ITEMS>(io, b0, tn, wv * WCHUNK + lane, key, val);
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        const uint32_t li = wv * WCHUNK + j * 64 + lane;
-        dig[j] = 0;
-        if (li < tn) {
-            key[j] = T::load(io.src, b0 + li);
-            val[j] = io.vsrc ? io.vsrc[b0 + li] : (uint32_t)(b0 + li);
-            dig[j] = T::digit(key[j], p);
-        }
-    }
+    for (int j = 0; j < ITEMS; j++)
+        dig[j] = wv * WCHUNK + j * 64 + lane < tn ? T::digit(key[j], p) : 0u;
     {
         // digit d's first position: its global offset, the groups before
         // this tile's group, the group's tiles before this one
@@ -836,11 +864,14 @@ __device__ __forceinline__ void emit_tile_at(const ColDesc &C, char *smem, bool 
     constexpr int kStageSlots = (kEmitTile + 1 + kBlock - 1) / kBlock;
     stage_all<kStageSlots>(
         kEmitTile + 1,
-        [&](uint32_t x) {
+        [&](uint32_t x) {  // clamped: the load never waits for a select
             const uint64_t i = tb + x;
-            return (i >= 1 && i - 1 < C.nd) ? T::load(keys, i - 1) : K{};
+            return T::load(keys, i >= 1 ? min<uint64_t>(i - 1, C.nd - 1) : 0);
         },
-        [&](uint32_t x, const K &k) { S.keys[x] = k; });
+        [&](uint32_t x, const K &k) {
+            const uint64_t i = tb + x;
+            S.keys[x] = (i >= 1 && i - 1 < C.nd) ? k : K{};
+        });
     __syncthreads();
     const uint64_t i0 = tb + (uint64_t)threadIdx.x * kEmitItems;
     const uint32_t l0 = threadIdx.x * kEmitItems;
@@ -948,15 +979,11 @@ __device__ __forceinline__ uint64_t window_view(const ColDesc &C, uint64_t n, ui
     const uint64_t lo = vb > (uint64_t)kWinPad ? vb - kWinPad : 0;
     const uint32_t m = (uint32_t)(min<uint64_t>(n, ve + kWinPad) - lo);
     const uint32_t v0 = (uint32_t)(vb - lo), v1 = (uint32_t)(ve - lo);  // the view, staged indices
-    struct KV {
-        N k;
-        uint32_t v;
-    };
     constexpr int kSlots = (kEmitWin + kBlock - 1) / kBlock;
     stage_all<kSlots>(
-        m, [&](uint32_t x) { return KV{T::norm(T::load(C.keys1, lo + x)), C.vals1[lo + x]}; },
-        [&](uint32_t x, const KV &e) {
-            S.keys[x] = e.k;
+        m, [&](uint32_t x) { return KeyVal<typename T::K>{T::load(C.keys1, lo + x), C.vals1[lo + x]}; },
+        [&](uint32_t x, const KeyVal<typename T::K> &e) {
+            S.keys[x] = T::norm(e.k);  // normalized once every load is in flight
             S.vals[x] = e.v;
         });
     int pp[kPrefixSlots];
