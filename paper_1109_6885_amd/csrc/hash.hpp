@@ -221,11 +221,19 @@ __device__ __forceinline__ void compact_tile(const ColDesc &C, uint64_t t, char 
     CompactSmem &S = *reinterpret_cast<CompactSmem *>(smem);
     if (C.hcnt) group_prefix(C.hcnt, C.hgsum, (uint32_t)t, kEmitGroup, &S.pre);
     const uint64_t r0 = C.hrow0 + t * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+    // every load first (clamped, unguarded), then the comparisons: a
+    // comparison inside each load's guard waits for that load
+    uint32_t rv[kCompactItems];
+#pragma unroll
+    for (int j = 0; j < kCompactItems; j++) {
+        const uint64_t row = r0 + j;
+        rv[j] = C.rep[row < C.nd ? row : (uint64_t)C.nd - 1];
+    }
     uint32_t flags = 0;
 #pragma unroll
     for (int j = 0; j < kCompactItems; j++) {
         const uint64_t row = r0 + j;
-        if (row < C.nd && C.rep[row] == (uint32_t)row) flags |= 1u << j;
+        if (row < C.nd && rv[j] == (uint32_t)row) flags |= 1u << j;
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan((uint32_t)__popc(flags), S.tmp, &tot);  // also publishes S.pre

@@ -138,15 +138,16 @@ __device__ __forceinline__ void hist_tile(const ColDesc &C, uint32_t blk, char *
     __syncthreads();
     const uint64_t b0 = (uint64_t)blk * kHistChunk;
     const uint64_t n = sort_n(C);
+    if (b0 >= n) return;  // past the values (hashing left fewer than the rows)
     // eight loads in flight per thread, then their counts
     constexpr int kBatch = 8;
     static_assert(kHistChunk % (kBatch * kBlock) == 0, "whole batches");
     for (int h = 0; h < kHistChunk / kBlock; h += kBatch) {
         typename T::K k[kBatch];
 #pragma unroll
-        for (int q = 0; q < kBatch; q++) {
+        for (int q = 0; q < kBatch; q++) {  // unguarded (clamped): no load waits for another
             const uint64_t i = b0 + (uint64_t)(h + q) * kBlock + threadIdx.x;
-            if (i < n) k[q] = T::load(C.sort_src, i);
+            k[q] = T::load(C.sort_src, i < n ? i : n - 1);
         }
 #pragma unroll
         for (int q = 0; q < kBatch; q++) {
