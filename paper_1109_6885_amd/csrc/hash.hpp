@@ -65,6 +65,15 @@ struct HashSmem {
 };
 static_assert(kHashTile <= 65536, "tile-local indices are 16-bit");
 
+// A slot of the global table changes once, from 0 to its representative's
+// row + 1, by an atomic compare-and-swap; a non-zero slot never changes
+// again within a merge.  So a slot is read with a plain load, which may hit
+// a cache: a non-zero value read anywhere is final, and a zero (perhaps
+// stale) only leads to the compare-and-swap, whose returned value is
+// authoritative.  (Reading every slot with a device-scope atomic load made
+// the probes of a skewed delta's frequent values, which every tile repeats,
+// queue on the same few words at the device's coherence point.)
+
 // Find or claim the slot of `key` in the global table, probing from slot h
 // on (`done` slots of its probe sequence already seen); returns the
 // representative row, or `row` itself if it claimed the slot.
@@ -72,7 +81,7 @@ template <class T>
 __device__ __forceinline__ uint32_t global_rep(const ColDesc &C, typename T::K key, uint32_t row,
                                                uint64_t h, uint64_t done, bool *ok) {
     for (uint64_t probe = done; probe <= C.hmask; probe++) {
-        uint32_t s = __hip_atomic_load(&C.htab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t s = C.htab[h];
         if (s == 0) {
             s = atomicCAS(&C.htab[h], 0u, row + 1u);
             if (s == 0) return row;  // claimed: this row represents its value
@@ -141,8 +150,7 @@ __device__ __forceinline__ void hash_insert_tile(const ColDesc &C, uint64_t t, c
     }
 #pragma unroll
     for (int j = 0; j < kHashItems; j++)
-        if ((live >> j) & 1u)
-            sv[j] = __hip_atomic_load(&C.htab[hh[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((live >> j) & 1u) sv[j] = C.htab[hh[j]];  // plain: see the note above global_rep
 #pragma unroll
     for (int j = 0; j < kHashItems; j++)
         if (((live >> j) & 1u) && sv[j] == 0)
