@@ -800,7 +800,11 @@ __device__ __forceinline__ void window_seam_tile(const ColDesc &C, uint32_t t, c
 
 // ---- run heads -> U_D and the delta rows' indices ---------------------------
 
-constexpr int kEmitItems = 8;
+// Sorted positions per thread of an emit tile: 1024 per tile, with the
+// windows' 2 x 257 staged neighbours (2048 per tile measured slower: c2
+// 0.581 -> 0.575 ms and c3 1.094 -> 1.072 ms at 1024, whose smaller LDS
+// keeps more workgroups per CU for the latency-bound run ranking).
+constexpr int kEmitItems = 4;
 constexpr int kEmitTile = kBlock * kEmitItems;
 
 template <class T>
