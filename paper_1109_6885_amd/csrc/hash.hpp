@@ -51,7 +51,10 @@ __device__ __forceinline__ uint64_t hash_key(uint32_t k) { return mix64(k); }
 __device__ __forceinline__ uint64_t hash_key(uint64_t k) { return mix64(k); }
 __device__ __forceinline__ uint64_t hash_key(Raw16 k) { return mix64(k.a ^ mix64(k.b)); }
 
-constexpr int kHashItems = 8;
+// Delta rows per hashing tile: 1024 (at 2048 the tile's LDS held 3
+// workgroups per CU instead of 6, and its global probes, a few random
+// round trips each, had less company to hide them: c3 1.072 -> 1.054 ms).
+constexpr int kHashItems = 4;
 constexpr int kHashTile = kBlock * kHashItems;
 constexpr int kLocalSlots = 2 * kHashTile;  // LDS table of the tile's first occurrences
 
@@ -214,8 +217,11 @@ struct CompactSmem {
     uint64_t pre;   // representatives of the tiles before it (per-tile counts)
 };
 
-constexpr int kCompactItems = 8;
+// The compaction's tile t covers the rows of hashing tile t, whose count of
+// representatives (hcnt[t]) gives it its place in the list.
+constexpr int kCompactItems = kHashItems;
 constexpr int kCompactTile = kBlock * kCompactItems;
+static_assert(kCompactTile == kHashTile, "compaction tile t takes hashing tile t's count");
 
 // With per-tile counts (C.hcnt, a merge's own hashing) the tile's range
 // starts after the representatives of the tiles before it, so the list is
