@@ -1226,7 +1226,7 @@ int merge_column_impl(mc_ctx *ctx, const mc_column_in *in, const mc_column_out *
 
 constexpr int kMaxPasses = 16;
 // map slots: 0 hist, 1 hist_scan, 2 sort tiles (prefix pass up/down,
-// windows), 3 prefix pass scan, 4 emit, 5..7 merge of the u32 / u64 / str16
+// the persistent launch's windows), 3 prefix pass scan, 4 emit, 5..7 merge of the u32 / u64 / str16
 // columns, 8 repack, 9 X_M compaction, 10 merge tile boundaries, 11 hash
 // insert, 12 compaction of the distinct values, 13 row ranks, 14..29
 // fallback pass p up/down (tiles) and 30..45 fallback pass p scan (digits or

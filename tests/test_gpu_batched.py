@@ -155,9 +155,47 @@ def few_prefix_values(rng, vtype, n):
     return v
 
 
+def test_batched_full_sort_concurrent_streams():
+    """Three batches enqueued on three streams at once, each with two columns
+    that need the full sort between ordinary ones: every batch's one-launch
+    full sort has at most one workgroup per two CUs and a grid-wide barrier
+    that assumes they are all resident, and three of them fit together (a CU
+    holds three of those workgroups).  Every column against the oracle."""
+    rng = np.random.default_rng(23)
+    batches = []
+    for b in range(3):
+        cols = []
+        for vt in ("u64", "str16"):
+            base = gen.random_column(rng, vt, 2000, 20_000, 0)
+            d = np.concatenate([few_prefix_values(rng, vt, 200_000),
+                                base.u_m[rng.integers(0, 2000, 40)]])
+            cols.append(gen.Column(vt, base.u_m, base.main_packed, base.n_main, base.w,
+                                   d[rng.permutation(d.shape[0])]))
+        cols.append(gen.random_column(rng, "u32", 3000, 25_000, 6_000, 0.5))
+        batches.append(cols)
+    say("case batched full sort, three batches on three streams at once")
+    streams = [torch.cuda.Stream() for _ in batches]
+    ctxs = []
+    for _ in batches:
+        ctx = cm.Context(torch.cuda.current_device())
+        ctx.set_tuning(hash_dict_ratio=0xFFFFFFFF)  # the radix route and its full sort
+        ctxs.append(ctx)
+    dcols = [[cm.ColumnInput.from_numpy(c) for c in cols] for cols in batches]
+    outs = [[cm.alloc_output(d) for d in dc] for dc in dcols]
+    scratch = [cm.alloc_scratch(cm.batched_bounds_of([d.descriptor() for d in dc], x))
+               for dc, x in zip(dcols, ctxs)]
+    torch.cuda.synchronize()
+    for dc, o, sc, st, x in zip(dcols, outs, scratch, streams, ctxs):
+        cm.merge_columns_batched(dc, outs=o, scratch=sc, stream=st, ctx=x)
+    torch.cuda.synchronize()
+    for cols, os_ in zip(batches, outs):
+        for c, o in zip(cols, os_):
+            check_col(c, o.fetch())
+
+
 def test_batched_full_sort_many_columns():
     """Ten columns that all need the full sort, 600,000 delta rows each,
-    between ordinary columns: the full sort's launches have fewer workgroups
+    between ordinary columns: the full sort's launch has fewer workgroups
     than those columns' tiles, digits and emit tiles, so each workgroup takes
     several, across column boundaries.  Through a graph, twice."""
     rng = np.random.default_rng(17)
