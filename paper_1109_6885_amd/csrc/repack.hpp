@@ -132,19 +132,50 @@ __device__ __forceinline__ void xcompact_tile(const ColDesc &C, uint64_t t, char
     const uint64_t c0 = t * kXCompactTile;
     if (c0 >= C.n_um) return;
     const uint32_t tn = (uint32_t)min<uint64_t>(kXCompactTile, C.n_um - c0);
-    stage_all<kXCompactTile / kBlock>(
-        tn, [&](uint32_t j) { return C.x_m[c0 + j]; }, [&](uint32_t j, uint32_t v) { s_x[xs_at(j)] = v; });
+    // staging: 16-byte loads of four entries where X_M is so aligned (the
+    // library's own tables always are; a caller's may not be), the rest one
+    // entry at a time
+    const uint32_t n4 = reinterpret_cast<uintptr_t>(C.x_m + c0) % 16 == 0 ? tn / 4 : 0u;
+    const uint4 *x4 = reinterpret_cast<const uint4 *>(C.x_m + c0);
+    stage_all<kXCompactTile / 4 / kBlock>(
+        n4, [&](uint32_t q) { return x4[q]; },
+        [&](uint32_t q, const uint4 &v) {
+            s_x[xs_at(4 * q)] = v.x;  // four entries of one 128-entry block
+            s_x[xs_at(4 * q + 1)] = v.y;
+            s_x[xs_at(4 * q + 2)] = v.z;
+            s_x[xs_at(4 * q + 3)] = v.w;
+        });
+    for (uint32_t j = 4 * n4 + threadIdx.x; j < tn; j += kBlock) s_x[xs_at(j)] = C.x_m[c0 + j];
     __syncthreads();
     const uint64_t A = xm_line_slope(C);
     bool bad = false;
-    for (uint32_t j = threadIdx.x; j < tn; j += kBlock) {
-        const uint64_t c = c0 + j;
-        const int64_t dev = (int64_t)s_x[xs_at(j)] - (int64_t)c - (int64_t)xm_line(c, A);
-        if (dev < -32768 || dev > 32767) {
-            bad = true;
-            C.xdev[c] = 0;
+    // eight consecutive deviations per thread and round, written as one
+    // 16-byte store (the table is the library's, 256-byte aligned, and
+    // c0 + j0 is a multiple of 8); a partial group one entry at a time
+    for (uint32_t j0 = 8 * threadIdx.x; j0 < tn; j0 += 8 * kBlock) {
+        const uint32_t m = min<uint32_t>(8u, tn - j0);
+        int16_t d[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint64_t c = c0 + j0 + i;
+            const int64_t dev = (uint32_t)i < m ? (int64_t)s_x[xs_at(j0 + i)] - (int64_t)c -
+                                                      (int64_t)xm_line(c, A)
+                                                : 0;
+            const bool ok = dev >= -32768 && dev <= 32767;
+            bad |= !ok;
+            d[i] = ok ? (int16_t)dev : (int16_t)0;
+        }
+        if (m == 8u) {
+            uint4 v;
+            v.x = (uint32_t)(uint16_t)d[0] | ((uint32_t)(uint16_t)d[1] << 16);
+            v.y = (uint32_t)(uint16_t)d[2] | ((uint32_t)(uint16_t)d[3] << 16);
+            v.z = (uint32_t)(uint16_t)d[4] | ((uint32_t)(uint16_t)d[5] << 16);
+            v.w = (uint32_t)(uint16_t)d[6] | ((uint32_t)(uint16_t)d[7] << 16);
+            *reinterpret_cast<uint4 *>(C.xdev + c0 + j0) = v;
         } else {
-            C.xdev[c] = (int16_t)dev;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                if ((uint32_t)i < m) C.xdev[c0 + j0 + i] = d[i];
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(C.xflag, 1u);
