@@ -790,10 +790,6 @@ __global__ __launch_bounds__(256) void kn_sort_down(Batch B, int kind, int p) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemDown];
     sort_down_units(B, kind, p, blockIdx.x, gridDim.x, smem);
 }
-__global__ __launch_bounds__(256) void kn_emit(Batch B, int again) {
-    __shared__ __attribute__((aligned(16))) char smem[sizeof(mc::EmitSmem<mc::TS16>)];
-    emit_units(B, again != 0, blockIdx.x, gridDim.x, smem);
-}
 // The first emit in two launches, as for a single column: the windows
 // folded into the emit (order each tile's view inside its runs of equal
 // prefix in LDS, count the run heads; the hashing route's distinct values
