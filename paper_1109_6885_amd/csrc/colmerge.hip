@@ -239,10 +239,12 @@ ColLayout col_layout(int32_t type, uint64_t n_um, uint64_t nd, uint64_t n_main,
     L.xflag = z.take(8);
     L.gh = z.take((uint64_t)mc::kGhCopies * L.passes * 256 * 4);
     L.trivial = z.take(16 * 4);
-    // single-column calls: the emit in two launches, and so the prefix passes
-    // when there are at most kP2MaxTiles sort tiles
+    // the prefix passes in two launches each (counts with group sums, then
+    // rank and scatter) for columns of at most kP2MaxTiles sort tiles; not
+    // in the persistent batched launch, whose items run the three phases
     L.single = !batched;
-    L.two_launch_pass = L.single && nd > 0 && L.sort_tiles <= mc::kP2MaxTiles;
+    L.two_launch_pass = nd > 0 && L.sort_tiles <= mc::kP2MaxTiles &&
+                        !(batched && tune.batched_launch == MC_BATCHED_PERSISTENT);
     if (L.two_launch_pass)
         L.pgsum = z.take((uint64_t)mc::kPrefixSlots * ceil_div(L.sort_tiles, mc::kP2Group) * 256 * 4);
     L.egsum = z.take(ceil_div(L.emit_tiles, mc::kEmitGroup) * 4);
@@ -729,7 +731,11 @@ __device__ __forceinline__ void sort_up_units(const Batch &B, int kind, int p, u
         const mc::ColDesc &C = B.cols[j];
         mc::PassIO io;
         if (!pass_io(C, kind, p, &io)) continue;
-        MC_DISPATCH(C, mc::sort_up_tile, C, io, b - B.map[j], smem);
+        if (kind == kPassPrefix && C.pgsum) {  // counts with group sums (slot p)
+            MC_DISPATCH(C, mc::sort_up2_tile, C, io, p, b - B.map[j], smem);
+        } else {
+            MC_DISPATCH(C, mc::sort_up_tile, C, io, b - B.map[j], smem);
+        }
     }
 }
 __device__ __forceinline__ void sort_scan_units(const Batch &B, int kind, int p, uint32_t first,
@@ -739,6 +745,7 @@ __device__ __forceinline__ void sort_scan_units(const Batch &B, int kind, int p,
         if (b != first) __syncthreads();
         const uint32_t j = find_col(B, b);
         const mc::ColDesc &C = B.cols[j];
+        if (kind == kPassPrefix && C.pgsum) continue;  // the scatter sums the counts itself
         mc::PassIO io;
         if (!pass_io(C, kind, p, &io)) continue;
         if (C.sort_tiles <= mc::kSmallScanTiles) {  // 64 digits per workgroup
@@ -757,7 +764,11 @@ __device__ __forceinline__ void sort_down_units(const Batch &B, int kind, int p,
         const mc::ColDesc &C = B.cols[j];
         mc::PassIO io;
         if (!pass_io(C, kind, p, &io)) continue;
-        MC_DISPATCH(C, mc::sort_down_tile, C, io, b - B.map[j], smem);
+        if (kind == kPassPrefix && C.pgsum) {
+            MC_DISPATCH(C, mc::sort_down2_tile, C, io, p, b - B.map[j], smem);
+        } else {
+            MC_DISPATCH(C, mc::sort_down_tile, C, io, b - B.map[j], smem);
+        }
     }
 }
 // emit_tile takes its tile from a per-column ticket (a workgroup holds one
@@ -1474,9 +1485,10 @@ int plan_batch(const mc_column_in *ins, uint32_t ncols, BatchPlan &P,
             if (m == kMapHist) n = L.hist_tiles;
             else if (m == kMapHistScan) n = has_delta ? 1 : 0;
             else if (m == kMapPass) n = has_delta ? L.sort_tiles : 0;
-            else if (m == kMapScan)
-                n = has_delta ? (L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts : 256)
-                              : 0;
+            else if (m == kMapScan)  // the prefix passes of three launches only
+                n = has_delta && !L.two_launch_pass
+                        ? (L.sort_tiles <= mc::kSmallScanTiles ? mc::kSmallScanParts : 256)
+                        : 0;
             else if (m >= kMapFbPass && m < kMapFbPass + kMaxPasses)
                 n = (has_delta && (uint32_t)(m - kMapFbPass) < L.passes)
                         ? L.sort_tiles
@@ -1547,15 +1559,18 @@ int enqueue_batch(const BatchPlan &P, uint32_t ncols, char *ws, uint32_t cus, hi
         MC_LAUNCHED("kn_hist_scan");
     }
     if (P.max_passes) {
-        // the prefix passes: one workgroup per tile of every column with a delta
+        // the prefix passes: one workgroup per tile of every column with a
+        // delta; the scan launch only for columns whose passes take three
         for (int p = 0; p < mc::kPrefixSlots; p++) {
             const uint32_t tp = tiles(kMapPass), ts = tiles(kMapScan);
             hipLaunchKernelGGL(kn_sort_up, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass),
                                kPassPrefix, p);
             MC_LAUNCHED("kn_sort_up");
-            hipLaunchKernelGGL(kn_sort_scan, dim3(ts), dim3(mc::kBlock), 0, s, batch(kMapScan),
-                               kPassPrefix, p);
-            MC_LAUNCHED("kn_sort_scan");
+            if (ts) {
+                hipLaunchKernelGGL(kn_sort_scan, dim3(ts), dim3(mc::kBlock), 0, s,
+                                   batch(kMapScan), kPassPrefix, p);
+                MC_LAUNCHED("kn_sort_scan");
+            }
             hipLaunchKernelGGL(kn_sort_down, dim3(tp), dim3(mc::kBlock), 0, s, batch(kMapPass),
                                kPassPrefix, p);
             MC_LAUNCHED("kn_sort_down");
