@@ -52,8 +52,9 @@ def test_batched_direct():
 
 
 def test_batched_partitioned_merge():
-    """Columns whose dictionaries merge over 2^20 positions find the merge
-    tile boundaries in a launch of their own; mixed with small columns."""
+    """Columns whose dictionaries merge over 2^20 positions (at least 128
+    tiles) find the merge tile boundaries in a launch of their own; mixed
+    with small columns."""
     rng = np.random.default_rng(6)
     cols = [gen.random_column(rng, "u64", 1_040_000, 60_000, 20_000, 0.5),
             gen.random_column(rng, "u32", 300, 2000, 100, 0.5),

@@ -456,8 +456,8 @@ def test_skewed_new_values(where):
                                                     ("u32", 1_048_575, 1, 0.0),
                                                     ("u32", 3, 1_100_000, 1.0)])
 def test_partitioned_merge(vtype, n_um, nd, frac_new):
-    """Merges of over 2^20 positions take their tile boundaries from a
-    launch of their own; the result must not change."""
+    """Merges of at least 128 tiles (here over 2^20 positions) take their
+    tile boundaries from a launch of their own; the result must not change."""
     rng = np.random.default_rng(77)
     col = gen.random_column(rng, vtype, n_um, 50_000, nd, frac_new)
     say(f"case partitioned merge {vtype} n_um={n_um} nd={nd}")
